@@ -1,0 +1,214 @@
+"""Benchmark of the dual-time EDAC SPH hot path on one MI355X.
+
+A step is one real time step of Algorithm 2 (cell build, wall pass, rate pass
+and predictor, cell rebuild, pseudo-time loop until the stop test, corrector)
+over the whole workload. Default workload: 2D Taylor-Green vortex, 400 x 400
+particles, FP32 pair sums with float64 positions, pressure accumulation and
+residuals. The metric is neighbour-pair evaluations of the pseudo-time
+iterations per second (pairs of the exact neighbour lists times iterations run,
+per sim), inputs resident in HBM before the timed region.
+
+Also reported: the same workload on the plain FP64 path, the 64-instance
+batched workload in instance-steps/s, the roofline of the pseudo-iteration pair
+pass (HIP events on the library's stream around each launch in the timed
+region) and the CPU oracle timed on a bounded sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point work of one neighbour pair in the pass kernel
+# (FMA = 2): 50 in 2D, 60 in 3D (count in the pass kernel's formula).
+FLOP_PER_PAIR = {2: 50, 3: 60}
+# FP32 vector peak without packed instructions: 256 CU x 4 SIMD x 16 lanes x
+# 2.4 GHz x 2 (FMA) = 78.6 TFLOP/s; FP64 vector: 78.6 TFLOP/s.
+PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+PEAK_PACKED_F32 = 157.3
+
+WORKLOADS = {
+    "C0": "2D Taylor-Green vortex, periodic unit square, 50x50 particles, Re=100",
+    "C1": "2D Taylor-Green vortex, periodic unit square, 400x400 particles, Re=100",
+    "C2": "3D Taylor-Green vortex, periodic unit cube, 64^3 particles, Re=1600",
+    "C3": "2D dam break, 1x2 column in a 4x4 tank, dx=0.002, 3 wall layers",
+    "C4": "batch of 64 periodic TGV / lid-driven cavity instances, 2.5k-160k particles",
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pair_evals(reports):
+    return sum(r["pairs"] * r["iters"] for step in reports for r in step)
+
+
+def run_leg(problems, precision, steps, warmup, timing):
+    import torch
+    from paper_1904_00861_amd import dtsph as D
+
+    sim = D.Sim(problems, precision=precision)
+    if warmup:
+        sim.step(warmup)
+    sim.set_option(D.OPT_TIMING, 1 if timing else 0)
+    sim.set_option(D.OPT_RESET_TIMING, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, reps = sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = sim.timing()
+    info = dict(sim.info)
+    sim.close()
+    return dict(seconds=t1 - t0, reports=reps, timing=tm, status=st, info=info)
+
+
+def traffic_from_profile(kernel_src):
+    """HBM bytes per pair-pass launch from the committed counter summary, or None
+    if the summary is missing or the pass kernel changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "k_pass_C1_fp32_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"source sha256: ([0-9a-f]{64})", txt)
+    m_bytes = re.search(r"HBM bytes per launch: ([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes:
+        return None
+    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    return float(m_bytes.group(1)) if digest == m_hash.group(1) else None
+
+
+def cpu_baseline(prob, budget_s=12.0, max_steps=40):
+    import oracle as O
+
+    x, v, vp, p = prob.x, prob.v, prob.v_prev, prob.p
+    t0 = time.perf_counter()
+    evals, steps = 0, 0
+    while steps < max_steps and time.perf_counter() - t0 < budget_s:
+        x, v, vp, p, reps, st = O.step(prob.params, prob.n_fluid, prob.n_wall, x, v, vp, p, 1)
+        evals += sum(r["pairs"] * r["iters"] for r in reps)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return dict(value=evals / dt, unit="pair-evals/s", cores=O.num_threads(), kind="oracle",
+                sample=f"{steps} real steps of the same workload from its initial state "
+                       f"({dt:.1f} s, FP64 C oracle, OpenMP)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C1", choices=["C0", "C1", "C2", "C3", "C4"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batched legs")
+    ap.add_argument("--no-timing", action="store_true", help="no HIP events in the timed region")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the batched workload shards whole simulations across GPUs without "
+              "communication, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1904_00861_amd import dtsph as D
+    from paper_1904_00861_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    D.lib()
+    prec = D.FP32 if args.precision == "fp32" else D.FP64
+    dtype = "f32" if args.precision == "fp32" else "f64"
+    prob = I.config(args.config)
+    problems = prob if isinstance(prob, list) else [prob]
+    dim = problems[0].params["dim"]
+    n_particles = sum(p.n for p in problems)
+
+    log(f"main leg {args.config} {args.precision}: {n_particles} particles, "
+        f"{args.warmup} warmup + {args.steps} timed steps")
+    main_leg = run_leg(problems, prec, args.steps, args.warmup, not args.no_timing)
+    evals = pair_evals(main_leg["reports"])
+    secs = main_leg["seconds"]
+    value = evals / secs
+    iters = [r["iters"] for step in main_leg["reports"] for r in step]
+    tm = main_leg["timing"]
+    log(f"main leg: {secs * 1e3:.2f} ms, {evals:.3e} pair evals, iterations/step "
+        f"mean {sum(iters) / len(iters):.2f}, pair-pass {tm['pass_launches']} launches "
+        f"{tm['pass_ms']:.3f} ms")
+
+    roofline = None
+    if tm["pass_launches"] > 0 and tm["pass_ms"] > 0:
+        flop = FLOP_PER_PAIR[dim] * tm["pass_pairs"]
+        achieved = flop / (tm["pass_ms"] * 1e-3) / 1e12
+        peak = PEAK_TFLOPS[dtype]
+        src = os.path.join(ROOT, "paper_1904_00861_amd", "csrc", "dtsph_pass.hip")
+        tr = traffic_from_profile(src) if (args.config == "C1" and dtype == "f32") else None
+        roofline = dict(bound="alu", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                        frac=round(achieved / peak, 4), traffic=tr,
+                        kernel="k_pass (pseudo-time pair pass)",
+                        launches=tm["pass_launches"],
+                        avg_launch_us=round(tm["pass_ms"] * 1e3 / tm["pass_launches"], 3),
+                        pairs_per_launch=round(tm["pass_pairs"] / tm["pass_launches"], 1),
+                        flop_per_pair=FLOP_PER_PAIR[dim],
+                        frac_of_packed_peak=round(achieved / PEAK_PACKED_F32, 4) if dtype == "f32" else None)
+
+    extras = {}
+    if not args.no_extras:
+        other = D.FP64 if prec == D.FP32 else D.FP32
+        oname = "fp64" if other == D.FP64 else "fp32"
+        log(f"{oname} leg on the same workload")
+        leg = run_leg(problems, other, args.steps, args.warmup, False)
+        ov = pair_evals(leg["reports"]) / leg["seconds"]
+        extras[f"{oname}_value"] = ov
+        extras[f"speedup_{args.precision}_over_{oname}"] = value / ov
+        if args.config != "C4":
+            batch = I.config("C4")
+            bsteps = 5
+            log(f"batched leg C4: {len(batch)} sims, {sum(p.n for p in batch)} particles, {bsteps} steps")
+            bl = run_leg(batch, D.FP32, bsteps, 1, False)
+            extras["batched_instance_steps_per_s"] = len(batch) * bsteps / bl["seconds"]
+            extras["batched_pair_evals_per_s"] = pair_evals(bl["reports"]) / bl["seconds"]
+            extras["batched_workload"] = WORKLOADS["C4"] + ", FP32 sums, 5 steps"
+    extras["iterations_per_step_mean"] = sum(iters) / len(iters)
+    extras["pass_share_of_step_time"] = (tm["pass_ms"] * 1e-3 / secs) if tm["pass_ms"] else None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(problems[0] if len(problems) == 1 else problems[0])
+
+    out = {
+        "metric": "pseudo-iteration neighbour-pair evaluations per second",
+        "value": value,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "particles": n_particles,
+                   "pair_sums": args.precision,
+                   "positions_pressure_residuals": "f64"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,279 @@
+/*
+ * dtsph.h - C-ABI of libdtsph.so, the MI355X (gfx950) hot path of dual-time
+ * EDAC SPH with particles frozen in pseudo-time.
+ *
+ * The library advances weakly-compressible SPH particle state (positions r,
+ * velocities V, pressures p) by real time steps of the dual-time scheme of
+ * Ramachandran, Muta & Ramakrishna, "Dual-Time Smoothed Particle Hydrodynamics
+ * for Incompressible Fluid Simulation" (arXiv:1904.00861):
+ *   - Algorithm 2 ("Fixed particles in pseudo-time") gives the structure of a
+ *     real step: a rate pass and predictor (eq. v0, eq. r0), the pseudo-time
+ *     loop (eqs. pkstar_frozen, vkp1_frozen, pkp1_frozen with the frozen
+ *     eq. dv_dtau_exact) run until the stop test of section 3.4 (eq. conv and
+ *     the stall rule after it), then the position update eq. r-update;
+ *   - the rates are the SPH sums of section 3.2: eq. dp-dtau-frozen-edac for
+ *     the pressure and eq. mom-sph-frozen for the momentum, with the Monaghan
+ *     artificial viscosity eq. mom-av / eq. av-phiij and the Morris viscous
+ *     term, over neighbours within the support of a quintic spline kernel;
+ *   - walls use the boundary condition of Adami et al. (2012) with the wall
+ *     pressure kept non-negative, as section 3.2 describes.
+ * Particle shifting (section 3.5) is not part of this library.
+ *
+ * Every numerical step runs in HIP kernels on the GPU. Many independent
+ * simulations ("sims") can share one context and advance together.
+ *
+ * Conventions
+ *   - Every call returns an int status (DTSPH_OK = 0, positive = warning,
+ *     negative = error) unless stated otherwise. No C++ exception crosses the
+ *     ABI. After an error, dtsph_last_error() describes it.
+ *   - Particles are in "caller order": sim 0's fluid particles, then sim 0's
+ *     walls, then sim 1's fluid, sim 1's walls, and so on. Per-particle vectors
+ *     are float64 [n][3] row-major (three components even in 2D; the unused one
+ *     is ignored on input and written as 0).
+ *   - Pointers in state views are DEVICE pointers (HIP/torch device memory of
+ *     the context's GPU). Pointers marked "host" are host memory.
+ *   - The caller owns every pointer it passes; the library keeps none of them
+ *     after the call returns. The context owns its internal (cell-ordered)
+ *     copy of the state and all scratch memory, allocated at creation.
+ *   - All GPU work is ordered on the stream given at creation. Calls that
+ *     return reports synchronise that stream before returning.
+ *   - One context must not be used from two threads at once.
+ */
+#ifndef DTSPH_H
+#define DTSPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define DTSPH_OK 0
+#define DTSPH_WARN_MAXITER 1 /* >= 1 sim stopped at max_iter; state valid      */
+#define DTSPH_EINVAL (-1)    /* invalid argument / description / call order    */
+#define DTSPH_ENOMEM (-2)    /* device allocation failed                       */
+#define DTSPH_EHIP (-3)      /* HIP runtime error                               */
+#define DTSPH_ENONFINITE (-4)/* NaN/Inf in a residual; state undefined         */
+#define DTSPH_EOVERFLOW (-5) /* neighbour list capacity exceeded (raise
+                                max_neighbors) or a cell holds > 4096 particles;
+                                state before the failed build is kept          */
+
+/* ---- precision of the pair sums ------------------------------------------
+ * DTSPH_FP64: every quantity in float64 (the plain path).
+ * DTSPH_FP32: pair sums, velocities and pressure rates in float32 on
+ *   cell-frame fixed-point positions; positions, pressure, the pseudo-time
+ *   pressure accumulation and the residual reductions stay float64.        */
+#define DTSPH_FP64 0
+#define DTSPH_FP32 1
+
+/* ---- stop reasons (dtsph_iter_report.reason) ----------------------------
+ * Section 3.4: the loop stops when both residuals are below tol (CONVERGED),
+ * or each is below tol or stalled - its last stall_window values spread by
+ * less than stall_rel of their maximum (STALLED) - or at max_iter. */
+#define DTSPH_RUNNING 0
+#define DTSPH_CONVERGED 1
+#define DTSPH_STALLED 2
+#define DTSPH_MAXITER 3
+#define DTSPH_NONFINITE 4
+#define DTSPH_FIXED 5 /* fixed_iters reached (stop test disabled) */
+
+/* ---- one simulation ------------------------------------------------------
+ * Physical inputs of one sim. Uniform density rho0 (the density is held fixed,
+ * section 3), mass and smoothing length for all its particles.
+ *   dim            2 or 3
+ *   max_neighbors  capacity of each particle's neighbour list; 0 = estimate
+ *                  1.5 x the lattice count of the support + 8
+ *   h, kappa       smoothing length and support radius kappa*h (quintic: 3)
+ *   rho0, mass     density and particle mass
+ *   vref, beta     reference speed and beta = c / vref (section 3.4)
+ *   nu             kinematic viscosity (Morris term)
+ *   nu_e           EDAC diffusivity; <= 0 selects h c / 16 (eq. nu_edac)
+ *   alpha, eps_av  artificial viscosity (eq. mom-av) and its regulariser
+ *   eta            Morris regulariser (0.01 in the paper)
+ *   g              body force per unit mass
+ *   dt, dtau       real step; pseudo step (<= 0 selects dt / beta)
+ *   tol            convergence tolerance epsilon of eq. conv
+ *   max_iter       iteration cap (1000 in the paper)
+ *   stall_window   iterations in the stall test (0..8; the paper says 3 or 4)
+ *   stall_rel      relative spread of the stall test (0.05)
+ *   conv_norm      0: mean residuals (the paper); 1: max residuals
+ *   edac_reg_literal  1: EDAC diffusion denominator r^2 + h^2 as printed,
+ *                  0: r^2 + eta h^2 (the Morris form of the viscous term)
+ *   edac_rho_literal  1: keep the printed extra 1/rho_j in the EDAC term
+ *   lo, hi         domain box. Periodic axes: the period [lo, hi); needs
+ *                  kappa*h < (hi-lo)/2. Other axes: the cell grid's extent;
+ *                  particles outside it are clamped into edge cells.
+ *   periodic       per axis 0/1                                            */
+typedef struct dtsph_sim_desc {
+    int32_t dim;
+    int32_t max_neighbors;
+    double h, kappa;
+    double rho0, mass;
+    double vref, beta;
+    double nu, nu_e;
+    double alpha, eps_av, eta;
+    double g[3];
+    double dt, dtau;
+    double tol;
+    int32_t max_iter, stall_window;
+    double stall_rel;
+    int32_t conv_norm, edac_reg_literal;
+    int32_t edac_rho_literal, reserved0;
+    double lo[3], hi[3];
+    int32_t periodic[3], reserved1;
+} dtsph_sim_desc;
+
+/* ---- state views (device pointers, caller order, n = all particles) -----
+ * Between steps the state is (x, v, v_prev, p) = (r^n, V^n, V^{n-1}, p^n).
+ * For walls, v is the prescribed wall velocity (walls never move), v_prev is
+ * ignored, and p (output only) is the last wall pressure.
+ * Inside a step, after dtsph_predict and until dtsph_correct, the pseudo-time
+ * state is also defined: x_iter = r^(0) (frozen positions), v_iter = V^k,
+ * p_iter = p^k, dpdtau = (dp/dtau)^k; x, v, v_prev, p still hold r^n, V^n,
+ * V^{n-1}, p^n.
+ * dtsph_set_state: x, v, v_prev, p are required. If x_iter is non-NULL, all
+ *   four in-loop pointers are required and the context enters the in-loop
+ *   phase (ready for dtsph_pseudo_iterate); otherwise the between-steps phase.
+ * dtsph_get_state: any pointer may be NULL (not written). In-loop pointers are
+ *   only valid in the in-loop phase (DTSPH_EINVAL otherwise).              */
+typedef struct dtsph_state_view {
+    double *x;      /* [n][3] */
+    double *v;      /* [n][3] */
+    double *v_prev; /* [n][3] */
+    double *p;      /* [n]    */
+    double *x_iter; /* [n][3] */
+    double *v_iter; /* [n][3] */
+    double *p_iter; /* [n]    */
+    double *dpdtau; /* [n]    (walls: 0) */
+} dtsph_state_view;
+
+/* ---- per-sim report of one pseudo-time loop (host memory) ---------------
+ * iters: iterations run; reason: DTSPH_* stop reason; rp_*, rv_*: the last
+ * iteration's residuals of eq. conv, mean |dp/dtau| dt/(rho0 c^2) and mean
+ * |Vtilde|/vref with Vtilde = dt dV/dtau (eq. vtilde), and the same with
+ * max instead of mean; pairs: fluid-row neighbour pairs per iteration.     */
+typedef struct dtsph_iter_report {
+    int32_t iters;
+    int32_t reason;
+    double rp_mean, rv_mean, rp_max, rv_max;
+    int64_t pairs;
+} dtsph_iter_report;
+
+/* ---- timing of the pair pass (host memory; dtsph_set_option TIMING) ----- */
+typedef struct dtsph_timing {
+    int64_t pass_launches;  /* pseudo-iteration pair-pass launches timed     */
+    double pass_ms;         /* summed duration (HIP events on the ctx stream) */
+    int64_t pass_pairs;     /* neighbour pairs those launches evaluated       */
+    int64_t pass_particles; /* fluid particles those launches updated         */
+    int64_t wall_launches;
+    double wall_ms;
+    int64_t build_launches; /* cell + neighbour-list builds                   */
+    double build_ms;
+} dtsph_timing;
+
+/* ---- sizes (host memory) ------------------------------------------------- */
+typedef struct dtsph_info {
+    int64_t n, n_fluid, n_wall;
+    int64_t n_cells;        /* fluid cells of all sims (wall cells: as many)  */
+    int32_t n_sims, precision;
+    int32_t nbr_capacity;   /* neighbour list capacity per particle           */
+    int32_t block;          /* pair-pass workgroup size                       */
+    int64_t device_bytes;   /* device memory owned by the context             */
+} dtsph_info;
+
+typedef struct dtsph_ctx dtsph_ctx;
+
+/* Create a context for n_sims simulations. sims, n_fluid, n_wall: host
+ * arrays of n_sims entries (n_fluid[s] >= 1, n_wall[s] >= 0). precision:
+ * DTSPH_FP64 or DTSPH_FP32. hip_stream: hipStream_t to order work on (NULL:
+ * the default stream). Uses the current HIP device. On success *out owns all
+ * device memory; release with dtsph_destroy. Errors: EINVAL (bad description,
+ * kappa*h >= L/2 on a periodic axis, dt/dtau <= 0, ...), ENOMEM, EHIP; on
+ * error *out is NULL and dtsph_last_error(NULL) describes it.             */
+int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64_t *n_wall,
+                 int32_t n_sims, int32_t precision, void *hip_stream, dtsph_ctx **out);
+
+/* Free the context and its device memory (synchronises its stream). NULL ok. */
+void dtsph_destroy(dtsph_ctx *ctx);
+
+/* Text of the last error of ctx (or of the last failed dtsph_create if ctx is
+ * NULL). Valid until the next call on ctx. Never NULL.                     */
+const char *dtsph_last_error(const dtsph_ctx *ctx);
+
+/* Load / read the particle state (see dtsph_state_view). set_state
+ * invalidates the cell lists. Errors: EINVAL (NULL required pointer, wrong
+ * phase for in-loop fields), EHIP.                                          */
+int dtsph_set_state(dtsph_ctx *ctx, const dtsph_state_view *state);
+int dtsph_get_state(dtsph_ctx *ctx, const dtsph_state_view *state);
+
+/* Cell-linked list and neighbour lists at the current positions (r^n
+ * between steps, r^(0) in the loop): cell key per particle, counting sort by
+ * cell (ties in caller order), cell-start table, and each particle's exact
+ * neighbour list N(i) = { j != i : |r_ij| < kappa h } (minimum image on
+ * periodic axes; fluid rows take fluid and wall j, wall rows fluid j only).
+ * The predicate is evaluated in float64 without fused multiply-add, so the
+ * sets equal those of any implementation of that formula. Neighbour search
+ * is needed once per position change: Algorithm 2 rebuilds once at r^n and
+ * once at r^(0); the pseudo-time loop reuses the list (frozen particles).
+ * Other calls build on demand; calling it explicitly is optional.
+ * Errors: EOVERFLOW (capacity; the message names the needed max_neighbors),
+ * EHIP.                                                                     */
+int dtsph_build_cells(dtsph_ctx *ctx);
+
+/* Predictor of Algorithm 2 (between-steps -> in-loop phase): wall pass and
+ * rate pass at (r^n, V^n, p^n) with dV/dtau = 0, then eq. v0 and eq. r0 in
+ * float64 (positions wrapped into periodic boxes), p^(0) = p^n and
+ * (dp/dtau)^0 = D^n. Errors: EINVAL (already in-loop), EOVERFLOW, EHIP.     */
+int dtsph_predict(dtsph_ctx *ctx);
+
+/* Pseudo-time loop of Algorithm 2 at the frozen positions r^(0) (in-loop
+ * phase, stays in it). Each iteration: p^{k+1/2} = p^k + dtau/2 (dp/dtau)^k;
+ * wall pass at (V^k, p^{k+1/2}); one pair pass giving (dp/dtau)^{k+1/2} and
+ * the momentum right side; dV/dtau from the frozen eq. dv_dtau_exact (BDF2
+ * real-time derivative); V^{k+1} = V^k + dtau dV/dtau; p^{k+1} = p^{k+1/2} +
+ * dtau/2 (dp/dtau)^{k+1/2}; float64 residual reduction and stop test per
+ * sim. fixed_iters > 0: run exactly that many iterations (no stop test);
+ * 0: run until every sim stops. rep: host array of n_sims reports, or NULL.
+ * Returns OK, WARN_MAXITER, ENONFINITE, EINVAL (not in-loop), EHIP.        */
+int dtsph_pseudo_iterate(dtsph_ctx *ctx, int32_t fixed_iters, dtsph_iter_report *rep);
+
+/* Corrector of Algorithm 2 (in-loop -> between-steps phase): eq. r-update
+ * r^{n+1} = r^n + dt/2 (V^n + V^{n+1}) in float64 (wrapped), V^{n-1} <- V^n,
+ * V^n <- V^{n+1}, p^n <- p^K. Errors: EINVAL (not in-loop), EHIP.           */
+int dtsph_correct(dtsph_ctx *ctx);
+
+/* n_steps real steps of Algorithm 2 (predict, pseudo-iterate until each sim
+ * stops, correct) from the between-steps phase. reps: host array of
+ * n_steps * n_sims reports (step-major) or NULL. Returns the worst status. */
+int dtsph_step(dtsph_ctx *ctx, int32_t n_steps, dtsph_iter_report *reps);
+
+/* Test API: neighbour lists at the current positions in caller indices.
+ * offsets: host int64[n+1]; nbrs: host int32[cap] receiving each row in
+ * ascending caller index; *needed (host) receives the total pair count. If
+ * cap < *needed only offsets and needed are written. Builds if needed.    */
+int dtsph_neighbor_list(dtsph_ctx *ctx, int64_t *offsets, int32_t *nbrs, int64_t cap,
+                        int64_t *needed);
+
+/* Test API: the cell-ordered layout of the last build, host arrays of n
+ * entries: key of each slot (fluid keys first, then wall keys), caller index
+ * of each slot; cell_start: host int64[2*n_cells + 1] (start slot of each
+ * key; key k holds slots [cell_start[k], cell_start[k+1])). NULL skips.     */
+int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int64_t *cell_start);
+
+/* Options (value semantics per option). Errors: EINVAL.                    */
+#define DTSPH_OPT_TIMING 1     /* 1: time pair passes with HIP events; 0: off */
+#define DTSPH_OPT_RESET_TIMING 2
+#define DTSPH_OPT_CHUNK 3      /* iterations launched between stop checks (>=1) */
+#define DTSPH_OPT_BLOCK 4      /* pair-pass workgroup size: 64, 128 or 256    */
+#define DTSPH_OPT_XCD_REMAP 5  /* 1: map consecutive tiles to one XCD (default) */
+int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
+
+int dtsph_get_timing(const dtsph_ctx *ctx, dtsph_timing *out);
+int dtsph_get_info(const dtsph_ctx *ctx, dtsph_info *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DTSPH_H */

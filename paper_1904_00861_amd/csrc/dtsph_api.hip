@@ -1,0 +1,728 @@
+// C-ABI of libdtsph: context set-up, argument checking, and the host side of
+// Algorithm 2 (predict -> pseudo-time loop -> correct). All arithmetic on
+// particle data happens in the kernels of dtsph_cells.hip and dtsph_pass.hip;
+// the host only orders launches and reads back per-sim stop flags.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "dtsph_internal.h"
+
+using namespace dtsph;
+
+struct dtsph_ctx {
+    Ctx c;
+};
+
+namespace {
+
+std::string g_create_error = "no error";
+
+template <typename F> int guarded(dtsph_ctx *ctx, F &&f)
+{
+    if (!ctx) return DTSPH_EINVAL;
+    try {
+        DTSPH_HIP_CHECK(hipSetDevice(ctx->c.device));
+        return f(ctx->c);
+    } catch (const ApiError &e) {
+        ctx->c.err = e.what;
+        return e.status;
+    } catch (const HipError &e) {
+        ctx->c.err = e.what;
+        return DTSPH_EHIP;
+    } catch (const std::exception &e) {
+        ctx->c.err = e.what();
+        return DTSPH_EHIP;
+    } catch (...) {
+        ctx->c.err = "unknown error";
+        return DTSPH_EHIP;
+    }
+}
+
+void *dev_alloc(Ctx &c, size_t bytes)
+{
+    void *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) throw ApiError(DTSPH_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                                          hipGetErrorString(e));
+    c.allocs.push_back(p);
+    c.device_bytes += (int64_t)bytes;
+    return p;
+}
+
+void free_all(Ctx &c)
+{
+    for (void *p : c.allocs) (void)hipFree(p);
+    c.allocs.clear();
+    if (c.done_host) (void)hipHostFree(c.flags_host);
+    c.done_host = c.flags_host = nullptr;
+    for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
+    c.ev_pool.clear();
+}
+
+void check_desc(const dtsph_sim_desc &d, int s, int64_t nf, int64_t nw)
+{
+    auto bad = [s](const std::string &m) { throw ApiError(DTSPH_EINVAL, "sim " + std::to_string(s) + ": " + m); };
+    if (d.dim != 2 && d.dim != 3) bad("dim must be 2 or 3");
+    if (nf < 1) bad("n_fluid must be >= 1");
+    if (nw < 0) bad("n_wall must be >= 0");
+    if (!(d.h > 0) || !(d.kappa > 0)) bad("h and kappa must be > 0");
+    if (!(d.rho0 > 0) || !(d.mass > 0)) bad("rho0 and mass must be > 0");
+    if (!(d.vref > 0) || !(d.beta > 0)) bad("vref and beta must be > 0");
+    if (!(d.dt > 0)) bad("dt must be > 0");
+    if (d.dtau < 0 || !std::isfinite(d.dtau)) bad("dtau must be >= 0 (0 selects dt/beta)");
+    if (d.nu < 0 || d.alpha < 0 || d.eta < 0 || d.eps_av < 0) bad("nu, alpha, eta, eps_av must be >= 0");
+    if (!(d.tol >= 0)) bad("tol must be >= 0");
+    if (d.max_iter < 1) bad("max_iter must be >= 1");
+    if (d.stall_window < 0 || d.stall_window > kHist) bad("stall_window must be in [0, 8]");
+    if (d.conv_norm != 0 && d.conv_norm != 1) bad("conv_norm must be 0 or 1");
+    if (d.max_neighbors < 0 || d.max_neighbors > 65535) bad("max_neighbors must be in [0, 65535]");
+    for (int a = 0; a < d.dim; ++a) {
+        if (!(d.hi[a] > d.lo[a])) bad("hi must exceed lo on every axis");
+        if (d.periodic[a] && !(d.kappa * d.h < 0.5 * (d.hi[a] - d.lo[a])))
+            bad("kappa*h must be below half the period on periodic axes");
+    }
+}
+
+SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
+{
+    SimDev S;
+    std::memset(&S, 0, sizeof(S));
+    S.dim = d.dim;
+    S.nf = (int)nf;
+    S.nw = (int)nw;
+    S.edac_reg_literal = d.edac_reg_literal;
+    const double kh = d.kappa * d.h;
+    for (int a = 0; a < 3; ++a) {
+        if (a < d.dim) {
+            S.lo[a] = d.lo[a];
+            S.hi[a] = d.hi[a];
+            S.L[a] = d.hi[a] - d.lo[a];
+            S.halfL[a] = 0.5 * S.L[a];
+            S.periodic[a] = d.periodic[a] ? 1 : 0;
+            // cells no smaller than kappa*h (small margin against rounding)
+            int n = (int)std::floor(S.L[a] / (kh * (1.0 + 1e-6)));
+            S.ncell[a] = std::max(1, n);
+            S.cs[a] = S.L[a] / S.ncell[a];
+            S.inv_cs[a] = 1.0 / S.cs[a];
+            // fixed-point frame: a length q_len maps onto 2^32 units; on periodic
+            // axes q_len divides the period so wrap-around is exact
+            if (S.periodic[a]) {
+                double m = std::max(1.0, std::floor(S.L[a] / (4.0 * kh)));
+                S.q_len[a] = S.L[a] / m;
+            } else {
+                S.q_len[a] = 4.0 * kh;
+            }
+            S.q_inv[a] = 4294967296.0 / S.q_len[a];
+        } else {
+            S.ncell[a] = 1;
+            S.cs[a] = S.inv_cs[a] = 1.0;
+            S.L[a] = S.halfL[a] = 1.0;
+            S.q_len[a] = 1.0;
+            S.q_inv[a] = 0.0;
+        }
+    }
+    S.kh2 = kh * kh;
+    S.h = d.h;
+    S.inv_h = 1.0 / d.h;
+    S.rho0 = d.rho0;
+    S.mass = d.mass;
+    // section 3.4: c = beta V_ref, dtau = dt / beta; eq. nu_edac: nu_e = h c / 16
+    S.c = d.beta * d.vref;
+    S.nu = d.nu;
+    S.nu_e = d.nu_e > 0 ? d.nu_e : d.h * S.c / 16.0;
+    for (int a = 0; a < 3; ++a) S.g[a] = a < d.dim ? d.g[a] : 0.0;
+    S.dt = d.dt;
+    S.dtau = d.dtau > 0 ? d.dtau : d.dt / d.beta;
+    // frozen eq. dv_dtau_exact: factor 2 dt / (2 dt + 3 dtau)
+    S.gamma = 2.0 * S.dt / (2.0 * S.dt + 3.0 * S.dtau);
+    S.inv2dt = 1.0 / (2.0 * S.dt);
+    S.tol = d.tol;
+    S.vref = d.vref;
+    S.max_iter = d.max_iter;
+    S.stall_window = d.stall_window;
+    S.stall_rel = d.stall_rel;
+    S.conv_norm = d.conv_norm;
+    // quintic spline normalisation; dW/dr = (sigma/h) w'(q) = kg * poly(q)
+    const double pi = 3.14159265358979323846;
+    S.sigma = d.dim == 2 ? 7.0 / (478.0 * pi * d.h * d.h) : 1.0 / (120.0 * pi * d.h * d.h * d.h);
+    S.kg = -5.0 * S.sigma / d.h;
+    const double rho = d.rho0, m = d.mass;
+    S.k_div = S.c * S.c * m * S.kg;                     // (m rho_i/rho_j) c^2, rho uniform
+    double ecoef = 4.0 * m / (2.0 * rho);                // 4 m_j / (rho_i + rho_j)
+    if (d.edac_rho_literal) ecoef /= rho;
+    S.k_lap = ecoef * S.nu_e * S.kg;
+    S.k_grad = -(m / (rho * rho)) * S.kg;
+    S.k_visc = 4.0 * m * d.nu / (2.0 * rho) * S.kg;
+    S.k_av = -d.alpha * d.h * S.c * rho;                 // rho^2 Pi = k_av * min(phi, 0)
+    S.den_v = d.eta * d.h * d.h;
+    S.den_e = d.edac_reg_literal ? d.h * d.h : d.eta * d.h * d.h;
+    S.den_a = d.eps_av * d.h * d.h;
+    S.tiny_r2 = 1e-12 * d.h * d.h;
+    S.res_p = S.dt / (rho * S.c * S.c) / (double)nf;
+    S.res_v = 1.0 / (d.vref * (double)nf);
+    return S;
+}
+
+void setup_tiles(Ctx &c)
+{
+    std::vector<int2> tiles;
+    for (int s = 0; s < c.n_sims; ++s) {
+        c.sims_h[s].tile_begin = (int)tiles.size();
+        for (int off = 0; off < (int)c.nf[s]; off += c.block) tiles.push_back(make_int2(s, c.fluid_begin[s] + off));
+        c.sims_h[s].tile_end = (int)tiles.size();
+    }
+    c.n_tiles = (int)tiles.size();
+    DTSPH_HIP_CHECK(hipMemcpy(c.tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice));
+    DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
+}
+
+template <typename T> void alloc_state(Ctx &c)
+{
+    const size_t N = c.N, Nf = c.Nf, Nw = std::max(c.Nw, 1);
+    for (int b = 0; b < 2; ++b) {
+        c.orig[b] = (int *)dev_alloc(c, 4 * N);
+        c.simid[b] = (int *)dev_alloc(c, 4 * N);
+        c.x[b] = (double *)dev_alloc(c, 8 * 3 * N);
+        c.xn[b] = (double *)dev_alloc(c, 8 * 3 * N);
+        c.vn[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
+        c.dv[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
+        c.w[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
+        c.pm[b] = (double *)dev_alloc(c, 8 * Nf);
+        c.pn[b] = (double *)dev_alloc(c, 8 * Nf);
+        c.dp[b] = dev_alloc(c, sizeof(T) * Nf);
+        c.vw[b] = dev_alloc(c, sizeof(T) * 3 * Nw);
+        c.pw[b] = dev_alloc(c, sizeof(T) * Nw);
+        c.vp[b] = dev_alloc(c, sizeof(T) * 4 * N);
+    }
+    c.prec = dev_alloc(c, (sizeof(T) == 4 ? 16 : 32) * N);
+}
+
+// ---- timing -------------------------------------------------------------------
+hipEvent_t pool_event(Ctx &c, size_t k)
+{
+    while (c.ev_pool.size() <= k) {
+        hipEvent_t e;
+        DTSPH_HIP_CHECK(hipEventCreate(&e));
+        c.ev_pool.push_back(e);
+    }
+    return c.ev_pool[k];
+}
+
+void resolve_timers(Ctx &c)
+{
+    for (auto &pr : c.ev_pending) {
+        float ms = 0.f;
+        DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, c.ev_pool[pr.first], c.ev_pool[pr.first + 1]));
+        if (pr.second == 0) { c.tstats.pass_launches++; c.tstats.pass_ms += ms; }
+        else if (pr.second == 1) { c.tstats.wall_launches++; c.tstats.wall_ms += ms; }
+        else { c.tstats.build_launches++; c.tstats.build_ms += ms; }
+    }
+    c.ev_pending.clear();
+    c.ev_used = 0;
+}
+
+// ---- flags / sync -------------------------------------------------------------
+void readback_flags(Ctx &c)
+{
+    DTSPH_HIP_CHECK(hipMemcpyAsync(c.flags_host, c.flags, sizeof(int) * (F_COUNT + c.n_sims), hipMemcpyDeviceToHost,
+                                   c.stream));
+    DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+    if (c.timing) resolve_timers(c);
+    if (c.flags_host[F_NBR_OVERFLOW])
+        throw ApiError(DTSPH_EOVERFLOW, "neighbour list capacity " + std::to_string(c.cap) + " exceeded; needs " +
+                                            std::to_string(c.flags_host[F_NBR_NEEDED]) +
+                                            " (set max_neighbors); particle state is undefined");
+    if (c.flags_host[F_CELL_OVERFLOW])
+        throw ApiError(DTSPH_EOVERFLOW, "a cell holds more than 4096 particles (particles far outside the grid "
+                                        "box or clumped); particle state is undefined");
+}
+
+template <typename T> void ensure_cells(Ctx &c)
+{
+    if (!c.cells_valid) {
+        build_cells<T>(c);
+        c.cells_valid = true;
+    }
+}
+
+template <typename T> void do_predict(Ctx &c)
+{
+    if (c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_predict: already inside a step (call dtsph_correct)");
+    ensure_cells<T>(c);
+    launch_pre_records<T>(c);
+    launch_wall<T>(c, MODE_PRE);
+    launch_pass<T>(c, MODE_PRE);
+    c.xb ^= 1;
+    c.in_loop = true;
+    c.cells_valid = false;
+}
+
+template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
+{
+    if (!c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_pseudo_iterate: not inside a step (call dtsph_predict)");
+    if (fixed < 0) throw ApiError(DTSPH_EINVAL, "fixed_iters must be >= 0");
+    ensure_cells<T>(c);
+    launch_loop_begin<T>(c, fixed);
+    int max_it = fixed;
+    if (fixed == 0)
+        for (auto &d : c.desc) max_it = std::max(max_it, (int)d.max_iter);
+    int launched = 0;
+    int chunk = c.chunk > 0 ? c.chunk : std::max(1, std::min(c.last_iters, 64));
+    if (fixed > 0) chunk = std::min(chunk, fixed);
+    for (;;) {
+        const int n = std::min(chunk, max_it - launched);
+        for (int k = 0; k < n; ++k) {
+            launch_wall<T>(c, MODE_PSEUDO);
+            launch_pass<T>(c, MODE_PSEUDO);
+            launch_finalize(c);
+        }
+        launched += n;
+        readback_flags(c);
+        bool all = true;
+        for (int s = 0; s < c.n_sims; ++s) all = all && c.flags_host[F_COUNT + s];
+        if (all || launched >= max_it) break;
+        chunk = c.chunk > 0 ? c.chunk : 2;
+    }
+    launch_loop_end<T>(c);
+    std::vector<SimIter> it(c.n_sims);
+    std::vector<unsigned long long> pairs(c.n_sims);
+    DTSPH_HIP_CHECK(hipMemcpyAsync(it.data(), c.iters, sizeof(SimIter) * c.n_sims, hipMemcpyDeviceToHost, c.stream));
+    DTSPH_HIP_CHECK(hipMemcpyAsync(pairs.data(), c.pairs, 8 * c.n_sims, hipMemcpyDeviceToHost, c.stream));
+    DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+    int status = DTSPH_OK, most = 1;
+    for (int s = 0; s < c.n_sims; ++s) {
+        most = std::max(most, it[s].iters);
+        c.tstats.pass_pairs += (int64_t)pairs[s] * it[s].iters;
+        c.tstats.pass_particles += c.nf[s] * it[s].iters;
+        if (rep) {
+            rep[s].iters = it[s].iters;
+            rep[s].reason = it[s].reason;
+            rep[s].rp_mean = it[s].rp_mean;
+            rep[s].rv_mean = it[s].rv_mean;
+            rep[s].rp_max = it[s].rp_max;
+            rep[s].rv_max = it[s].rv_max;
+            rep[s].pairs = (int64_t)pairs[s];
+        }
+        if (it[s].reason == DTSPH_NONFINITE) status = DTSPH_ENONFINITE;
+        else if (it[s].reason == DTSPH_MAXITER && status == DTSPH_OK) status = DTSPH_WARN_MAXITER;
+    }
+    c.last_iters = most;
+    if (status == DTSPH_ENONFINITE) c.err = "non-finite residual in the pseudo-time loop";
+    return status;
+}
+
+template <typename T> void do_correct(Ctx &c)
+{
+    if (!c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_correct: not inside a step (call dtsph_predict)");
+    launch_correct<T>(c);
+    c.in_loop = false;
+    c.cells_valid = false;
+}
+
+template <typename T> int do_step(Ctx &c, int n_steps, dtsph_iter_report *reps)
+{
+    if (n_steps < 0) throw ApiError(DTSPH_EINVAL, "n_steps must be >= 0");
+    if (c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_step: inside a step (call dtsph_correct first)");
+    int status = DTSPH_OK;
+    for (int s = 0; s < n_steps; ++s) {
+        do_predict<T>(c);
+        int st = do_loop<T>(c, 0, reps ? reps + (size_t)s * c.n_sims : nullptr);
+        do_correct<T>(c);
+        if (st < 0) return st;
+        if (st > 0) status = st;
+    }
+    return status;
+}
+
+template <typename F> auto by_precision(Ctx &c, F &&f)
+{
+    if (c.precision == DTSPH_FP32) return f(float());
+    return f(double());
+}
+
+}  // namespace
+
+namespace dtsph {
+
+int timer_begin(Ctx &c)
+{
+    if (!c.timing) return -1;
+    size_t k = c.ev_used;
+    c.ev_used += 2;
+    DTSPH_HIP_CHECK(hipEventRecord(pool_event(c, k), c.stream));
+    pool_event(c, k + 1);
+    return (int)k;
+}
+
+void timer_end(Ctx &c, int slot, int kind)
+{
+    if (slot < 0) return;
+    DTSPH_HIP_CHECK(hipEventRecord(c.ev_pool[slot + 1], c.stream));
+    c.ev_pending.emplace_back(slot, kind);
+}
+
+}  // namespace dtsph
+
+extern "C" {
+
+int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64_t *n_wall, int32_t n_sims,
+                 int32_t precision, void *hip_stream, dtsph_ctx **out)
+{
+    if (out) *out = nullptr;
+    dtsph_ctx *ctx = nullptr;
+    try {
+        if (!sims || !n_fluid || !n_wall || !out) throw ApiError(DTSPH_EINVAL, "NULL argument");
+        if (n_sims < 1) throw ApiError(DTSPH_EINVAL, "n_sims must be >= 1");
+        if (precision != DTSPH_FP32 && precision != DTSPH_FP64)
+            throw ApiError(DTSPH_EINVAL, "precision must be DTSPH_FP32 or DTSPH_FP64");
+        int64_t N = 0, Nf = 0, Nw = 0, C = 0;
+        for (int s = 0; s < n_sims; ++s) {
+            check_desc(sims[s], s, n_fluid[s], n_wall[s]);
+            if (sims[s].dim != sims[0].dim) throw ApiError(DTSPH_EINVAL, "all sims of a context must share dim");
+            Nf += n_fluid[s];
+            Nw += n_wall[s];
+        }
+        N = Nf + Nw;
+        if (N >= (int64_t)1 << 31) throw ApiError(DTSPH_EINVAL, "too many particles for one context");
+
+        ctx = new dtsph_ctx();
+        Ctx &c = ctx->c;
+        DTSPH_HIP_CHECK(hipGetDevice(&c.device));
+        c.stream = (hipStream_t)hip_stream;
+        c.precision = precision;
+        c.n_sims = n_sims;
+        c.N = (int)N;
+        c.Nf = (int)Nf;
+        c.Nw = (int)Nw;
+        c.desc.assign(sims, sims + n_sims);
+        c.nf.assign(n_fluid, n_fluid + n_sims);
+        c.nw.assign(n_wall, n_wall + n_sims);
+        c.max_dim = sims[0].dim;
+        c.sims_h.resize(n_sims);
+        c.fluid_begin.resize(n_sims);
+        int64_t fb = 0, wb = 0;
+        double cap_est = 0;
+        std::vector<int> init_slot(2 * N);
+        int64_t caller = 0;
+        for (int s = 0; s < n_sims; ++s) {
+            const dtsph_sim_desc &d = sims[s];
+            SimDev S = make_simdev(d, n_fluid[s], n_wall[s]);
+            S.fluid_begin = (int)fb;
+            S.key_base = (int)C;
+            int64_t cells = (int64_t)S.ncell[0] * S.ncell[1] * S.ncell[2];
+            C += cells;
+            if (2 * C > (int64_t)4096 * 4096)
+                throw ApiError(DTSPH_EINVAL, "cell grid too large (more than 8M cells); enlarge h or shrink the box");
+            c.sims_h[s] = S;
+            c.fluid_begin[s] = (int)fb;
+            for (int64_t k = 0; k < n_fluid[s]; ++k, ++caller) {
+                init_slot[caller] = (int)(fb + k);
+                init_slot[N + caller] = s;
+            }
+            for (int64_t k = 0; k < n_wall[s]; ++k, ++caller) {
+                init_slot[caller] = (int)(Nf + wb + k);
+                init_slot[N + caller] = s;
+            }
+            fb += n_fluid[s];
+            wb += n_wall[s];
+            c.any_walls = c.any_walls || n_wall[s] > 0;
+            c.any_av = c.any_av || d.alpha > 0;
+            c.sep_den = c.sep_den || S.den_e != S.den_v || (d.alpha > 0 && S.den_a != S.den_v);
+            double est;
+            if (d.max_neighbors > 0) {
+                est = d.max_neighbors;
+            } else {
+                const double dx = std::pow(d.mass / d.rho0, 1.0 / d.dim), kh = d.kappa * d.h;
+                const double lat = d.dim == 2 ? 3.14159265358979 * kh * kh / (dx * dx)
+                                              : 4.0 / 3.0 * 3.14159265358979 * kh * kh * kh / (dx * dx * dx);
+                est = 1.5 * lat + 8.0;
+            }
+            cap_est = std::max(cap_est, est);
+        }
+        c.C = (int)C;
+        c.cap = std::min(65535, ((int)std::ceil(cap_est) + 3) / 4 * 4);
+
+        // device memory
+        c.sims = (SimDev *)dev_alloc(c, sizeof(SimDev) * n_sims);
+        c.iters = (SimIter *)dev_alloc(c, sizeof(SimIter) * n_sims);
+        if (precision == DTSPH_FP32) alloc_state<float>(c);
+        else alloc_state<double>(c);
+        c.key = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
+        c.rank = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
+        c.perm = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
+        c.count = (uint32_t *)dev_alloc(c, 4 * (size_t)(2 * C));
+        c.cell_start = (uint32_t *)dev_alloc(c, 4 * (size_t)(2 * C + 1));
+        c.scan_tmp = (uint32_t *)dev_alloc(c, 4 * (size_t)(4096 + 1));
+        c.nbr = (int *)dev_alloc(c, 4 * (size_t)c.cap * (size_t)N);
+        c.cnt = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
+        c.pairs = (unsigned long long *)dev_alloc(c, 8 * (size_t)n_sims);
+        const size_t max_tiles = (size_t)(Nf / 64 + n_sims + 8);
+        c.tiles = (int2 *)dev_alloc(c, sizeof(int2) * max_tiles);
+        c.partials = (double4 *)dev_alloc(c, sizeof(double4) * max_tiles);
+        c.flags = (int *)dev_alloc(c, sizeof(int) * (F_COUNT + n_sims));
+        c.done_dev = c.flags + F_COUNT;
+        c.init_slot = (int *)dev_alloc(c, sizeof(int) * 2 * (size_t)N);
+        DTSPH_HIP_CHECK(hipHostMalloc((void **)&c.flags_host, sizeof(int) * (F_COUNT + n_sims), 0));
+        c.done_host = c.flags_host + F_COUNT;
+        DTSPH_HIP_CHECK(hipMemcpy(c.init_slot, init_slot.data(), sizeof(int) * 2 * N, hipMemcpyHostToDevice));
+        DTSPH_HIP_CHECK(hipMemset(c.flags, 0, sizeof(int) * (F_COUNT + n_sims)));
+        DTSPH_HIP_CHECK(hipMemset(c.cell_start, 0, 4 * (size_t)(2 * C + 1)));
+        DTSPH_HIP_CHECK(hipMemset(c.cnt, 0, 4 * (size_t)N));
+        DTSPH_HIP_CHECK(hipMemset(c.pairs, 0, 8 * (size_t)n_sims));
+        setup_tiles(c);
+        DTSPH_HIP_CHECK(hipDeviceSynchronize());
+        *out = ctx;
+        return DTSPH_OK;
+    } catch (const ApiError &e) {
+        g_create_error = e.what;
+        if (ctx) { free_all(ctx->c); delete ctx; }
+        return e.status;
+    } catch (const HipError &e) {
+        g_create_error = e.what;
+        if (ctx) { free_all(ctx->c); delete ctx; }
+        return DTSPH_EHIP;
+    } catch (...) {
+        g_create_error = "unknown error in dtsph_create";
+        if (ctx) { free_all(ctx->c); delete ctx; }
+        return DTSPH_EHIP;
+    }
+}
+
+void dtsph_destroy(dtsph_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipStreamSynchronize(ctx->c.stream);
+    free_all(ctx->c);
+    delete ctx;
+}
+
+const char *dtsph_last_error(const dtsph_ctx *ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return ctx->c.err.empty() ? "no error" : ctx->c.err.c_str();
+}
+
+int dtsph_set_state(dtsph_ctx *ctx, const dtsph_state_view *s)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        if (!s || !s->x || !s->v || !s->v_prev || !s->p) throw ApiError(DTSPH_EINVAL, "x, v, v_prev, p are required");
+        const bool lp = s->x_iter != nullptr;
+        if (lp && (!s->v_iter || !s->p_iter || !s->dpdtau))
+            throw ApiError(DTSPH_EINVAL, "in-loop state needs x_iter, v_iter, p_iter and dpdtau");
+        by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            launch_set_state<T>(c, *s, lp);
+            return 0;
+        });
+        c.in_loop = lp;
+        c.cells_valid = false;
+        c.cur = 0;
+        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+        return DTSPH_OK;
+    });
+}
+
+int dtsph_get_state(dtsph_ctx *ctx, const dtsph_state_view *s)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        if (!s) throw ApiError(DTSPH_EINVAL, "NULL view");
+        const bool want_loop = s->x_iter || s->v_iter || s->p_iter || s->dpdtau;
+        if (want_loop && !c.in_loop) throw ApiError(DTSPH_EINVAL, "in-loop fields requested outside a step");
+        by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            launch_get_state<T>(c, *s, c.in_loop);
+            return 0;
+        });
+        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+        return DTSPH_OK;
+    });
+}
+
+int dtsph_build_cells(dtsph_ctx *ctx)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            ensure_cells<T>(c);
+            return 0;
+        });
+        readback_flags(c);
+        return DTSPH_OK;
+    });
+}
+
+int dtsph_predict(dtsph_ctx *ctx)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            do_predict<T>(c);
+            return 0;
+        });
+        readback_flags(c);
+        return DTSPH_OK;
+    });
+}
+
+int dtsph_pseudo_iterate(dtsph_ctx *ctx, int32_t fixed_iters, dtsph_iter_report *rep)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        return by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            return do_loop<T>(c, fixed_iters, rep);
+        });
+    });
+}
+
+int dtsph_correct(dtsph_ctx *ctx)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            do_correct<T>(c);
+            return 0;
+        });
+        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+        return DTSPH_OK;
+    });
+}
+
+int dtsph_step(dtsph_ctx *ctx, int32_t n_steps, dtsph_iter_report *reps)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        return by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            return do_step<T>(c, n_steps, reps);
+        });
+    });
+}
+
+int dtsph_neighbor_list(dtsph_ctx *ctx, int64_t *offsets, int32_t *nbrs, int64_t cap, int64_t *needed)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        if (!offsets || !needed) throw ApiError(DTSPH_EINVAL, "offsets and needed are required");
+        by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            ensure_cells<T>(c);
+            return 0;
+        });
+        readback_flags(c);
+        const size_t N = c.N;
+        std::vector<uint32_t> cnt(N);
+        std::vector<int> orig(N), nb((size_t)c.cap * N);
+        DTSPH_HIP_CHECK(hipMemcpy(cnt.data(), c.cnt, 4 * N, hipMemcpyDeviceToHost));
+        DTSPH_HIP_CHECK(hipMemcpy(orig.data(), c.orig[c.buf], 4 * N, hipMemcpyDeviceToHost));
+        DTSPH_HIP_CHECK(hipMemcpy(nb.data(), c.nbr, 4 * (size_t)c.cap * N, hipMemcpyDeviceToHost));
+        std::vector<int64_t> len(N + 1, 0);
+        std::vector<size_t> slot_of(N);
+        for (size_t i = 0; i < N; ++i) {
+            len[orig[i] + 1] = (cnt[i] & 0xffffu) + (cnt[i] >> 16);
+            slot_of[orig[i]] = i;
+        }
+        for (size_t k = 0; k < N; ++k) len[k + 1] += len[k];
+        *needed = len[N];
+        std::memcpy(offsets, len.data(), 8 * (N + 1));
+        if (nbrs && cap >= len[N]) {
+            for (size_t cidx = 0; cidx < N; ++cidx) {
+                const size_t i = slot_of[cidx];
+                const int n = (int)((cnt[i] & 0xffffu) + (cnt[i] >> 16));
+                int32_t *row = nbrs + len[cidx];
+                for (int k = 0; k < n; ++k) row[k] = orig[nb[(size_t)k * N + i]];
+                std::sort(row, row + n);
+            }
+        }
+        return DTSPH_OK;
+    });
+}
+
+int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int64_t *cell_start)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            ensure_cells<T>(c);
+            return 0;
+        });
+        readback_flags(c);
+        const size_t N = c.N, K = 2 * (size_t)c.C + 1;
+        if (keys) {
+            std::vector<uint32_t> key(N), perm(N);
+            DTSPH_HIP_CHECK(hipMemcpy(key.data(), c.key, 4 * N, hipMemcpyDeviceToHost));
+            DTSPH_HIP_CHECK(hipMemcpy(perm.data(), c.perm, 4 * N, hipMemcpyDeviceToHost));
+            for (size_t d = 0; d < N; ++d) keys[d] = (int32_t)key[perm[d]];
+        }
+        if (caller_index) DTSPH_HIP_CHECK(hipMemcpy(caller_index, c.orig[c.buf], 4 * N, hipMemcpyDeviceToHost));
+        if (cell_start) {
+            std::vector<uint32_t> cs(K);
+            DTSPH_HIP_CHECK(hipMemcpy(cs.data(), c.cell_start, 4 * K, hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < K; ++k) cell_start[k] = cs[k];
+        }
+        return DTSPH_OK;
+    });
+}
+
+int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        switch (option) {
+        case DTSPH_OPT_TIMING:
+            c.timing = value != 0;
+            break;
+        case DTSPH_OPT_RESET_TIMING:
+            DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+            resolve_timers(c);
+            c.tstats = dtsph_timing{};
+            break;
+        case DTSPH_OPT_CHUNK:
+            if (value < 0 || value > 1000) throw ApiError(DTSPH_EINVAL, "chunk must be in [0, 1000] (0 = adaptive)");
+            c.chunk = (int)value;
+            break;
+        case DTSPH_OPT_BLOCK:
+            if (value != 64 && value != 128 && value != 256) throw ApiError(DTSPH_EINVAL, "block must be 64, 128 or 256");
+            DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+            c.block = (int)value;
+            setup_tiles(c);
+            break;
+        case DTSPH_OPT_XCD_REMAP:
+            c.xcd_remap = value != 0;
+            break;
+        default:
+            throw ApiError(DTSPH_EINVAL, "unknown option " + std::to_string(option));
+        }
+        return DTSPH_OK;
+    });
+}
+
+int dtsph_get_timing(const dtsph_ctx *ctx, dtsph_timing *out)
+{
+    if (!ctx || !out) return DTSPH_EINVAL;
+    dtsph_ctx *m = const_cast<dtsph_ctx *>(ctx);
+    return guarded(m, [&](Ctx &c) {
+        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+        resolve_timers(c);
+        *out = c.tstats;
+        return DTSPH_OK;
+    });
+}
+
+int dtsph_get_info(const dtsph_ctx *ctx, dtsph_info *out)
+{
+    if (!ctx || !out) return DTSPH_EINVAL;
+    const Ctx &c = ctx->c;
+    out->n = c.N;
+    out->n_fluid = c.Nf;
+    out->n_wall = c.Nw;
+    out->n_cells = c.C;
+    out->n_sims = c.n_sims;
+    out->precision = c.precision;
+    out->nbr_capacity = c.cap;
+    out->block = c.block;
+    out->device_bytes = c.device_bytes;
+    return DTSPH_OK;
+}
+
+}  // extern "C"

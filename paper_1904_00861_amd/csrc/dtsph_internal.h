@@ -1,0 +1,185 @@
+// Internal declarations of libdtsph (not part of the C-ABI).
+//
+// Layout on the device (one context, all sims):
+//   * "slots" are the cell-ordered particle positions in memory. Keys put every
+//     fluid particle of every sim before every wall particle, and within each
+//     type sim by sim, cell by cell, caller index by caller index. Hence fluid
+//     slots [0, Nf) hold sim s's fluid at [fluid_begin[s], fluid_begin[s]+nf[s])
+//     (fixed for the context's life) and wall slots are [Nf, N).
+//   * Structure-of-arrays, one array per component ([a*n + i]), float64 master
+//     copies of positions and pressure; velocity-like arrays in the pass type T.
+//   * The pair pass reads neighbours through two gathered records per slot: a
+//     position record (32-bit fixed point for FP32, float64 for FP64) built with
+//     the neighbour list, and a T4 {V, p} record ping-ponged between passes.
+//   * Neighbour lists are column-major (ELL): entry k of slot i at nbr[k*N + i],
+//     so lanes of a wavefront read consecutive words. Fluid neighbours come
+//     first, then wall neighbours; cnt[i] = n_fluid_nbrs | n_wall_nbrs << 16.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "dtsph.h"
+
+namespace dtsph {
+
+constexpr int kHist = 8;             // residual history ring (stall window <= 8)
+constexpr int kMaxCellOccupancy = 4096;
+constexpr int kMaxBlock = 256;
+
+enum PassMode { MODE_PRE = 0, MODE_PSEUDO = 1 };
+
+// Device flag words
+enum Flag { F_NBR_OVERFLOW = 0, F_NBR_NEEDED = 1, F_CELL_OVERFLOW = 2, F_COUNT = 4 };
+
+// Per-sim constants (device). Everything the kernels need, precomputed on the
+// host in float64; FP32 kernels convert once per thread.
+struct SimDev {
+    int dim, nf, nw;
+    int fluid_begin;     // first fluid slot
+    int key_base;        // first fluid key; wall keys add the total cell count
+    int tile_begin, tile_end;  // fluid tiles of this sim (residual partials)
+    int ncell[3];
+    int periodic[3];
+    int edac_reg_literal;
+    double lo[3], hi[3], L[3], halfL[3], cs[3], inv_cs[3];
+    double kh2;          // (kappa h)^2, exact neighbour predicate
+    double h, inv_h, rho0, mass, c, nu, nu_e;
+    double g[3];
+    double dt, dtau, gamma, inv2dt, tol, vref;
+    int max_iter, stall_window, conv_norm, pad0;
+    double stall_rel;
+    // pass coefficients: dW/dr = kg * poly(q); see the pass kernel
+    double sigma, kg;
+    double k_div, k_lap, k_grad, k_visc, k_av;
+    double den_v, den_e, den_a;   // eta h^2, EDAC regulariser, eps_av h^2
+    double tiny_r2;
+    // 32-bit fixed-point frame of the FP32 pass: x_q = (x - lo) * q_inv mod 2^32
+    double q_inv[3], q_len[3];
+    double res_p, res_v;          // residual scales incl. 1/nf
+};
+
+// Per-sim pseudo-time loop state (device).
+struct SimIter {
+    int iters, done, reason, fixed;
+    double hp[kHist], hv[kHist];
+    double rp_mean, rv_mean, rp_max, rv_max;
+};
+
+// Context (host object owning device memory).
+struct Ctx {
+    int precision = DTSPH_FP32;
+    int n_sims = 0;
+    int N = 0, Nf = 0, Nw = 0;
+    int C = 0;               // fluid cells of all sims; keys 0..2C-1
+    int cap = 0;             // neighbour-list capacity per particle
+    int block = 256;
+    int chunk = 0;           // 0 = adaptive
+    int xcd_remap = 1;
+    int max_dim = 2;
+    bool any_walls = false, any_av = false, sep_den = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    std::vector<dtsph_sim_desc> desc;
+    std::vector<int64_t> nf, nw;
+    std::vector<SimDev> sims_h;
+    std::vector<int> fluid_begin, wall_begin_caller, caller_begin;
+
+    // phase
+    bool in_loop = false;
+    bool cells_valid = false;
+    int cur = 0;             // which vp buffer is current
+    int last_iters = 4;      // adaptive chunking
+
+    // device memory
+    std::vector<void *> allocs;
+    int64_t device_bytes = 0;
+    SimDev *sims = nullptr;
+    SimIter *iters = nullptr;
+    int *orig[2] = {nullptr, nullptr};
+    int *simid[2] = {nullptr, nullptr};
+    double *x[2] = {nullptr, nullptr};    // active positions (3 x N SoA)
+    double *xn[2] = {nullptr, nullptr};   // r^n during the loop (3 x N)
+    void *vn[2] = {nullptr, nullptr};     // V^n (3 x Nf, type T)
+    void *dv[2] = {nullptr, nullptr};     // V^n - V^{n-1}
+    void *w[2] = {nullptr, nullptr};      // V^k - V^n
+    double *pm[2] = {nullptr, nullptr};   // p^n, or p^{k+1/2} inside the loop
+    double *pn[2] = {nullptr, nullptr};   // p^n kept during the loop
+    void *dp[2] = {nullptr, nullptr};     // (dp/dtau)^k (type T)
+    void *vw[2] = {nullptr, nullptr};     // prescribed wall velocity (3 x Nw)
+    void *pw[2] = {nullptr, nullptr};     // last wall pressure (Nw)
+    int buf = 0;                          // which gathered buffer set is live
+    int xb = 0;                           // live buffer of x (also swapped by the predictor)
+    void *vp[2] = {nullptr, nullptr};     // T4 {V, p} records (N)
+    void *prec = nullptr;                 // position records (N): uint4 or double4
+    uint32_t *key = nullptr, *rank = nullptr, *perm = nullptr;
+    uint32_t *count = nullptr, *cell_start = nullptr, *scan_tmp = nullptr;
+    int *nbr = nullptr;
+    uint32_t *cnt = nullptr;
+    unsigned long long *pairs = nullptr;  // per sim
+    int2 *tiles = nullptr;
+    int n_tiles = 0;
+    int2 *wtiles = nullptr;
+    int n_wtiles = 0;
+    double4 *partials = nullptr;
+    int *flags = nullptr;
+    int *done_dev = nullptr;
+    int *init_slot = nullptr;             // caller index -> slot before any sort
+
+    // pinned host mirrors
+    int *done_host = nullptr;
+    int *flags_host = nullptr;
+
+    // timing
+    bool timing = false;
+    dtsph_timing tstats{};
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_pending;  // (start event, kind)
+    size_t ev_used = 0;
+
+    std::string err;
+};
+
+// ---- launchers (defined in the .hip files) ---------------------------------
+template <typename T> void build_cells(Ctx &c);        // dtsph_cells.hip
+template <typename T> void launch_pre_records(Ctx &c);
+template <typename T> void launch_wall(Ctx &c, int mode);
+template <typename T> void launch_pass(Ctx &c, int mode);
+void launch_finalize(Ctx &c);
+template <typename T> void launch_loop_begin(Ctx &c, int fixed_iters);
+template <typename T> void launch_loop_end(Ctx &c);
+template <typename T> void launch_correct(Ctx &c);
+template <typename T> void launch_set_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
+template <typename T> void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
+
+// timing helpers (dtsph_api.hip)
+int timer_begin(Ctx &c);
+void timer_end(Ctx &c, int slot, int kind);
+
+#define DTSPH_HIP_CHECK(expr)                                                              \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) throw HipError(e_, #expr, __FILE__, __LINE__);               \
+    } while (0)
+
+struct HipError {
+    hipError_t code;
+    std::string what;
+    HipError(hipError_t c, const char *expr, const char *file, int line)
+        : code(c), what(std::string(hipGetErrorString(c)) + " in " + expr + " at " + file + ":" +
+                        std::to_string(line)) {}
+};
+
+struct ApiError {
+    int status;
+    std::string what;
+    ApiError(int s, std::string w) : status(s), what(std::move(w)) {}
+};
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace dtsph

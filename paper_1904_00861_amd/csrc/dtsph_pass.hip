@@ -1,0 +1,793 @@
+// Pair passes of the frozen-particle dual-time EDAC SPH step.
+//
+// k_pass (the hot kernel) evaluates, for every fluid particle i over its exact
+// neighbour list (paper section 3.2):
+//   D_i = sum_j (m rho_i/rho_j) c^2 V_ij . gradW_ij
+//       + sum_j 4 m/(rho_i+rho_j) nu_e p_ij gradW_ij . r_ij / (r^2 + reg_e)
+//                                                      (eq. dp-dtau-frozen-edac)
+//   R_i = -sum_j m (p_i/rho^2 + p_j/rho^2 + Pi_ij) gradW_ij
+//       + sum_j m 4 nu gradW_ij . r_ij / ((rho_i+rho_j)(r^2 + eta h^2)) V_ij + g
+//                                                      (eq. mom-sph-frozen,
+//                                                       eq. mom-av, eq. av-phiij)
+// With the quintic spline, dW/dr = kg * poly(q), poly = (3-q)^4 - 6(2-q)^4 +
+// 15(1-q)^4 (terms clipped at zero), kg = -5 sigma / h, so per pair
+//   gradW = kg * G * r_vec with G = poly / r,
+//   gradW . r / (r^2 + reg) = kg * poly * r / (r^2 + reg),
+// and all constant factors move out of the sums. The density is uniform.
+//
+// MODE_PSEUDO fuses the pseudo-time update (eqs. pkstar_frozen, vkp1_frozen,
+// pkp1_frozen with the frozen eq. dv_dtau_exact) and the per-block float64
+// residual partials of eq. conv. MODE_PRE is the rate pass before the loop
+// fused with the predictor (eq. v0, eq. r0).
+//
+// Work distribution: one thread per fluid particle; a workgroup is a "tile" of
+// consecutive cell-ordered slots of one sim (tiles never straddle sims, so each
+// sim's residual is a fixed-order sum of its own partials and a batch member
+// computes bit-for-bit what it computes alone). Consecutive tiles are mapped to
+// the same XCD so that neighbouring tiles share that XCD's L2.
+#include "dtsph_internal.h"
+
+namespace dtsph {
+
+namespace {
+
+template <typename T> struct V4;
+template <> struct V4<float> { using type = float4; };
+template <> struct V4<double> { using type = double4; };
+
+template <typename T> __device__ inline T rsq(T x);
+template <> __device__ inline float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ inline double rsq<double>(double x) { return 1.0 / sqrt(x); }
+template <typename T> __device__ inline T rcp(T x);
+template <> __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
+
+// component access of the {V, p} record: 2D {vx, vy, p, -}, 3D {vx, vy, vz, p}
+template <typename Q> __device__ inline auto comp(const Q &v, int k) { return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w; }
+
+template <int DIM, typename Q> __device__ inline auto pres(const Q &v) { return DIM == 2 ? v.z : v.w; }
+
+template <typename T, int DIM> __device__ inline typename V4<T>::type make_rec(const T v[3], T p)
+{
+    typename V4<T>::type r;
+    r.x = v[0];
+    r.y = v[1];
+    if (DIM == 2) { r.z = p; r.w = T(0); }
+    else { r.z = v[2]; r.w = p; }
+    return r;
+}
+
+// Position records and separations r_i - r_j.
+template <typename T, int DIM> struct Pos;
+
+template <int DIM> struct Pos<float, DIM> {
+    using Rec = uint4;
+    float step[3];
+    __device__ explicit Pos(const SimDev &S)
+    {
+        for (int a = 0; a < 3; ++a) step[a] = (float)(S.q_len[a] * 0x1p-32);
+    }
+    __device__ inline void delta(const Rec &a, const Rec &b, float r[3]) const
+    {
+        r[0] = (float)(int)(a.x - b.x) * step[0];
+        r[1] = (float)(int)(a.y - b.y) * step[1];
+        r[2] = DIM == 3 ? (float)(int)(a.z - b.z) * step[2] : 0.0f;
+    }
+};
+
+template <int DIM> struct Pos<double, DIM> {
+    using Rec = double4;
+    double L[3], halfL[3];
+    int per[3];
+    __device__ explicit Pos(const SimDev &S)
+    {
+        for (int a = 0; a < 3; ++a) { L[a] = S.L[a]; halfL[a] = S.halfL[a]; per[a] = S.periodic[a]; }
+    }
+    __device__ inline double mi(double s, int a) const
+    {
+        if (per[a]) {
+            if (s > halfL[a]) s -= L[a];
+            else if (s < -halfL[a]) s += L[a];
+        }
+        return s;
+    }
+    __device__ inline void delta(const Rec &a, const Rec &b, double r[3]) const
+    {
+        r[0] = mi(a.x - b.x, 0);
+        r[1] = mi(a.y - b.y, 1);
+        r[2] = DIM == 3 ? mi(a.z - b.z, 2) : 0.0;
+    }
+};
+
+template <typename T> struct PassConst {
+    T inv_h, tiny, den_v, den_e, den_a, k_av;
+    __device__ explicit PassConst(const SimDev &S)
+        : inv_h((T)S.inv_h), tiny((T)S.tiny_r2), den_v((T)S.den_v), den_e((T)S.den_e),
+          den_a((T)S.den_a), k_av((T)S.k_av) {}
+};
+
+template <typename T> struct Acc {
+    T div = 0, lap = 0, grad[3] = {0, 0, 0}, vis[3] = {0, 0, 0};
+};
+
+// One neighbour's contribution. vd: V_ij for the divergence term; vv: V_ij for
+// the viscous and artificial-viscosity terms (they differ only for walls).
+template <typename T, int DIM, bool AV, bool SEPDEN>
+__device__ __forceinline__ void pair_terms(const PassConst<T> &K, const T r[3], const T vd[3], const T vv[3],
+                                           T pi, T pj, Acc<T> &acc)
+{
+    T r2 = r[0] * r[0] + r[1] * r[1];
+    if (DIM == 3) r2 += r[2] * r[2];
+    const T r2s = r2 > K.tiny ? r2 : K.tiny;
+    const T rinv = rsq<T>(r2s);
+    const T rr = r2s * rinv;
+    const T q = rr * K.inv_h;
+    T t3 = T(3) - q, t2 = T(2) - q, t1 = T(1) - q;
+    t3 = t3 > T(0) ? t3 : T(0);
+    t2 = t2 > T(0) ? t2 : T(0);
+    t1 = t1 > T(0) ? t1 : T(0);
+    T a = t3 * t3, b = t2 * t2, c = t1 * t1;
+    a *= a;
+    b *= b;
+    c *= c;
+    const T poly = T(15) * c + (T(-6) * b + a);
+    const T G = poly * rinv;
+    const T rden = rcp<T>(r2 + K.den_v);
+    const T pr = poly * rr;
+    const T Fv = pr * rden;
+    const T Fe = SEPDEN ? pr * rcp<T>(r2 + K.den_e) : Fv;
+    T dotd = vd[0] * r[0] + vd[1] * r[1];
+    if (DIM == 3) dotd += vd[2] * r[2];
+    acc.div += G * dotd;
+    acc.lap += Fe * (pi - pj);
+    T P = pi + pj;
+    if (AV) {
+        T dotv = vv[0] * r[0] + vv[1] * r[1];
+        if (DIM == 3) dotv += vv[2] * r[2];
+        const T phi = dotv * (SEPDEN ? rcp<T>(r2 + K.den_a) : rden);
+        P += K.k_av * (phi < T(0) ? phi : T(0));
+    }
+    const T PG = P * G;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        acc.vis[d] += Fv * vv[d];
+        acc.grad[d] += PG * r[d];
+    }
+}
+
+__device__ inline int tile_of_block(int n_tiles, int remap)
+{
+    const int b = blockIdx.x;
+    if (!remap) return b < n_tiles ? b : -1;
+    const int per = (n_tiles + 7) >> 3;
+    const int t = (b & 7) * per + (b >> 3);
+    return t < n_tiles ? t : -1;
+}
+
+template <typename T> struct PassArgs {
+    using Q = typename V4<T>::type;
+    int N, Nf, Nw, n_tiles, remap;
+    const int2 *tiles;
+    const SimDev *sims;
+    const SimIter *iters;
+    const int *nbr;
+    const uint32_t *cnt;
+    const void *prec;
+    const Q *vin;
+    Q *vout;
+    const T *vwall;
+    const T *vn, *dv;
+    T *w, *dp;
+    double *pm, *pn;
+    const double *x;
+    double *x_alt, *xn;
+    double4 *partials;
+};
+
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE>
+__global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
+{
+    using Q = typename V4<T>::type;
+    using PosT = Pos<T, DIM>;
+    using Rec = typename PosT::Rec;
+    const int t = tile_of_block(A.n_tiles, A.remap);
+    if (t < 0) return;
+    const int2 tl = A.tiles[t];
+    const int s = tl.x;
+    const SimDev &S = A.sims[s];
+    const int i = tl.y + (int)threadIdx.x;
+    const bool active = i < S.fluid_begin + S.nf;
+    const int N = A.N, Nf = A.Nf;
+
+    if (MODE == MODE_PSEUDO && A.iters[s].done) {  // uniform per block
+        if (active) A.vout[i] = A.vin[i];
+        if (threadIdx.x == 0) A.partials[t] = make_double4(0.0, 0.0, 0.0, 0.0);
+        return;
+    }
+
+    const PassConst<T> K(S);
+    const PosT pos(S);
+    const Rec *__restrict__ prec = (const Rec *)A.prec;
+    const Q *__restrict__ vin = A.vin;
+
+    Acc<T> acc;
+    T Dv = 0, R[3] = {0, 0, 0}, vt2 = 0;
+    if (active) {
+        const Rec ri = prec[i];
+        const Q me = vin[i];
+        const T vi[3] = {me.x, me.y, DIM == 3 ? me.z : T(0)};
+        const T pi = pres<DIM>(me);
+        const uint32_t cn = A.cnt[i];
+        const int nfl = (int)(cn & 0xffffu), nwl = (int)(cn >> 16);
+        const int *__restrict__ nb = A.nbr + i;
+        for (int k = 0; k < nfl; ++k) {
+            const int j = nb[(size_t)k * N];
+            const Rec rj = prec[j];
+            const Q vj = vin[j];
+            T r[3], vd[3];
+            pos.delta(ri, rj, r);
+            vd[0] = vi[0] - vj.x;
+            vd[1] = vi[1] - vj.y;
+            vd[2] = DIM == 3 ? vi[2] - vj.z : T(0);
+            pair_terms<T, DIM, AV, SEPDEN>(K, r, vd, vd, pi, pres<DIM>(vj), acc);
+        }
+        if (WALLS) {
+            for (int k = nfl; k < nfl + nwl; ++k) {
+                const int j = nb[(size_t)k * N];
+                const Rec rj = prec[j];
+                const Q gj = vin[j];  // ghost velocity and wall pressure
+                const int jw = j - Nf;
+                T r[3], vd[3], vv[3];
+                pos.delta(ri, rj, r);
+                for (int d = 0; d < 3; ++d) vd[d] = d < DIM ? vi[d] - A.vwall[d * A.Nw + jw] : T(0);
+                vv[0] = vi[0] - gj.x;
+                vv[1] = vi[1] - gj.y;
+                vv[2] = DIM == 3 ? vi[2] - gj.z : T(0);
+                pair_terms<T, DIM, AV, SEPDEN>(K, r, vd, vv, pi, pres<DIM>(gj), acc);
+            }
+        }
+        Dv = (T)S.k_div * acc.div + (T)S.k_lap * acc.lap;
+        for (int d = 0; d < DIM; ++d) R[d] = (T)S.k_grad * acc.grad[d] + (T)S.k_visc * acc.vis[d] + (T)S.g[d];
+
+        if (MODE == MODE_PSEUDO) {
+            const T inv2dt = (T)S.inv2dt, gamma = (T)S.gamma, dtau = (T)S.dtau, dt = (T)S.dt;
+            T vnew[3] = {0, 0, 0};
+            for (int d = 0; d < DIM; ++d) {
+                const T wk = A.w[d * Nf + i];
+                const T bdf = (T(3) * wk - A.dv[d * Nf + i]) * inv2dt;
+                const T dvdtau = (R[d] - bdf) * gamma;
+                const T wn = wk + dtau * dvdtau;
+                const T vt = dt * dvdtau;
+                vt2 += vt * vt;
+                A.w[d * Nf + i] = wn;
+                vnew[d] = A.vn[d * Nf + i] + wn;
+            }
+            const double pm = A.pm[i] + S.dtau * (double)Dv;
+            A.pm[i] = pm;
+            A.dp[i] = Dv;
+            A.vout[i] = make_rec<T, DIM>(vnew, (T)pm);
+        } else {
+            const double dt = S.dt, hdt2 = 0.5 * S.dt * S.dt;
+            for (int d = 0; d < DIM; ++d) {
+                const double xv = A.x[d * N + i];
+                const double vv = (double)A.vn[d * Nf + i];
+                double x0 = (xv + dt * vv) + hdt2 * (double)R[d];
+                if (S.periodic[d]) {
+                    if (x0 >= S.hi[d]) x0 -= S.L[d];
+                    else if (x0 < S.lo[d]) x0 += S.L[d];
+                }
+                A.x_alt[d * N + i] = x0;
+                A.xn[d * N + i] = xv;
+                A.w[d * Nf + i] = (T)(dt * (double)R[d]);
+            }
+            if (DIM == 2) { A.x_alt[2 * N + i] = 0.0; A.xn[2 * N + i] = 0.0; }
+            A.dp[i] = Dv;
+            A.pn[i] = A.pm[i];
+        }
+    }
+
+    if (MODE == MODE_PSEUDO) {
+        // fixed-order block reduction of {sum |D|, sum |Vtilde|, max |D|, max |Vtilde|}
+        __shared__ double lds[kMaxBlock / 64][4];
+        double sd = active ? fabs((double)Dv) : 0.0;
+        double sv = active ? sqrt((double)vt2) : 0.0;
+        double md = sd, mv = sv;
+        for (int o = 32; o > 0; o >>= 1) {
+            sd += __shfl_xor(sd, o, 64);
+            sv += __shfl_xor(sv, o, 64);
+            md = fmax(md, __shfl_xor(md, o, 64));
+            mv = fmax(mv, __shfl_xor(mv, o, 64));
+        }
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (lane == 0) { lds[wave][0] = sd; lds[wave][1] = sv; lds[wave][2] = md; lds[wave][3] = mv; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) {
+                a0 += lds[wv][0];
+                a1 += lds[wv][1];
+                a2 = fmax(a2, lds[wv][2]);
+                a3 = fmax(a3, lds[wv][3]);
+            }
+            A.partials[t] = make_double4(a0, a1, a2, a3);
+        }
+    }
+}
+
+// ---- wall pass (Adami et al. 2012, pressure clipped at zero) -----------------
+template <typename T> struct WallArgs {
+    using Q = typename V4<T>::type;
+    int N, Nf, Nw, mode;
+    const int *simid;
+    const SimDev *sims;
+    const SimIter *iters;
+    const int *nbr;
+    const uint32_t *cnt;
+    const void *prec;
+    Q *vin;          // reads fluid records, writes wall records
+    const T *vwall;
+    T *pwall;
+    const double *x;
+    double *x_alt;   // MODE_PRE: walls keep their position
+};
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
+{
+    using Q = typename V4<T>::type;
+    using PosT = Pos<T, DIM>;
+    using Rec = typename PosT::Rec;
+    const int iw = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iw >= A.Nw) return;
+    const int i = A.Nf + iw;
+    const int N = A.N;
+    const int s = A.simid[i];
+    const SimDev &S = A.sims[s];
+    if (A.mode == MODE_PRE) {
+        for (int d = 0; d < 3; ++d) A.x_alt[d * N + i] = A.x[d * N + i];
+    } else if (A.iters[s].done) {
+        return;
+    }
+    const PosT pos(S);
+    const Rec *__restrict__ prec = (const Rec *)A.prec;
+    const Rec ri = prec[i];
+    const T inv_h = (T)S.inv_h, rho = (T)S.rho0;
+    const uint32_t cn = A.cnt[i];
+    const int nfl = (int)(cn & 0xffffu);
+    const int *__restrict__ nb = A.nbr + i;
+    T S0 = 0, Sp = 0, Srr[3] = {0, 0, 0}, Sv[3] = {0, 0, 0};
+    for (int k = 0; k < nfl; ++k) {
+        const int j = nb[(size_t)k * N];
+        const Rec rj = prec[j];
+        const Q vj = A.vin[j];
+        T r[3];
+        pos.delta(ri, rj, r);
+        T r2 = r[0] * r[0] + r[1] * r[1];
+        if (DIM == 3) r2 += r[2] * r[2];
+        const T q = sqrt(r2) * inv_h;
+        T t3 = T(3) - q, t2 = T(2) - q, t1 = T(1) - q;
+        t3 = t3 > T(0) ? t3 : T(0);
+        t2 = t2 > T(0) ? t2 : T(0);
+        t1 = t1 > T(0) ? t1 : T(0);
+        const T a5 = t3 * t3 * t3 * t3 * t3, b5 = t2 * t2 * t2 * t2 * t2, c5 = t1 * t1 * t1 * t1 * t1;
+        const T W = T(15) * c5 + (T(-6) * b5 + a5);  // sigma cancels in the ratios
+        S0 += W;
+        Sp += pres<DIM>(vj) * W;
+        for (int d = 0; d < DIM; ++d) {
+            Srr[d] += rho * r[d] * W;
+            Sv[d] += comp(vj, d) * W;
+        }
+    }
+    T vw[3] = {0, 0, 0}, ghost[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) vw[d] = A.vwall[d * A.Nw + iw];
+    T pw = 0;
+    if (S0 > T(0)) {
+        T gr = 0;
+        for (int d = 0; d < DIM; ++d) gr += (T)S.g[d] * Srr[d];
+        const T pv = (Sp + gr) / S0;
+        pw = pv > T(0) ? pv : T(0);
+        for (int d = 0; d < DIM; ++d) ghost[d] = T(2) * vw[d] - Sv[d] / S0;
+    } else {
+        for (int d = 0; d < DIM; ++d) ghost[d] = vw[d];
+    }
+    A.vin[i] = make_rec<T, DIM>(ghost, pw);
+    A.pwall[iw] = pw;
+}
+
+// ---- residual reduction and stop test (section 3.4) --------------------------
+__global__ void k_finalize(const SimDev *__restrict__ sims, SimIter *__restrict__ iters,
+                           const double4 *__restrict__ partials, int *__restrict__ done_out)
+{
+    const int s = blockIdx.x;
+    const int lane = threadIdx.x;
+    SimIter &It = iters[s];
+    if (It.done) {
+        if (lane == 0) done_out[s] = 1;
+        return;
+    }
+    const SimDev &S = sims[s];
+    double sd = 0, sv = 0, md = 0, mv = 0;
+    for (int t = S.tile_begin + lane; t < S.tile_end; t += 64) {
+        const double4 p = partials[t];
+        sd += p.x;
+        sv += p.y;
+        md = fmax(md, p.z);
+        mv = fmax(mv, p.w);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sd += __shfl_xor(sd, o, 64);
+        sv += __shfl_xor(sv, o, 64);
+        md = fmax(md, __shfl_xor(md, o, 64));
+        mv = fmax(mv, __shfl_xor(mv, o, 64));
+    }
+    if (lane != 0) return;
+    const double pscale = S.dt / (S.rho0 * S.c * S.c);
+    const double rp = sd * S.res_p, rv = sv * S.res_v;
+    const double rpx = md * pscale, rvx = mv / S.vref;
+    const int k = It.iters;
+    const int slot = k % kHist;
+    It.hp[slot] = S.conv_norm == 1 ? rpx : rp;
+    It.hv[slot] = S.conv_norm == 1 ? rvx : rv;
+    It.rp_mean = rp;
+    It.rv_mean = rv;
+    It.rp_max = rpx;
+    It.rv_max = rvx;
+    const int count = k + 1;
+    It.iters = count;
+    const double xp = It.hp[slot], xv = It.hv[slot];
+    int reason = 0;
+    if (!isfinite(xp) || !isfinite(xv)) {
+        reason = DTSPH_NONFINITE;
+    } else if (It.fixed > 0) {
+        reason = count >= It.fixed ? DTSPH_FIXED : 0;
+    } else {
+        bool stalled[2] = {false, false};
+        const int W = S.stall_window;
+        if (W > 0 && count >= W) {
+            for (int ser = 0; ser < 2; ++ser) {
+                const double *h = ser ? It.hv : It.hp;
+                double mn = INFINITY, mx = -INFINITY;
+                for (int m = count - W; m < count; ++m) {
+                    const double v = h[m % kHist];
+                    mn = v < mn ? v : mn;
+                    mx = v > mx ? v : mx;
+                }
+                stalled[ser] = (mx - mn) < S.stall_rel * mx;
+            }
+        }
+        const bool bp = xp < S.tol, bv = xv < S.tol;
+        if ((bp || stalled[0]) && (bv || stalled[1])) reason = (bp && bv) ? DTSPH_CONVERGED : DTSPH_STALLED;
+        else if (count >= S.max_iter) reason = DTSPH_MAXITER;
+    }
+    if (reason) {
+        It.done = 1;
+        It.reason = reason;
+    }
+    done_out[s] = It.done;
+}
+
+// ---- per-particle kernels -------------------------------------------------------
+__global__ void k_iter_reset(SimIter *iters, int n_sims, int fixed)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sims) return;
+    SimIter z{};
+    z.fixed = fixed;
+    for (int k = 0; k < kHist; ++k) { z.hp[k] = 0.0; z.hv[k] = 0.0; }
+    iters[s] = z;
+}
+
+template <typename T, int DIM>
+__global__ void k_records(int Nf, const int *__restrict__ simid, const SimDev *__restrict__ sims,
+                          const T *__restrict__ vn, const T *__restrict__ w, double *__restrict__ pm,
+                          const T *__restrict__ dp, typename V4<T>::type *__restrict__ vout, int half_step)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nf) return;
+    double p = pm[i];
+    if (half_step) {  // p^{k+1/2} = p^k + dtau/2 (dp/dtau)^k
+        p += 0.5 * sims[simid[i]].dtau * (double)dp[i];
+        pm[i] = p;
+    }
+    T v[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) v[d] = vn[d * Nf + i] + (w ? w[d * Nf + i] : T(0));
+    vout[i] = make_rec<T, DIM>(v, (T)p);
+}
+
+template <typename T>
+__global__ void k_loop_end(int Nf, const int *__restrict__ simid, const SimDev *__restrict__ sims,
+                           double *__restrict__ pm, const T *__restrict__ dp)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nf) return;
+    pm[i] -= 0.5 * sims[simid[i]].dtau * (double)dp[i];
+}
+
+template <typename T>
+__global__ void k_correct(int N, int Nf, const int *__restrict__ simid, const SimDev *__restrict__ sims,
+                          double *__restrict__ x, const double *__restrict__ xn, T *__restrict__ vn,
+                          T *__restrict__ dv, T *__restrict__ w)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nf) return;
+    const SimDev &S = sims[simid[i]];
+    for (int d = 0; d < S.dim; ++d) {
+        const T v0 = vn[d * Nf + i];
+        const T v1 = v0 + w[d * Nf + i];
+        double xv = xn[d * N + i] + 0.5 * S.dt * ((double)v0 + (double)v1);
+        if (S.periodic[d]) {
+            if (xv >= S.hi[d]) xv -= S.L[d];
+            else if (xv < S.lo[d]) xv += S.L[d];
+        }
+        x[d * N + i] = xv;
+        dv[d * Nf + i] = v1 - v0;
+        vn[d * Nf + i] = v1;
+        w[d * Nf + i] = T(0);
+    }
+}
+
+template <typename T>
+struct StateArgs {
+    int N, Nf, Nw, in_loop;
+    const int *init_slot, *init_sim;
+    int *orig, *simid;
+    double *x, *xn;
+    T *vn, *dv, *w, *dp, *vw, *pw;
+    double *pm, *pn;
+    double *cx, *cv, *cvp, *cp, *cxi, *cvi, *cpi, *cdp;  // caller arrays
+};
+
+template <typename T>
+__global__ void k_set_state(StateArgs<T> A)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= A.N) return;
+    const int N = A.N, Nf = A.Nf, Nw = A.Nw;
+    const int i = A.init_slot[c];
+    A.orig[i] = c;
+    A.simid[i] = A.init_sim[c];
+    const bool lp = A.in_loop != 0;
+    for (int d = 0; d < 3; ++d) {
+        A.x[d * N + i] = lp ? A.cxi[3 * c + d] : A.cx[3 * c + d];
+        A.xn[d * N + i] = A.cx[3 * c + d];
+    }
+    if (i < Nf) {
+        for (int d = 0; d < 3; ++d) {
+            const double v = A.cv[3 * c + d];
+            A.vn[d * Nf + i] = (T)v;
+            A.dv[d * Nf + i] = (T)(v - A.cvp[3 * c + d]);
+            A.w[d * Nf + i] = lp ? (T)(A.cvi[3 * c + d] - v) : T(0);
+        }
+        A.pn[i] = A.cp[c];
+        A.pm[i] = lp ? A.cpi[c] : A.cp[c];
+        A.dp[i] = lp ? (T)A.cdp[c] : T(0);
+    } else {
+        const int iw = i - Nf;
+        for (int d = 0; d < 3; ++d) A.vw[d * Nw + iw] = (T)A.cv[3 * c + d];
+        A.pw[iw] = T(0);
+    }
+}
+
+template <typename T>
+__global__ void k_get_state(StateArgs<T> A)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.N) return;
+    const int N = A.N, Nf = A.Nf, Nw = A.Nw;
+    const int c = A.orig[i];
+    const bool lp = A.in_loop != 0;
+    for (int d = 0; d < 3; ++d) {
+        const double xa = A.x[d * N + i];
+        if (A.cx) A.cx[3 * c + d] = (lp && i < Nf) ? A.xn[d * N + i] : xa;
+        if (A.cxi) A.cxi[3 * c + d] = xa;
+    }
+    if (i < Nf) {
+        for (int d = 0; d < 3; ++d) {
+            const T vn = A.vn[d * Nf + i];
+            if (A.cv) A.cv[3 * c + d] = (double)vn;
+            if (A.cvp) A.cvp[3 * c + d] = (double)(vn - A.dv[d * Nf + i]);
+            if (A.cvi) A.cvi[3 * c + d] = (double)(vn + A.w[d * Nf + i]);
+        }
+        if (A.cp) A.cp[c] = lp ? A.pn[i] : A.pm[i];
+        if (A.cpi) A.cpi[c] = A.pm[i];
+        if (A.cdp) A.cdp[c] = (double)A.dp[i];
+    } else {
+        const int iw = i - Nf;
+        for (int d = 0; d < 3; ++d) {
+            const double v = (double)A.vw[d * Nw + iw];
+            if (A.cv) A.cv[3 * c + d] = v;
+            if (A.cvp) A.cvp[3 * c + d] = 0.0;
+            if (A.cvi) A.cvi[3 * c + d] = v;
+        }
+        if (A.cp) A.cp[c] = (double)A.pw[iw];
+        if (A.cpi) A.cpi[c] = (double)A.pw[iw];
+        if (A.cdp) A.cdp[c] = 0.0;
+    }
+}
+
+inline int grid_for(int n, int b = 256) { return n > 0 ? ceil_div(n, b) : 1; }
+
+template <typename T> PassArgs<T> pass_args(Ctx &c)
+{
+    using Q = typename V4<T>::type;
+    const int b = c.buf;
+    PassArgs<T> a;
+    a.N = c.N; a.Nf = c.Nf; a.Nw = c.Nw; a.n_tiles = c.n_tiles; a.remap = c.xcd_remap;
+    a.tiles = c.tiles; a.sims = c.sims; a.iters = c.iters; a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec;
+    a.vin = (const Q *)c.vp[c.cur];
+    a.vout = (Q *)c.vp[c.cur ^ 1];
+    a.vwall = (const T *)c.vw[b];
+    a.vn = (const T *)c.vn[b]; a.dv = (const T *)c.dv[b];
+    a.w = (T *)c.w[b]; a.dp = (T *)c.dp[b];
+    a.pm = c.pm[b]; a.pn = c.pn[b];
+    a.x = c.x[c.xb]; a.x_alt = c.x[c.xb ^ 1]; a.xn = c.xn[b];
+    a.partials = c.partials;
+    return a;
+}
+
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN>
+void dispatch_mode(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
+{
+    if (mode == MODE_PRE)
+        hipLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PRE>), grid, dim3(c.block), 0, c.stream, a);
+    else
+        hipLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO>), grid, dim3(c.block), 0, c.stream, a);
+}
+
+template <typename T, int DIM, bool WALLS, bool AV>
+void dispatch_sep(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
+{
+    if (c.sep_den) dispatch_mode<T, DIM, WALLS, AV, true>(c, mode, a, grid);
+    else dispatch_mode<T, DIM, WALLS, AV, false>(c, mode, a, grid);
+}
+
+template <typename T, int DIM, bool WALLS>
+void dispatch_av(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
+{
+    if (c.any_av) dispatch_sep<T, DIM, WALLS, true>(c, mode, a, grid);
+    else dispatch_sep<T, DIM, WALLS, false>(c, mode, a, grid);
+}
+
+template <typename T, int DIM>
+void dispatch_walls(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
+{
+    if (c.any_walls) dispatch_av<T, DIM, true>(c, mode, a, grid);
+    else dispatch_av<T, DIM, false>(c, mode, a, grid);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_pass(Ctx &c, int mode)
+{
+    PassArgs<T> a = pass_args<T>(c);
+    const int grid = c.xcd_remap ? 8 * ((c.n_tiles + 7) / 8) : c.n_tiles;
+    int t0 = mode == MODE_PSEUDO ? timer_begin(c) : -1;
+    if (c.max_dim == 2) dispatch_walls<T, 2>(c, mode, a, dim3(grid));
+    else dispatch_walls<T, 3>(c, mode, a, dim3(grid));
+    DTSPH_HIP_CHECK(hipGetLastError());
+    if (mode == MODE_PSEUDO) {
+        timer_end(c, t0, 0);
+        c.cur ^= 1;
+    }
+}
+
+template <typename T>
+void launch_wall(Ctx &c, int mode)
+{
+    if (c.Nw == 0) return;
+    using Q = typename V4<T>::type;
+    const int b = c.buf;
+    WallArgs<T> a;
+    a.N = c.N; a.Nf = c.Nf; a.Nw = c.Nw; a.mode = mode;
+    a.simid = c.simid[b]; a.sims = c.sims; a.iters = c.iters; a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec;
+    a.vin = (Q *)c.vp[c.cur];
+    a.vwall = (const T *)c.vw[b];
+    a.pwall = (T *)c.pw[b];
+    a.x = c.x[c.xb]; a.x_alt = c.x[c.xb ^ 1];
+    int t0 = mode == MODE_PSEUDO ? timer_begin(c) : -1;
+    if (c.max_dim == 2) hipLaunchKernelGGL((k_wall<T, 2>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_wall<T, 3>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
+    DTSPH_HIP_CHECK(hipGetLastError());
+    if (mode == MODE_PSEUDO) timer_end(c, t0, 1);
+}
+
+void launch_finalize(Ctx &c)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(c.n_sims), dim3(64), 0, c.stream, c.sims, c.iters, c.partials, c.done_dev);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_pre_records(Ctx &c)
+{
+    using Q = typename V4<T>::type;
+    const int b = c.buf;
+    if (c.max_dim == 2)
+        hipLaunchKernelGGL((k_records<T, 2>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
+                           (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0);
+    else
+        hipLaunchKernelGGL((k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
+                           (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_loop_begin(Ctx &c, int fixed_iters)
+{
+    using Q = typename V4<T>::type;
+    const int b = c.buf;
+    hipLaunchKernelGGL(k_iter_reset, dim3(grid_for(c.n_sims)), dim3(256), 0, c.stream, c.iters, c.n_sims, fixed_iters);
+    if (c.max_dim == 2)
+        hipLaunchKernelGGL((k_records<T, 2>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
+                           (const T *)c.vn[b], (const T *)c.w[b], c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 1);
+    else
+        hipLaunchKernelGGL((k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
+                           (const T *)c.vn[b], (const T *)c.w[b], c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 1);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_loop_end(Ctx &c)
+{
+    const int b = c.buf;
+    hipLaunchKernelGGL(k_loop_end<T>, dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims, c.pm[b],
+                       (const T *)c.dp[b]);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_correct(Ctx &c)
+{
+    const int b = c.buf;
+    hipLaunchKernelGGL(k_correct<T>, dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.N, c.Nf, c.simid[b], c.sims,
+                       c.x[c.xb], c.xn[b], (T *)c.vn[b], (T *)c.dv[b], (T *)c.w[b]);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+static StateArgs<T> state_args(Ctx &c, const dtsph_state_view &s, bool in_loop)
+{
+    const int b = c.buf;
+    StateArgs<T> a;
+    a.N = c.N; a.Nf = c.Nf; a.Nw = c.Nw; a.in_loop = in_loop ? 1 : 0;
+    a.init_slot = c.init_slot; a.init_sim = c.init_slot + c.N;
+    a.orig = c.orig[b]; a.simid = c.simid[b];
+    a.x = c.x[c.xb]; a.xn = c.xn[b];
+    a.vn = (T *)c.vn[b]; a.dv = (T *)c.dv[b]; a.w = (T *)c.w[b]; a.dp = (T *)c.dp[b];
+    a.vw = (T *)c.vw[b]; a.pw = (T *)c.pw[b];
+    a.pm = c.pm[b]; a.pn = c.pn[b];
+    a.cx = s.x; a.cv = s.v; a.cvp = s.v_prev; a.cp = s.p;
+    a.cxi = s.x_iter; a.cvi = s.v_iter; a.cpi = s.p_iter; a.cdp = s.dpdtau;
+    return a;
+}
+
+template <typename T>
+void launch_set_state(Ctx &c, const dtsph_state_view &s, bool in_loop)
+{
+    StateArgs<T> a = state_args<T>(c, s, in_loop);
+    hipLaunchKernelGGL(k_set_state<T>, dim3(grid_for(c.N)), dim3(256), 0, c.stream, a);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop)
+{
+    StateArgs<T> a = state_args<T>(c, s, in_loop);
+    hipLaunchKernelGGL(k_get_state<T>, dim3(grid_for(c.N)), dim3(256), 0, c.stream, a);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+#define DTSPH_INSTANTIATE(T)                                                   \
+    template void launch_pass<T>(Ctx &, int);                                  \
+    template void launch_wall<T>(Ctx &, int);                                  \
+    template void launch_pre_records<T>(Ctx &);                                \
+    template void launch_loop_begin<T>(Ctx &, int);                            \
+    template void launch_loop_end<T>(Ctx &);                                   \
+    template void launch_correct<T>(Ctx &);                                    \
+    template void launch_set_state<T>(Ctx &, const dtsph_state_view &, bool);  \
+    template void launch_get_state<T>(Ctx &, const dtsph_state_view &, bool);
+DTSPH_INSTANTIATE(float)
+DTSPH_INSTANTIATE(double)
+
+}  // namespace dtsph

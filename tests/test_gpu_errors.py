@@ -1,0 +1,123 @@
+"""Error handling of the C-ABI on the GPU: invalid descriptions, call order,
+capacity overflow, non-finite state and the iteration cap. Every condition is
+forced from the host; no kernel faults or hangs."""
+import numpy as np
+import pytest
+
+from paper_1904_00861_amd import dtsph as D
+from paper_1904_00861_amd import inputs as I
+
+from gpu_helpers import banner
+
+pytestmark = pytest.mark.gpu
+
+
+def _create(prob, **over):
+    prm = dict(prob.params, **over)
+    return D.dtsph_create([prm], [prob.n_fluid], [prob.n_wall], D.FP32)
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(h=0.2), "half the period"),       # kappa h = 0.6 >= L/2 on a periodic axis
+    (dict(dim=1), "dim"),
+    (dict(dt=0.0), "dt"),
+    (dict(stall_window=9), "stall_window"),
+    (dict(max_iter=0), "max_iter"),
+    (dict(hi=(0.0, 1.0, 1.0)), "hi must exceed lo"),
+])
+def test_invalid_descriptions(over, msg):
+    banner(f"invalid {over}")
+    with pytest.raises(D.DtsphError) as e:
+        _create(I.tgv2d(10), **over)
+    assert e.value.status == D.EINVAL and msg in str(e.value)
+
+
+def test_invalid_counts_and_precision():
+    prob = I.tgv2d(10)
+    with pytest.raises(D.DtsphError) as e:
+        D.dtsph_create([prob.params], [0], [0], D.FP32)
+    assert e.value.status == D.EINVAL
+    with pytest.raises(D.DtsphError) as e:
+        D.dtsph_create([prob.params], [prob.n], [0], 7)
+    assert e.value.status == D.EINVAL
+    with pytest.raises(D.DtsphError) as e:
+        D.dtsph_create([prob.params, I.tgv3d(8).params], [prob.n, 512], [0, 0], D.FP32)
+    assert e.value.status == D.EINVAL
+
+
+def test_call_order():
+    banner("call order")
+    sim = D.Sim(I.tgv2d(12), precision=D.FP32)
+    with pytest.raises(D.DtsphError) as e:
+        sim.pseudo_iterate(1)
+    assert e.value.status == D.EINVAL
+    with pytest.raises(D.DtsphError):
+        sim.correct()
+    with pytest.raises(D.DtsphError):
+        sim.get_state(loop=True)
+    sim.predict()
+    with pytest.raises(D.DtsphError):
+        sim.predict()
+    with pytest.raises(D.DtsphError):
+        sim.step(1)
+    sim.pseudo_iterate(2)
+    sim.correct()
+    st, reps = sim.step(1)
+    assert st >= 0
+    with pytest.raises(D.DtsphError):
+        sim.set_option(D.OPT_BLOCK, 100)
+    sim.close()
+
+
+def test_neighbour_capacity_overflow():
+    banner("capacity overflow")
+    prob = I.tgv2d(16)
+    prob.params["max_neighbors"] = 8
+    sim = D.Sim(prob, precision=D.FP32)
+    with pytest.raises(D.DtsphError) as e:
+        sim.build_cells()
+    assert e.value.status == D.EOVERFLOW and "needs" in str(e.value)
+    sim.close()
+
+
+def test_nonfinite_pressure():
+    banner("non-finite")
+    prob = I.tgv2d(16)
+    prob.p[5] = np.nan
+    sim = D.Sim(prob, precision=D.FP64)
+    sim.predict()
+    with pytest.raises(D.DtsphError) as e:
+        sim.pseudo_iterate(0)
+    assert e.value.status == D.ENONFINITE
+    sim.close()
+
+
+def test_iteration_cap():
+    banner("max_iter")
+    prob = I.tgv2d(16)
+    prob.params.update(tol=0.0, stall_rel=0.0, max_iter=3)
+    sim = D.Sim(prob, precision=D.FP32)
+    st, reps = sim.step(2)
+    sim.close()
+    assert st == D.WARN_MAXITER
+    assert all(r[0]["iters"] == 3 and D.REASONS[r[0]["reason"]] == "max_iter" for r in reps)
+
+
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_block_and_xcd_options_do_not_change_results(block):
+    banner(f"block {block}")
+    prob = I.tgv2d(30, seed=5)
+    ref = D.Sim(prob, precision=D.FP32)
+    ref.step(2)
+    a = ref.get_state()
+    ref.close()
+    sim = D.Sim(prob, precision=D.FP32)
+    sim.set_option(D.OPT_BLOCK, block)
+    sim.set_option(D.OPT_XCD_REMAP, 0)
+    sim.set_option(D.OPT_CHUNK, 1)
+    sim.step(2)
+    b = sim.get_state()
+    sim.close()
+    # fields do not depend on the launch shape (residual sums may differ in the last bit)
+    for f in a:
+        assert np.array_equal(a[f], b[f])

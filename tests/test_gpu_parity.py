@@ -1,0 +1,277 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle.
+
+Bars (relative L2 over fluid particles unless noted; pressure rates are compared
+on the scale of their terms, see gpu_helpers.rate_floor):
+  neighbour lists      bit-exact (same sets, caller indices ascending)
+  FP64 path            one pass <= 1e-12; 20 fixed iterations <= 1e-11;
+                       several real steps <= 1e-10, positions <= 1e-12 absolute;
+                       iteration counts equal
+  FP32 path            one pass: V <= 1e-6, p <= 1e-5, dp/dtau <= 1e-4;
+                       20 fixed iterations: V <= 1e-5, p <= 1e-4;
+                       several real steps: V, p <= 1e-4, positions <= 1e-7 absolute;
+                       iteration counts within one of the oracle's
+The FP32 bars follow from float32 rounding (6e-8) of pair terms summed over
+~26 (2D) / ~110 (3D) neighbours; the pressure rate cancels (a divergence of a
+nearly solenoidal field) and carries the loosest bar.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1904_00861_amd import dtsph as D
+from paper_1904_00861_amd import inputs as I
+
+from gpu_helpers import banner, gpu_steps, oracle_steps, rate_floor, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+PREC = {"fp64": D.FP64, "fp32": D.FP32}
+TOL_PASS = {"fp64": dict(v=1e-12, p=1e-12, d=1e-12), "fp32": dict(v=1e-6, p=1e-5, d=1e-4)}
+TOL_K20 = {"fp64": dict(v=1e-11, p=1e-11), "fp32": dict(v=1e-5, p=1e-4)}
+TOL_STEPS = {"fp64": dict(v=1e-10, p=1e-10, x=1e-12), "fp32": dict(v=1e-4, p=1e-4, x=1e-7)}
+
+
+def _dam_outside():
+    prob = I.dam_break(0.05)
+    prob.x[0, :2] = [2.0, 4.3]      # above the grid box (clamped into the top row)
+    prob.x[1, :2] = [-0.31, 0.8]    # left of it
+    return prob
+
+
+def _perfect():
+    return I.tgv2d(20, jitter=0.0)
+
+
+CASES = {
+    "tgv2d_16_j03": lambda: I.tgv2d(16, seed=3, jitter=0.3),
+    "tgv2d_50": lambda: I.config("C0"),
+    "tgv2d_23_ragged": lambda: I.tgv2d(23, seed=8),
+    "tgv2d_perfect": _perfect,
+    "tgv3d_10": lambda: I.tgv3d(10, seed=2),
+    "cavity_16": lambda: I.cavity(16),
+    "dam_0.05": lambda: I.dam_break(0.05),
+    "dam_outside": _dam_outside,
+    "tank_10": lambda: I.hydrostatic_tank(10),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_neighbour_lists_bit_exact(case):
+    prob = CASES[case]()
+    banner(f"neighbours {case} n={prob.n}")
+    ob, ib = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, prob.x, "brute")
+    for prec in (D.FP64, D.FP32):
+        sim = D.Sim(prob, precision=prec)
+        off, idx = sim.neighbor_list()
+        sim.close()
+        assert np.array_equal(off, ob)
+        assert np.array_equal(idx, ib)
+
+
+@pytest.mark.parametrize("case", ["tgv2d_50", "cavity_16", "dam_outside", "tgv3d_10"])
+def test_cell_layout_is_a_stable_sort_by_cell(case):
+    prob = CASES[case]()
+    banner(f"cell layout {case}")
+    sim = D.Sim(prob, precision=D.FP32)
+    sim.build_cells()
+    keys, callers, starts = sim.cell_layout()
+    sim.close()
+    n, nf = prob.n, prob.n_fluid
+    assert np.array_equal(np.sort(callers), np.arange(n))            # a permutation
+    assert np.all(np.diff(keys) >= 0)                                 # sorted by key
+    same = np.diff(keys) == 0
+    assert np.all(np.diff(callers)[same] > 0)                          # ties in caller order
+    assert np.all(callers[:nf] < nf) and np.all(callers[nf:] >= nf)   # fluid keys first
+    # cell-start table agrees with the keys
+    counts = np.bincount(keys, minlength=starts.size - 1)
+    assert np.array_equal(np.diff(starts), counts)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["tgv2d_50", "tgv2d_23_ragged", "cavity_16", "dam_0.05", "tgv3d_10"])
+def test_predict_parity(case, prec):
+    prob = CASES[case]()
+    banner(f"predict {case} {prec}")
+    nf = prob.n_fluid
+    sim = D.Sim(prob, precision=PREC[prec])
+    sim.predict()
+    g = sim.get_state(loop=True)
+    sim.close()
+    pr = O.predict(prob.params, nf, prob.n_wall, prob.x, prob.v, prob.p)
+    t = TOL_PASS[prec]
+    assert rel_l2(g["v_iter"][:nf], pr["v_iter"][:nf]) <= t["v"]
+    assert rel_l2(g["dpdtau"][:nf], pr["dpdtau"][:nf], rate_floor(prob)) <= t["d"]
+    assert np.abs(g["x_iter"] - pr["x_iter"]).max() <= (1e-14 if prec == "fp64" else 1e-8)
+    assert np.array_equal(g["p_iter"][:nf], prob.p[:nf])
+    # the between-steps fields are untouched by the predictor
+    assert np.array_equal(g["x"], prob.x) and np.array_equal(g["p"][:nf], prob.p[:nf])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("k", [1, 20])
+@pytest.mark.parametrize("case", ["tgv2d_50", "tgv2d_23_ragged", "cavity_16", "dam_0.05", "tgv3d_10"])
+def test_pseudo_iterate_fixed_k(case, k, prec):
+    prob = CASES[case]()
+    banner(f"pseudo_iterate {case} K={k} {prec}")
+    nf = prob.n_fluid
+    ls = I.loop_state_from(prob)
+    sim = D.Sim(prob, precision=PREC[prec])
+    sim.set_state_from_problems(loop=ls)
+    st, reps = sim.pseudo_iterate(k)
+    g = sim.get_state(loop=True)
+    sim.close()
+    vk, pk, dk, rep = O.pseudo_loop(prob.params, nf, prob.n_wall, ls["x_iter"], prob.v, prob.v_prev,
+                                    ls["v_iter"], ls["p_iter"], ls["dpdtau"], fixed_iters=k)
+    t = TOL_PASS[prec] if k == 1 else TOL_K20[prec]
+    assert reps[0]["iters"] == k and D.REASONS[reps[0]["reason"]] == "fixed"
+    assert rel_l2(g["v_iter"][:nf], vk[:nf]) <= t["v"]
+    assert rel_l2(g["p_iter"][:nf], pk[:nf]) <= t["p"]
+    if k == 1:
+        assert rel_l2(g["dpdtau"][:nf], dk[:nf], rate_floor(prob)) <= t["d"]
+    # residuals of eq. conv agree
+    rtol = 1e-9 if prec == "fp64" else 1e-3
+    for key in ("rp_mean", "rv_mean", "rp_max", "rv_max"):
+        assert abs(reps[0][key] - rep[key]) <= rtol * abs(rep[key]) + 1e-300
+    assert reps[0]["pairs"] == rep["pairs"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case,steps", [("tgv2d_50", 10), ("cavity_16", 5), ("dam_0.05", 5),
+                                        ("tgv3d_10", 3), ("tgv2d_23_ragged", 4)])
+def test_real_steps_parity(case, steps, prec):
+    prob = CASES[case]()
+    banner(f"steps {case} x{steps} {prec}")
+    nf = prob.n_fluid
+    x, v, vp, p, oreps, ost = oracle_steps(prob, steps)
+    g, greps, st = gpu_steps(prob, steps, PREC[prec])
+    gi = [r[0]["iters"] for r in greps]
+    oi = [r["iters"] for r in oreps]
+    t = TOL_STEPS[prec]
+    if prec == "fp64":
+        assert gi == oi
+    else:
+        assert all(abs(a - b) <= 1 for a, b in zip(gi, oi))
+    loose = 1.0 if gi == oi else 20.0
+    assert rel_l2(g["v"][:nf], v[:nf]) <= t["v"] * loose
+    assert rel_l2(g["p"][:nf], p[:nf]) <= t["p"] * loose
+    assert rel_l2(g["v_prev"][:nf], vp[:nf]) <= t["v"] * loose
+    assert np.abs(g["x"] - x).max() <= t["x"] * loose
+    if prob.n_wall:
+        assert rel_l2(g["p"][nf:], p[nf:], 1e-30 + np.linalg.norm(p[:nf])) <= t["p"] * loose
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_free_running_iteration_counts(prec):
+    prob = I.cavity(16)
+    banner(f"free-running loop {prec}")
+    nf = prob.n_fluid
+    ls = I.loop_state_from(prob, amp_v=0.01)
+    sim = D.Sim(prob, precision=PREC[prec])
+    sim.set_state_from_problems(loop=ls)
+    st, reps = sim.pseudo_iterate(0)
+    sim.close()
+    vk, pk, dk, rep = O.pseudo_loop(prob.params, nf, prob.n_wall, ls["x_iter"], prob.v, prob.v_prev,
+                                    ls["v_iter"], ls["p_iter"], ls["dpdtau"])
+    if prec == "fp64":
+        assert reps[0]["iters"] == rep["iters"] and reps[0]["reason"] == rep["reason"]
+    else:
+        assert abs(reps[0]["iters"] - rep["iters"]) <= 1
+
+
+def _batch():
+    return [I.tgv2d(20, seed=11, name="a"), I.cavity(16, re=400.0, name="b"),
+            I.tgv2d(24, re=700.0, seed=12, name="c"), I.cavity(12, re=150.0, name="d")]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_members_match_solo_runs_bitwise(prec):
+    probs = _batch()
+    banner(f"batch vs solo {prec}")
+    sim = D.Sim(probs, precision=PREC[prec])
+    st, reps = sim.step(4)
+    g = sim.get_state()
+    sim.close()
+    for k, (prob, sl) in enumerate(zip(probs, _slices(probs))):
+        solo, sreps, sst = gpu_steps(prob, 4, PREC[prec])
+        for f in ("x", "v", "v_prev", "p"):
+            assert np.array_equal(g[f][sl], solo[f]), (prob.name, f)
+        assert [r[k]["iters"] for r in reps] == [r[0]["iters"] for r in sreps]
+        assert [r[k]["rp_mean"] for r in reps] == [r[0]["rp_mean"] for r in sreps]
+
+
+def _slices(probs):
+    out, o = [], 0
+    for p in probs:
+        out.append(slice(o, o + p.n))
+        o += p.n
+    return out
+
+
+def test_batch_members_match_oracle():
+    probs = _batch()
+    banner("batch vs oracle fp64")
+    sim = D.Sim(probs, precision=D.FP64)
+    st, reps = sim.step(3)
+    g = sim.get_state()
+    sim.close()
+    for k, (prob, sl) in enumerate(zip(probs, _slices(probs))):
+        x, v, vp, p, oreps, ost = oracle_steps(prob, 3)
+        nf = prob.n_fluid
+        assert [r[k]["iters"] for r in reps] == [r["iters"] for r in oreps]
+        assert rel_l2(g["v"][sl][:nf], v[:nf]) <= 1e-10
+        assert rel_l2(g["p"][sl][:nf], p[:nf]) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_isolated_particle_closed_form(prec):
+    # one fluid particle with no neighbours: V^k -> V* geometrically (ratio 20/23)
+    prob = I.tgv2d(10)
+    prm = dict(prob.params, periodic=(0, 0, 0), lo=(0, 0, 0), hi=(1, 1, 1), g=(0.0, -2.0, 0.0))
+    x = np.array([[0.5, 0.5, 0.0]])
+    vn = np.array([[0.3, -0.1, 0.0]])
+    vnm1 = np.array([[0.25, 0.05, 0.0]])
+    one = I.Problem("iso", prm, x, vn, vnm1, np.array([0.7]), 1, 0)
+    banner(f"isolated particle {prec}")
+    dt, beta = prm["dt"], prm["beta"]
+    ratio = 2 * dt / (2 * dt + 3 * dt / beta)
+    g_ = np.array(prm["g"])
+    vstar = (4 * vn - vnm1 + 2 * dt * g_) / 3
+    sim = D.Sim(one, precision=PREC[prec])
+    sim.predict()
+    v0 = sim.get_state(loop=True)["v_iter"]
+    assert np.allclose(v0, vn + dt * g_, rtol=0, atol=1e-15 if prec == "fp64" else 1e-7)
+    st, reps = sim.pseudo_iterate(7)
+    vk = sim.get_state(loop=True)["v_iter"]
+    sim.close()
+    expect = vstar + (v0 - vstar) * ratio ** 7
+    assert np.allclose(vk, expect, rtol=0, atol=1e-14 if prec == "fp64" else 1e-6)
+
+
+def test_runs_are_deterministic():
+    prob = I.tgv2d(40, seed=21)
+    banner("determinism")
+    a, ra, _ = gpu_steps(prob, 3, D.FP32)
+    b, rb, _ = gpu_steps(prob, 3, D.FP32)
+    for f in a:
+        assert np.array_equal(a[f], b[f])
+    assert ra == rb
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_checkpoint_restart(prec):
+    # a restart from get_state continues the run; FP64 to round-off of the
+    # V^{n-1} round trip, FP32 to float rounding
+    prob = I.cavity(16)
+    banner(f"checkpoint/restart {prec}")
+    full, _, _ = gpu_steps(prob, 5, PREC[prec])
+    sim = D.Sim(prob, precision=PREC[prec])
+    sim.step(3)
+    mid = sim.get_state()
+    sim.close()
+    p2 = prob.copy()
+    p2.x, p2.v, p2.v_prev, p2.p = mid["x"], mid["v"], mid["v_prev"], mid["p"]
+    end, _, _ = gpu_steps(p2, 2, PREC[prec])
+    nf = prob.n_fluid
+    tol = 1e-11 if prec == "fp64" else 1e-4
+    assert rel_l2(end["v"][:nf], full["v"][:nf]) <= tol
+    assert rel_l2(end["p"][:nf], full["p"][:nf]) <= tol
