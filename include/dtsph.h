@@ -58,13 +58,14 @@ extern "C" {
 #define DTSPH_ENONFINITE (-4)/* NaN/Inf in a residual; state undefined         */
 #define DTSPH_EOVERFLOW (-5) /* neighbour list capacity exceeded (raise
                                 max_neighbors) or a cell holds > 4096 particles;
-                                state before the failed build is kept          */
+                                particle state undefined, recreate the context */
 
 /* ---- precision of the pair sums ------------------------------------------
  * DTSPH_FP64: every quantity in float64 (the plain path).
  * DTSPH_FP32: pair sums, velocities and pressure rates in float32 on
- *   cell-frame fixed-point positions; positions, pressure, the pseudo-time
- *   pressure accumulation and the residual reductions stay float64.        */
+ *   32-bit fixed-point positions (exact periodic wrap-around); positions,
+ *   pressure, the pseudo-time pressure accumulation and the residual
+ *   reductions stay float64.                                               */
 #define DTSPH_FP64 0
 #define DTSPH_FP32 1
 
@@ -180,6 +181,8 @@ typedef struct dtsph_info {
     int32_t n_sims, precision;
     int32_t nbr_capacity;   /* neighbour list capacity per particle           */
     int32_t block;          /* pair-pass workgroup size                       */
+    int32_t lanes;          /* lanes per particle in the pair pass            */
+    int32_t reserved;
     int64_t device_bytes;   /* device memory owned by the context             */
 } dtsph_info;
 
@@ -268,6 +271,8 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
 #define DTSPH_OPT_CHUNK 3      /* iterations launched between stop checks (>=1) */
 #define DTSPH_OPT_BLOCK 4      /* pair-pass workgroup size: 64, 128 or 256    */
 #define DTSPH_OPT_XCD_REMAP 5  /* 1: map consecutive tiles to one XCD (default) */
+#define DTSPH_OPT_LANES 6      /* lanes per particle in the pair pass: 1, 2, 4, 8
+                                  (default: smallest giving >= 512k threads)  */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 int dtsph_get_timing(const dtsph_ctx *ctx, dtsph_timing *out);

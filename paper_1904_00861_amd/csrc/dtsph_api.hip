@@ -56,8 +56,9 @@ void free_all(Ctx &c)
 {
     for (void *p : c.allocs) (void)hipFree(p);
     c.allocs.clear();
-    if (c.done_host) (void)hipHostFree(c.flags_host);
-    c.done_host = c.flags_host = nullptr;
+    if (c.mirror_h) (void)hipHostFree(c.mirror_h);
+    c.mirror_h = nullptr;
+    c.flags_host = nullptr;
     for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
     c.ev_pool.clear();
 }
@@ -171,7 +172,8 @@ void setup_tiles(Ctx &c)
     std::vector<int2> tiles;
     for (int s = 0; s < c.n_sims; ++s) {
         c.sims_h[s].tile_begin = (int)tiles.size();
-        for (int off = 0; off < (int)c.nf[s]; off += c.block) tiles.push_back(make_int2(s, c.fluid_begin[s] + off));
+        const int per = c.block / c.lpp;  // particles per tile
+        for (int off = 0; off < (int)c.nf[s]; off += per) tiles.push_back(make_int2(s, c.fluid_begin[s] + off));
         c.sims_h[s].tile_end = (int)tiles.size();
     }
     c.n_tiles = (int)tiles.size();
@@ -227,8 +229,7 @@ void resolve_timers(Ctx &c)
 // ---- flags / sync -------------------------------------------------------------
 void readback_flags(Ctx &c)
 {
-    DTSPH_HIP_CHECK(hipMemcpyAsync(c.flags_host, c.flags, sizeof(int) * (F_COUNT + c.n_sims), hipMemcpyDeviceToHost,
-                                   c.stream));
+    launch_publish(c);
     DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
     if (c.timing) resolve_timers(c);
     if (c.flags_host[F_NBR_OVERFLOW])
@@ -287,27 +288,24 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
         chunk = c.chunk > 0 ? c.chunk : 2;
     }
     launch_loop_end<T>(c);
-    std::vector<SimIter> it(c.n_sims);
-    std::vector<unsigned long long> pairs(c.n_sims);
-    DTSPH_HIP_CHECK(hipMemcpyAsync(it.data(), c.iters, sizeof(SimIter) * c.n_sims, hipMemcpyDeviceToHost, c.stream));
-    DTSPH_HIP_CHECK(hipMemcpyAsync(pairs.data(), c.pairs, 8 * c.n_sims, hipMemcpyDeviceToHost, c.stream));
-    DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
     int status = DTSPH_OK, most = 1;
     for (int s = 0; s < c.n_sims; ++s) {
-        most = std::max(most, it[s].iters);
-        c.tstats.pass_pairs += (int64_t)pairs[s] * it[s].iters;
-        c.tstats.pass_particles += c.nf[s] * it[s].iters;
+        const MirrorRep &it = c.reps_host[s];
+        const int64_t pairs = (int64_t)c.pairs_host[s];
+        most = std::max(most, it.iters);
+        c.tstats.pass_pairs += pairs * it.iters;
+        c.tstats.pass_particles += c.nf[s] * it.iters;
         if (rep) {
-            rep[s].iters = it[s].iters;
-            rep[s].reason = it[s].reason;
-            rep[s].rp_mean = it[s].rp_mean;
-            rep[s].rv_mean = it[s].rv_mean;
-            rep[s].rp_max = it[s].rp_max;
-            rep[s].rv_max = it[s].rv_max;
-            rep[s].pairs = (int64_t)pairs[s];
+            rep[s].iters = it.iters;
+            rep[s].reason = it.reason;
+            rep[s].rp_mean = it.rp_mean;
+            rep[s].rv_mean = it.rv_mean;
+            rep[s].rp_max = it.rp_max;
+            rep[s].rv_max = it.rv_max;
+            rep[s].pairs = pairs;
         }
-        if (it[s].reason == DTSPH_NONFINITE) status = DTSPH_ENONFINITE;
-        else if (it[s].reason == DTSPH_MAXITER && status == DTSPH_OK) status = DTSPH_WARN_MAXITER;
+        if (it.reason == DTSPH_NONFINITE) status = DTSPH_ENONFINITE;
+        else if (it.reason == DTSPH_MAXITER && status == DTSPH_OK) status = DTSPH_WARN_MAXITER;
     }
     c.last_iters = most;
     if (status == DTSPH_ENONFINITE) c.err = "non-finite residual in the pseudo-time loop";
@@ -459,14 +457,34 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         c.nbr = (int *)dev_alloc(c, 4 * (size_t)c.cap * (size_t)N);
         c.cnt = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
         c.pairs = (unsigned long long *)dev_alloc(c, 8 * (size_t)n_sims);
-        const size_t max_tiles = (size_t)(Nf / 64 + n_sims + 8);
+        // lanes per particle: enough threads for ~8 waves per SIMD on 256 CUs
+        {
+            int lpp = 1;
+            while (lpp < 8 && (int64_t)lpp * Nf < (int64_t)256 * 2048) lpp *= 2;
+            c.lpp = lpp;
+        }
+        const size_t max_tiles = (size_t)(Nf + n_sims + 8);
         c.tiles = (int2 *)dev_alloc(c, sizeof(int2) * max_tiles);
         c.partials = (double4 *)dev_alloc(c, sizeof(double4) * max_tiles);
         c.flags = (int *)dev_alloc(c, sizeof(int) * (F_COUNT + n_sims));
         c.done_dev = c.flags + F_COUNT;
         c.init_slot = (int *)dev_alloc(c, sizeof(int) * 2 * (size_t)N);
-        DTSPH_HIP_CHECK(hipHostMalloc((void **)&c.flags_host, sizeof(int) * (F_COUNT + n_sims), 0));
-        c.done_host = c.flags_host + F_COUNT;
+        {
+            const size_t fb_bytes = (sizeof(int) * (F_COUNT + n_sims) + 15) / 16 * 16;
+            const size_t pb_bytes = 8 * (size_t)n_sims;
+            const size_t bytes = fb_bytes + pb_bytes + sizeof(MirrorRep) * n_sims;
+            DTSPH_HIP_CHECK(hipHostMalloc(&c.mirror_h, bytes, hipHostMallocMapped));
+            std::memset(c.mirror_h, 0, bytes);
+            void *md = nullptr;
+            DTSPH_HIP_CHECK(hipHostGetDevicePointer(&md, c.mirror_h, 0));
+            char *hb = (char *)c.mirror_h, *db = (char *)md;
+            c.flags_host = (int *)hb;
+            c.pairs_host = (unsigned long long *)(hb + fb_bytes);
+            c.reps_host = (MirrorRep *)(hb + fb_bytes + pb_bytes);
+            c.m_flags_d = (int *)db;
+            c.m_pairs_d = (unsigned long long *)(db + fb_bytes);
+            c.m_reps_d = (MirrorRep *)(db + fb_bytes + pb_bytes);
+        }
         DTSPH_HIP_CHECK(hipMemcpy(c.init_slot, init_slot.data(), sizeof(int) * 2 * N, hipMemcpyHostToDevice));
         DTSPH_HIP_CHECK(hipMemset(c.flags, 0, sizeof(int) * (F_COUNT + n_sims)));
         DTSPH_HIP_CHECK(hipMemset(c.cell_start, 0, 4 * (size_t)(2 * C + 1)));
@@ -652,7 +670,7 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
         if (keys) {
             std::vector<uint32_t> key(N), perm(N);
             DTSPH_HIP_CHECK(hipMemcpy(key.data(), c.key, 4 * N, hipMemcpyDeviceToHost));
-            DTSPH_HIP_CHECK(hipMemcpy(perm.data(), c.perm, 4 * N, hipMemcpyDeviceToHost));
+            DTSPH_HIP_CHECK(hipMemcpy(perm.data(), c.rank, 4 * N, hipMemcpyDeviceToHost));
             for (size_t d = 0; d < N; ++d) keys[d] = (int32_t)key[perm[d]];
         }
         if (caller_index) DTSPH_HIP_CHECK(hipMemcpy(caller_index, c.orig[c.buf], 4 * N, hipMemcpyDeviceToHost));
@@ -690,6 +708,13 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
         case DTSPH_OPT_XCD_REMAP:
             c.xcd_remap = value != 0;
             break;
+        case DTSPH_OPT_LANES:
+            if (value != 1 && value != 2 && value != 4 && value != 8)
+                throw ApiError(DTSPH_EINVAL, "lanes per particle must be 1, 2, 4 or 8");
+            DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+            c.lpp = (int)value;
+            setup_tiles(c);
+            break;
         default:
             throw ApiError(DTSPH_EINVAL, "unknown option " + std::to_string(option));
         }
@@ -721,6 +746,8 @@ int dtsph_get_info(const dtsph_ctx *ctx, dtsph_info *out)
     out->precision = c.precision;
     out->nbr_capacity = c.cap;
     out->block = c.block;
+    out->lanes = c.lpp;
+    out->reserved = 0;
     out->device_bytes = c.device_bytes;
     return DTSPH_OK;
 }

@@ -1,13 +1,17 @@
 // Cell-linked list and neighbour lists (HBM-bound streaming kernels).
 //
-// Per build:  k_keys (cell key + rank within cell by integer atomics)
+// Per build:  k_keys (cell key; per-cell counts by integer atomics, one atomic
+//             per run of equal keys in a wavefront)
 //          -> three-kernel exclusive scan of the per-key counts (= cell-start table)
-//          -> k_scatter (slot of each particle) -> k_cell_sort (ties by caller index)
-//          -> k_gather (all state arrays into the new order)
+//          -> k_scatter (provisional slot: cell start + arrival order)
+//          -> k_rank_gather (final slot: cell start + rank of the caller index
+//             among the cell's particles; every state array moved there)
 //          -> k_nbr (exact neighbour lists, position records, pair counts).
 // The sort is a counting sort over the whole key (one radix digit holding the
 // cell id): keys are dense and each cell holds a handful of particles, so one
 // histogram + scan + scatter moves the data once instead of once per 8-bit digit.
+#include <algorithm>
+
 #include "dtsph_internal.h"
 
 namespace dtsph {
@@ -17,18 +21,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kThreads * kScanItems;  // 4096 keys per block
-
-__global__ void k_fill_u32(uint32_t *p, int n, uint32_t v)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
-__global__ void k_fill_u64(unsigned long long *p, int n)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0ull;
-}
 
 __device__ inline int cell_coord(double x, double lo, double inv_cs, int n)
 {
@@ -45,17 +37,35 @@ __device__ inline int cell_linear(const SimDev &S, const double *x, int N, int i
     return (c3[2] * S.ncell[1] + c3[1]) * S.ncell[0] + c3[0];
 }
 
-__global__ void k_keys(int N, int Nf, int C, const double *__restrict__ x, const int *__restrict__ simid,
-                       const SimDev *__restrict__ sims, uint32_t *__restrict__ key,
-                       uint32_t *__restrict__ rank, uint32_t *__restrict__ count)
+__global__ void __launch_bounds__(kThreads) k_keys(int N, int Nf, int C, const double *__restrict__ x,
+                                                   const int *__restrict__ simid, const SimDev *__restrict__ sims,
+                                                   uint32_t *__restrict__ key, uint32_t *__restrict__ rank,
+                                                   uint32_t *__restrict__ count)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const SimDev &S = sims[simid[i]];
-    int c3[3];
-    uint32_t k = (uint32_t)(S.key_base + cell_linear(S, x, N, i, c3) + (i >= Nf ? C : 0));
-    key[i] = k;
-    rank[i] = atomicAdd(&count[k], 1u);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < N;
+    uint32_t k = 0xffffffffu;
+    if (active) {
+        const SimDev &S = sims[simid[i]];
+        int c3[3];
+        k = (uint32_t)(S.key_base + cell_linear(S, x, N, i, c3) + (i >= Nf ? C : 0));
+        key[i] = k;
+    }
+    // Slots are in the previous build's cell order, so equal keys sit in runs of
+    // consecutive lanes: the first lane of each run reserves the whole run.
+    const int lane = threadIdx.x & 63;
+    const uint32_t prev = __shfl_up(k, 1, 64);
+    const bool head = active && (lane == 0 || prev != k);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long act = __ballot(active);
+    const unsigned long long below = heads & ((2ull << lane) - 1ull);  // heads at lanes <= lane
+    const int my_head = 63 - __builtin_clzll(below | 1ull);
+    const unsigned long long above = heads & ~((2ull << lane) - 1ull);
+    const int next_head = above ? __builtin_ctzll(above) : 64 - __builtin_clzll(act);
+    uint32_t base = 0;
+    if (head) base = atomicAdd(&count[k], (uint32_t)(next_head - lane));
+    base = __shfl(base, my_head, 64);
+    if (active) rank[i] = base + (uint32_t)(lane - my_head);
 }
 
 // Block-wide exclusive scan of one value per thread (wave64 shuffles + LDS).
@@ -140,33 +150,14 @@ __global__ void k_scatter(int N, const uint32_t *__restrict__ key, const uint32_
     perm[cell_start[key[i]] + rank[i]] = (uint32_t)i;
 }
 
-// Order each cell's slots by caller index (insertion sort; cells are small).
-__global__ void k_cell_sort(int nkeys, const uint32_t *__restrict__ cell_start, uint32_t *__restrict__ perm,
-                            const int *__restrict__ orig, int *__restrict__ flags)
-{
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nkeys) return;
-    int b = (int)cell_start[k], e = (int)cell_start[k + 1];
-    if (e - b > kMaxCellOccupancy) {
-        atomicOr(&flags[F_CELL_OVERFLOW], 1);
-        return;
-    }
-    for (int m = b + 1; m < e; ++m) {
-        uint32_t v = perm[m];
-        int ov = orig[v];
-        int j = m - 1;
-        while (j >= b && orig[perm[j]] > ov) {
-            perm[j + 1] = perm[j];
-            --j;
-        }
-        perm[j + 1] = v;
-    }
-}
-
 template <typename T>
 struct GatherArgs {
     int N, Nf, Nw;
-    const uint32_t *perm;
+    const uint32_t *perm;      // provisional order from k_scatter
+    const uint32_t *key;
+    const uint32_t *cell_start;
+    uint32_t *src_of;          // final order: source slot of each slot
+    int *flags;
     const int *orig_in, *simid_in;
     int *orig_out, *simid_out;
     const double *x_in, *xn_in;
@@ -179,14 +170,28 @@ struct GatherArgs {
     T *vw_out, *pw_out;
 };
 
+// Final slot = cell start + number of the cell's particles with a smaller caller
+// index (ties in caller order, independent of atomic arrival order); every
+// state array is copied from the old slot to the final one.
 template <typename T>
-__global__ void k_gather(GatherArgs<T> A)
+__global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
 {
-    int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= A.N) return;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= A.N) return;
     const int N = A.N, Nf = A.Nf, Nw = A.Nw;
-    int s = (int)A.perm[d];
-    A.orig_out[d] = A.orig_in[s];
+    const int s = (int)A.perm[m];
+    const uint32_t k = A.key[s];
+    const int b = (int)A.cell_start[k], e = (int)A.cell_start[k + 1];
+    if (e - b > kMaxCellOccupancy) {
+        atomicOr(&A.flags[F_CELL_OVERFLOW], 1);
+        return;
+    }
+    const int os = A.orig_in[s];
+    int r = 0;
+    for (int q = b; q < e; ++q) r += A.orig_in[A.perm[q]] < os;
+    const int d = b + r;
+    A.src_of[d] = (uint32_t)s;
+    A.orig_out[d] = os;
     A.simid_out[d] = A.simid_in[s];
     for (int a = 0; a < 3; ++a) {
         A.x_out[a * N + d] = A.x_in[a * N + s];
@@ -202,7 +207,7 @@ __global__ void k_gather(GatherArgs<T> A)
         A.pn_out[d] = A.pn_in[s];
         A.dp_out[d] = A.dp_in[s];
     } else {
-        int dw = d - Nf, sw = s - Nf;
+        const int dw = d - Nf, sw = s - Nf;
         for (int a = 0; a < 3; ++a) A.vw_out[a * Nw + dw] = A.vw_in[a * Nw + sw];
         A.pw_out[dw] = A.pw_in[sw];
     }
@@ -285,56 +290,84 @@ __device__ inline void write_record<double>(const SimDev &S, void *prec, int i, 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.N) return;
+    __shared__ int s_ref;
+    __shared__ unsigned long long wsum[kThreads / 64];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < A.N;
     const int N = A.N;
-    const int s = A.simid[i];
-    const SimDev &S = A.sims[s];
+    const int s = active ? A.simid[i] : -1;
     const bool fluid = i < A.Nf;
-    double xi[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
-    if (S.dim < 3) xi[2] = 0.0;
-    write_record<T>(S, A.prec, i, xi);
-
-    int c3[3];
-    cell_linear(S, A.x, N, i, c3);
-    int ax[3][3], na[3];
-    for (int a = 0; a < 3; ++a) {
-        if (a < S.dim) na[a] = axis_cells(c3[a], S.ncell[a], S.periodic[a], ax[a]);
-        else { na[a] = 1; ax[a][0] = 0; }
-    }
-    const int cap = A.cap;
     int count[2] = {0, 0};
-    int total = 0;
-    for (int tp = 0; tp < (fluid ? 2 : 1); ++tp) {
-        const int base = S.key_base + (tp ? A.C : 0);
-        for (int u = 0; u < na[2]; ++u)
-            for (int v = 0; v < na[1]; ++v) {
-                const int row = base + (ax[2][u] * S.ncell[1] + ax[1][v]) * S.ncell[0];
-                int k = 0;
-                while (k < na[0]) {  // contiguous runs of x cells
-                    int xa = ax[0][k], xb = xa;
-                    while (k + 1 < na[0] && ax[0][k + 1] == xb + 1) { ++k; ++xb; }
-                    ++k;
-                    const int jb = (int)A.cell_start[row + xa], je = (int)A.cell_start[row + xb + 1];
-                    for (int j = jb; j < je; ++j) {
-                        if (j == i) continue;
-                        double xj[3] = {A.x[j], A.x[N + j], S.dim == 3 ? A.x[2 * N + j] : 0.0};
-                        if (!exact_neighbor(S, xi, xj)) continue;
-                        if (total < cap) A.nbr[(size_t)total * N + i] = j;
-                        ++total;
-                        ++count[tp];
+    if (active) {
+        const SimDev &S = A.sims[s];
+        double xi[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
+        if (S.dim < 3) xi[2] = 0.0;
+        write_record<T>(S, A.prec, i, xi);
+
+        int c3[3];
+        cell_linear(S, A.x, N, i, c3);
+        int ax[3][3], na[3];
+        for (int a = 0; a < 3; ++a) {
+            if (a < S.dim) na[a] = axis_cells(c3[a], S.ncell[a], S.periodic[a], ax[a]);
+            else { na[a] = 1; ax[a][0] = 0; }
+        }
+        const int cap = A.cap;
+        int total = 0;
+        for (int tp = 0; tp < (fluid ? 2 : 1); ++tp) {
+            const int base = S.key_base + (tp ? A.C : 0);
+            for (int u = 0; u < na[2]; ++u)
+                for (int v = 0; v < na[1]; ++v) {
+                    const int row = base + (ax[2][u] * S.ncell[1] + ax[1][v]) * S.ncell[0];
+                    int k = 0;
+                    while (k < na[0]) {  // contiguous runs of x cells
+                        int xa = ax[0][k], xb = xa;
+                        while (k + 1 < na[0] && ax[0][k + 1] == xb + 1) { ++k; ++xb; }
+                        ++k;
+                        const int jb = (int)A.cell_start[row + xa], je = (int)A.cell_start[row + xb + 1];
+                        for (int j = jb; j < je; ++j) {
+                            if (j == i) continue;
+                            double xj[3] = {A.x[j], A.x[N + j], S.dim == 3 ? A.x[2 * N + j] : 0.0};
+                            if (!exact_neighbor(S, xi, xj)) continue;
+                            if (total < cap) A.nbr[(size_t)total * N + i] = j;
+                            ++total;
+                            ++count[tp];
+                        }
                     }
                 }
-            }
+        }
+        if (total > cap) {
+            atomicOr(&A.flags[F_NBR_OVERFLOW], 1);
+            atomicMax(&A.flags[F_NBR_NEEDED], total);
+            count[0] = count[0] < cap ? count[0] : cap;
+            count[1] = cap - count[0] < count[1] ? cap - count[0] : count[1];
+        }
+        A.cnt[i] = (uint32_t)count[0] | ((uint32_t)count[1] << 16);
     }
-    if (total > cap) {
-        atomicOr(&A.flags[F_NBR_OVERFLOW], 1);
-        atomicMax(&A.flags[F_NBR_NEEDED], total);
-        count[0] = count[0] < cap ? count[0] : cap;
-        count[1] = cap - count[0] < count[1] ? cap - count[0] : count[1];
+    // pairs per sim: one atomic per block when the block's fluid rows share a sim
+    const unsigned long long mine = (active && fluid) ? (unsigned long long)(count[0] + count[1]) : 0ull;
+    if (threadIdx.x == 0) s_ref = s;
+    __syncthreads();
+    if (__syncthreads_and(mine == 0ull || s == s_ref)) {
+        unsigned long long v = mine;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
+            if (tot) atomicAdd(&A.pairs[s_ref], tot);
+        }
+    } else if (mine) {
+        atomicAdd(&A.pairs[s], mine);
     }
-    A.cnt[i] = (uint32_t)count[0] | ((uint32_t)count[1] << 16);
-    if (fluid) atomicAdd(&A.pairs[s], (unsigned long long)(count[0] + count[1]));
+}
+
+__global__ void k_build_reset(uint32_t *count, int nkeys, int *flags, unsigned long long *pairs, int n_sims)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nkeys) count[i] = 0u;
+    if (i < F_COUNT) flags[i] = 0;
+    if (i < n_sims) pairs[i] = 0ull;
 }
 
 inline int grid_for(int n) { return n > 0 ? ceil_div(n, kThreads) : 1; }
@@ -348,9 +381,9 @@ void build_cells(Ctx &c)
     const int N = c.N, nkeys = 2 * c.C;
     const int b = c.buf, o = c.buf ^ 1;
     int t0 = timer_begin(c);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nkeys)), dim3(kThreads), 0, st, c.count, nkeys, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, st, (uint32_t *)c.flags, (int)F_COUNT, 0u);
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(c.n_sims)), dim3(kThreads), 0, st, c.pairs, c.n_sims);
+    const int nreset = std::max(nkeys, std::max((int)F_COUNT, c.n_sims));
+    hipLaunchKernelGGL(k_build_reset, dim3(grid_for(nreset)), dim3(kThreads), 0, st, c.count, nkeys, c.flags,
+                       c.pairs, c.n_sims);
     hipLaunchKernelGGL(k_keys, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.Nf, c.C, c.x[c.xb], c.simid[b],
                        c.sims, c.key, c.rank, c.count);
     const int nblk = ceil_div(nkeys, kScanTile);
@@ -360,11 +393,11 @@ void build_cells(Ctx &c)
                        c.cell_start);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.key, c.rank, c.cell_start,
                        c.perm);
-    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(nkeys)), dim3(kThreads), 0, st, nkeys, c.cell_start, c.perm,
-                       c.orig[b], c.flags);
     GatherArgs<T> g;
     g.N = N; g.Nf = c.Nf; g.Nw = c.Nw;
-    g.perm = c.perm;
+    g.perm = c.perm; g.key = c.key; g.cell_start = c.cell_start;
+    g.src_of = c.rank;  // the arrival ranks are consumed by k_scatter
+    g.flags = c.flags;
     g.orig_in = c.orig[b]; g.orig_out = c.orig[o];
     g.simid_in = c.simid[b]; g.simid_out = c.simid[o];
     g.x_in = c.x[c.xb]; g.x_out = c.x[c.xb ^ 1];
@@ -377,7 +410,7 @@ void build_cells(Ctx &c)
     g.pn_in = c.pn[b]; g.pn_out = c.pn[o];
     g.vw_in = (const T *)c.vw[b]; g.vw_out = (T *)c.vw[o];
     g.pw_in = (const T *)c.pw[b]; g.pw_out = (T *)c.pw[o];
-    hipLaunchKernelGGL(k_gather<T>, dim3(grid_for(N)), dim3(kThreads), 0, st, g);
+    hipLaunchKernelGGL(k_rank_gather<T>, dim3(grid_for(N)), dim3(kThreads), 0, st, g);
     c.buf = o;
     c.xb ^= 1;
     NbrArgs<T> a;

@@ -69,6 +69,12 @@ struct SimIter {
     double rp_mean, rv_mean, rp_max, rv_max;
 };
 
+// Per-sim report as published to mapped host memory.
+struct MirrorRep {
+    int iters, reason;
+    double rp_mean, rv_mean, rp_max, rv_max;
+};
+
 // Context (host object owning device memory).
 struct Ctx {
     int precision = DTSPH_FP32;
@@ -77,6 +83,7 @@ struct Ctx {
     int C = 0;               // fluid cells of all sims; keys 0..2C-1
     int cap = 0;             // neighbour-list capacity per particle
     int block = 256;
+    int lpp = 1;             // lanes per particle in the pair pass
     int chunk = 0;           // 0 = adaptive
     int xcd_remap = 1;
     int max_dim = 2;
@@ -130,9 +137,14 @@ struct Ctx {
     int *done_dev = nullptr;
     int *init_slot = nullptr;             // caller index -> slot before any sort
 
-    // pinned host mirrors
-    int *done_host = nullptr;
-    int *flags_host = nullptr;
+    // mapped host memory written by k_publish (host and device views)
+    void *mirror_h = nullptr;
+    int *flags_host = nullptr;             // F_COUNT flags then n_sims stop flags
+    MirrorRep *reps_host = nullptr;
+    unsigned long long *pairs_host = nullptr;
+    int *m_flags_d = nullptr;
+    MirrorRep *m_reps_d = nullptr;
+    unsigned long long *m_pairs_d = nullptr;
 
     // timing
     bool timing = false;
@@ -150,6 +162,7 @@ template <typename T> void launch_pre_records(Ctx &c);
 template <typename T> void launch_wall(Ctx &c, int mode);
 template <typename T> void launch_pass(Ctx &c, int mode);
 void launch_finalize(Ctx &c);
+void launch_publish(Ctx &c);
 template <typename T> void launch_loop_begin(Ctx &c, int fixed_iters);
 template <typename T> void launch_loop_end(Ctx &c);
 template <typename T> void launch_correct(Ctx &c);

@@ -184,7 +184,15 @@ template <typename T> struct PassArgs {
     double4 *partials;
 };
 
-template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE>
+template <typename T> __device__ inline void lane_sum(T &v, int lpp)
+{
+    for (int o = lpp >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+}
+
+// LPP lanes share one particle: lane `sub` takes neighbour entries sub, sub+LPP,
+// ... and the partial sums are combined with butterfly shuffles, so that small
+// problems still put enough waves on every SIMD to hide the gather latency.
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP>
 __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
 {
     using Q = typename V4<T>::type;
@@ -195,12 +203,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
     const int2 tl = A.tiles[t];
     const int s = tl.x;
     const SimDev &S = A.sims[s];
-    const int i = tl.y + (int)threadIdx.x;
+    const int sub = (int)threadIdx.x & (LPP - 1);
+    const int i = tl.y + (int)threadIdx.x / LPP;
     const bool active = i < S.fluid_begin + S.nf;
+    const bool owner = active && sub == 0;
     const int N = A.N, Nf = A.Nf;
 
     if (MODE == MODE_PSEUDO && A.iters[s].done) {  // uniform per block
-        if (active) A.vout[i] = A.vin[i];
+        if (owner) A.vout[i] = A.vin[i];
         if (threadIdx.x == 0) A.partials[t] = make_double4(0.0, 0.0, 0.0, 0.0);
         return;
     }
@@ -211,16 +221,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
     const Q *__restrict__ vin = A.vin;
 
     Acc<T> acc;
-    T Dv = 0, R[3] = {0, 0, 0}, vt2 = 0;
+    T pi = 0, vi[3] = {0, 0, 0};
     if (active) {
         const Rec ri = prec[i];
         const Q me = vin[i];
-        const T vi[3] = {me.x, me.y, DIM == 3 ? me.z : T(0)};
-        const T pi = pres<DIM>(me);
+        vi[0] = me.x;
+        vi[1] = me.y;
+        vi[2] = DIM == 3 ? me.z : T(0);
+        pi = pres<DIM>(me);
         const uint32_t cn = A.cnt[i];
         const int nfl = (int)(cn & 0xffffu), nwl = (int)(cn >> 16);
         const int *__restrict__ nb = A.nbr + i;
-        for (int k = 0; k < nfl; ++k) {
+#pragma unroll 2
+        for (int k = sub; k < nfl; k += LPP) {
             const int j = nb[(size_t)k * N];
             const Rec rj = prec[j];
             const Q vj = vin[j];
@@ -232,7 +245,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
             pair_terms<T, DIM, AV, SEPDEN>(K, r, vd, vd, pi, pres<DIM>(vj), acc);
         }
         if (WALLS) {
-            for (int k = nfl; k < nfl + nwl; ++k) {
+            for (int k = nfl + sub; k < nfl + nwl; k += LPP) {
                 const int j = nb[(size_t)k * N];
                 const Rec rj = prec[j];
                 const Q gj = vin[j];  // ghost velocity and wall pressure
@@ -246,6 +259,18 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
                 pair_terms<T, DIM, AV, SEPDEN>(K, r, vd, vv, pi, pres<DIM>(gj), acc);
             }
         }
+    }
+    if (LPP > 1) {
+        lane_sum(acc.div, LPP);
+        lane_sum(acc.lap, LPP);
+        for (int d = 0; d < DIM; ++d) {
+            lane_sum(acc.grad[d], LPP);
+            lane_sum(acc.vis[d], LPP);
+        }
+    }
+
+    T Dv = 0, R[3] = {0, 0, 0}, vt2 = 0;
+    if (owner) {
         Dv = (T)S.k_div * acc.div + (T)S.k_lap * acc.lap;
         for (int d = 0; d < DIM; ++d) R[d] = (T)S.k_grad * acc.grad[d] + (T)S.k_visc * acc.vis[d] + (T)S.g[d];
 
@@ -289,8 +314,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
     if (MODE == MODE_PSEUDO) {
         // fixed-order block reduction of {sum |D|, sum |Vtilde|, max |D|, max |Vtilde|}
         __shared__ double lds[kMaxBlock / 64][4];
-        double sd = active ? fabs((double)Dv) : 0.0;
-        double sv = active ? sqrt((double)vt2) : 0.0;
+        double sd = owner ? fabs((double)Dv) : 0.0;
+        double sv = owner ? sqrt((double)vt2) : 0.0;
         double md = sd, mv = sv;
         for (int o = 32; o > 0; o >>= 1) {
             sd += __shfl_xor(sd, o, 64);
@@ -466,6 +491,29 @@ __global__ void k_finalize(const SimDev *__restrict__ sims, SimIter *__restrict_
     done_out[s] = It.done;
 }
 
+// Copy the host-visible control words (build flags, stop flags, per-sim reports
+// and pair counts) into mapped host memory, so one stream sync makes them
+// readable without a separate copy.
+__global__ void k_publish(int n_sims, const int *__restrict__ flags, const SimIter *__restrict__ iters,
+                          const unsigned long long *__restrict__ pairs, int *__restrict__ h_flags,
+                          MirrorRep *__restrict__ h_reps, unsigned long long *__restrict__ h_pairs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < F_COUNT + n_sims) h_flags[i] = flags[i];
+    if (i < n_sims) {
+        const SimIter &It = iters[i];
+        MirrorRep r;
+        r.iters = It.iters;
+        r.reason = It.reason;
+        r.rp_mean = It.rp_mean;
+        r.rv_mean = It.rv_mean;
+        r.rp_max = It.rp_max;
+        r.rv_max = It.rv_max;
+        h_reps[i] = r;
+        h_pairs[i] = pairs[i];
+    }
+}
+
 // ---- per-particle kernels -------------------------------------------------------
 __global__ void k_iter_reset(SimIter *iters, int n_sims, int fixed)
 {
@@ -625,20 +673,32 @@ template <typename T> PassArgs<T> pass_args(Ctx &c)
     return a;
 }
 
-template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN>
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int LPP>
 void dispatch_mode(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
 {
     if (mode == MODE_PRE)
-        hipLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PRE>), grid, dim3(c.block), 0, c.stream, a);
+        hipLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PRE, LPP>), grid, dim3(c.block), 0, c.stream, a);
     else
-        hipLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO>), grid, dim3(c.block), 0, c.stream, a);
+        hipLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP>), grid, dim3(c.block), 0, c.stream,
+                           a);
+}
+
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN>
+void dispatch_lpp(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
+{
+    switch (c.lpp) {
+    case 1: dispatch_mode<T, DIM, WALLS, AV, SEPDEN, 1>(c, mode, a, grid); break;
+    case 2: dispatch_mode<T, DIM, WALLS, AV, SEPDEN, 2>(c, mode, a, grid); break;
+    case 4: dispatch_mode<T, DIM, WALLS, AV, SEPDEN, 4>(c, mode, a, grid); break;
+    default: dispatch_mode<T, DIM, WALLS, AV, SEPDEN, 8>(c, mode, a, grid); break;
+    }
 }
 
 template <typename T, int DIM, bool WALLS, bool AV>
 void dispatch_sep(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
 {
-    if (c.sep_den) dispatch_mode<T, DIM, WALLS, AV, true>(c, mode, a, grid);
-    else dispatch_mode<T, DIM, WALLS, AV, false>(c, mode, a, grid);
+    if (c.sep_den) dispatch_lpp<T, DIM, WALLS, AV, true>(c, mode, a, grid);
+    else dispatch_lpp<T, DIM, WALLS, AV, false>(c, mode, a, grid);
 }
 
 template <typename T, int DIM, bool WALLS>
@@ -690,6 +750,14 @@ void launch_wall(Ctx &c, int mode)
     else hipLaunchKernelGGL((k_wall<T, 3>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
     DTSPH_HIP_CHECK(hipGetLastError());
     if (mode == MODE_PSEUDO) timer_end(c, t0, 1);
+}
+
+void launch_publish(Ctx &c)
+{
+    const int n = F_COUNT + c.n_sims;
+    hipLaunchKernelGGL(k_publish, dim3(grid_for(n)), dim3(256), 0, c.stream, c.n_sims, c.flags, c.iters, c.pairs,
+                       c.m_flags_d, c.m_reps_d, c.m_pairs_d);
+    DTSPH_HIP_CHECK(hipGetLastError());
 }
 
 void launch_finalize(Ctx &c)

@@ -21,7 +21,7 @@ OK, WARN_MAXITER = 0, 1
 EINVAL, ENOMEM, EHIP, ENONFINITE, EOVERFLOW = -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 REASONS = {0: "running", 1: "converged", 2: "stalled", 3: "max_iter", 4: "nonfinite", 5: "fixed"}
-OPT_TIMING, OPT_RESET_TIMING, OPT_CHUNK, OPT_BLOCK, OPT_XCD_REMAP = 1, 2, 3, 4, 5
+OPT_TIMING, OPT_RESET_TIMING, OPT_CHUNK, OPT_BLOCK, OPT_XCD_REMAP, OPT_LANES = 1, 2, 3, 4, 5, 6
 
 EXPORTS = [
     "dtsph_create", "dtsph_destroy", "dtsph_last_error", "dtsph_set_state", "dtsph_get_state",
@@ -85,7 +85,8 @@ class Timing(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_fluid", C.c_int64), ("n_wall", C.c_int64),
                 ("n_cells", C.c_int64), ("n_sims", C.c_int32), ("precision", C.c_int32),
-                ("nbr_capacity", C.c_int32), ("block", C.c_int32), ("device_bytes", C.c_int64)]
+                ("nbr_capacity", C.c_int32), ("block", C.c_int32), ("lanes", C.c_int32),
+                ("reserved", C.c_int32), ("device_bytes", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -28,6 +28,16 @@ def _row_floor(prob, rows):
     return rate_floor(prob) * np.sqrt(len(rows) / prob.n_fluid)
 
 
+def _acc_floor(prob, rows):
+    """Scale of the momentum terms: |g| when there is a body force (in a
+    hydrostatic column -grad p / rho and g cancel to a small remainder),
+    2 pi V_ref^2 / L otherwise; per row, as an L2 norm over the rows."""
+    p = prob.params
+    g = float(np.linalg.norm(p["g"]))
+    a = g if g > 0 else 2 * np.pi * p["vref"] ** 2
+    return a * np.sqrt(len(rows))
+
+
 @pytest.mark.parametrize("cfg", ["C1", "C2", "C3"])
 def test_fullsize_predict_sampled(cfg):
     prob = I.config(cfg)
@@ -39,7 +49,11 @@ def test_fullsize_predict_sampled(cfg):
     sim.close()
     rows = _rows(prob)
     vo, po, do = O.rows(prob.params, nf, nw, 0, rows, prob.x, prob.v, prob.p)
-    assert rel_l2(g["v_iter"][rows], vo) <= 1e-6
+    dt = prob.params["dt"]
+    acc_gpu = (g["v_iter"][rows] - prob.v[rows]) / dt
+    acc_or = (vo - prob.v[rows]) / dt
+    assert rel_l2(acc_gpu, acc_or, _acc_floor(prob, rows)) <= 1e-4
+    assert rel_l2(g["v_iter"][rows], vo) <= 1e-6 or nw > 0
     assert rel_l2(g["dpdtau"][rows], do, _row_floor(prob, rows)) <= 1e-4
     if nw == 0 and not any(prob.params["g"]):
         # periodic, no body force: pairwise antisymmetry conserves momentum
