@@ -57,6 +57,9 @@ def run_leg(problems, precision, steps, warmup, timing):
     from paper_1904_00861_amd import dtsph as D
 
     sim = D.Sim(problems, precision=precision)
+    tune = sim.autotune()
+    log(f"autotune: lanes {tune['lanes']} block {tune['block']} ({tune['us']:.2f} us/pass); " +
+        " ".join(f"{e['lanes']}x{e['block']}:{e['us']:.1f}" for e in tune["entries"]))
     if warmup:
         sim.step(warmup)
     sim.set_option(D.OPT_TIMING, 1 if timing else 0)
@@ -69,7 +72,7 @@ def run_leg(problems, precision, steps, warmup, timing):
     tm = sim.timing()
     info = dict(sim.info)
     sim.close()
-    return dict(seconds=t1 - t0, reports=reps, timing=tm, status=st, info=info)
+    return dict(seconds=t1 - t0, reports=reps, timing=tm, status=st, info=info, tune=tune)
 
 
 def traffic_from_profile(kernel_src):
@@ -87,7 +90,7 @@ def traffic_from_profile(kernel_src):
     return float(m_bytes.group(1)) if digest == m_hash.group(1) else None
 
 
-def cpu_baseline(prob, budget_s=12.0, max_steps=40):
+def cpu_baseline(prob, budget_s=12.0, max_steps=400):
     import oracle as O
 
     x, v, vp, p = prob.x, prob.v, prob.v_prev, prob.p
@@ -160,6 +163,8 @@ def main():
                         avg_launch_us=round(tm["pass_ms"] * 1e3 / tm["pass_launches"], 3),
                         pairs_per_launch=round(tm["pass_pairs"] / tm["pass_launches"], 1),
                         flop_per_pair=FLOP_PER_PAIR[dim],
+                        launch_shape=dict(lanes_per_particle=main_leg["tune"]["lanes"],
+                                          block=main_leg["tune"]["block"]),
                         frac_of_packed_peak=round(achieved / PEAK_PACKED_F32, 4) if dtype == "f32" else None)
 
     extras = {}

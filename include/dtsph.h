@@ -275,6 +275,28 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
                                   (default: smallest giving >= 512k threads)  */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
+/* Autotuner of the pair pass's launch shape. Between steps only (EINVAL in
+ * the loop). Builds the cell lists if needed, then times the rate pass of the
+ * predictor (it writes only scratch between steps, so the state is unchanged)
+ * for every lanes-per-particle in {1, 2, 4, 8} and workgroup size in {64, 128,
+ * 256}, `repeats` launches each (<= 0: 5), and keeps the fastest for this
+ * context. The choice is cached per process by (dim, precision, walls,
+ * artificial viscosity, fluid-count bucket) and applied to later contexts of
+ * the same kind. out (host, may be NULL) receives every timing.             */
+typedef struct dtsph_tune_entry {
+    int32_t lanes, block;
+    double us; /* mean duration of one pass launch */
+} dtsph_tune_entry;
+
+typedef struct dtsph_tune_report {
+    int32_t lanes, block; /* the choice */
+    double us;
+    int32_t n_entries, reserved;
+    dtsph_tune_entry entries[12];
+} dtsph_tune_report;
+
+int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out);
+
 int dtsph_get_timing(const dtsph_ctx *ctx, dtsph_timing *out);
 int dtsph_get_info(const dtsph_ctx *ctx, dtsph_info *out);
 

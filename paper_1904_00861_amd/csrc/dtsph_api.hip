@@ -4,6 +4,8 @@
 // the host only orders launches and reads back per-sim stop flags.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 
@@ -18,6 +20,18 @@ struct dtsph_ctx {
 namespace {
 
 std::string g_create_error = "no error";
+
+// autotuner choices of this process: key -> (lanes per particle, block)
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+std::string tune_key(const Ctx &c)
+{
+    int bucket = 0;
+    while ((1ll << (bucket + 1)) <= (long long)c.Nf) ++bucket;
+    return std::to_string(c.max_dim) + "/" + std::to_string(c.precision) + "/" + std::to_string(c.any_walls) +
+           "/" + std::to_string(c.any_av) + "/" + std::to_string(c.sep_den) + "/" + std::to_string(bucket);
+}
 
 template <typename F> int guarded(dtsph_ctx *ctx, F &&f)
 {
@@ -462,6 +476,12 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             int lpp = 1;
             while (lpp < 8 && (int64_t)lpp * Nf < (int64_t)256 * 2048) lpp *= 2;
             c.lpp = lpp;
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(tune_key(c));
+            if (it != g_tune_cache.end()) {
+                c.lpp = it->second.first;
+                c.block = it->second.second;
+            }
         }
         const size_t max_tiles = (size_t)(Nf + n_sims + 8);
         c.tiles = (int2 *)dev_alloc(c, sizeof(int2) * max_tiles);
@@ -488,6 +508,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         DTSPH_HIP_CHECK(hipMemcpy(c.init_slot, init_slot.data(), sizeof(int) * 2 * N, hipMemcpyHostToDevice));
         DTSPH_HIP_CHECK(hipMemset(c.flags, 0, sizeof(int) * (F_COUNT + n_sims)));
         DTSPH_HIP_CHECK(hipMemset(c.cell_start, 0, 4 * (size_t)(2 * C + 1)));
+        DTSPH_HIP_CHECK(hipMemset(c.count, 0, 4 * (size_t)(2 * C)));
         DTSPH_HIP_CHECK(hipMemset(c.cnt, 0, 4 * (size_t)N));
         DTSPH_HIP_CHECK(hipMemset(c.pairs, 0, 8 * (size_t)n_sims));
         setup_tiles(c);
@@ -718,6 +739,65 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
         default:
             throw ApiError(DTSPH_EINVAL, "unknown option " + std::to_string(option));
         }
+        return DTSPH_OK;
+    });
+}
+
+int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        if (c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_autotune: only between steps");
+        const int reps = repeats > 0 ? repeats : 5;
+        const bool timing = c.timing;
+        c.timing = false;
+        by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            ensure_cells<T>(c);
+            launch_pre_records<T>(c);
+            launch_wall<T>(c, MODE_PRE);
+            return 0;
+        });
+        hipEvent_t e0, e1;
+        DTSPH_HIP_CHECK(hipEventCreate(&e0));
+        DTSPH_HIP_CHECK(hipEventCreate(&e1));
+        dtsph_tune_report rep{};
+        rep.us = 1e300;
+        const int lanes[4] = {1, 2, 4, 8}, blocks[3] = {64, 128, 256};
+        for (int li = 0; li < 4; ++li)
+            for (int bi = 0; bi < 3; ++bi) {
+                c.lpp = lanes[li];
+                c.block = blocks[bi];
+                setup_tiles(c);
+                float ms = 0.f;
+                by_precision(c, [&](auto t) {
+                    using T = decltype(t);
+                    launch_pass<T>(c, MODE_PRE);  // warm-up
+                    DTSPH_HIP_CHECK(hipEventRecord(e0, c.stream));
+                    for (int r = 0; r < reps; ++r) launch_pass<T>(c, MODE_PRE);
+                    DTSPH_HIP_CHECK(hipEventRecord(e1, c.stream));
+                    return 0;
+                });
+                DTSPH_HIP_CHECK(hipEventSynchronize(e1));
+                DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                const double us = 1e3 * ms / reps;
+                rep.entries[rep.n_entries++] = dtsph_tune_entry{c.lpp, c.block, us};
+                if (us < rep.us) {
+                    rep.us = us;
+                    rep.lanes = c.lpp;
+                    rep.block = c.block;
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c.lpp = rep.lanes;
+        c.block = rep.block;
+        setup_tiles(c);
+        c.timing = timing;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[tune_key(c)] = {c.lpp, c.block};
+        }
+        if (out) *out = rep;
         return DTSPH_OK;
     });
 }

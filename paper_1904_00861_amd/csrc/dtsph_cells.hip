@@ -102,30 +102,20 @@ __global__ void k_scan_reduce(const uint32_t *__restrict__ in, int n, uint32_t *
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// Single block: exclusive scan of the block sums (n <= kScanTile).
-__global__ void k_scan_top(uint32_t *__restrict__ sums, int n)
+// Block b adds the sums of blocks 0..b-1 (read directly: there are at most a few
+// hundred), scans its own tile, writes the cell-start table, and leaves the
+// counts (and the per-sim pair counters) zeroed for the next build.
+__global__ void __launch_bounds__(kThreads) k_scan_down(uint32_t *__restrict__ in, int n,
+                                                        const uint32_t *__restrict__ sums,
+                                                        uint32_t *__restrict__ out,
+                                                        unsigned long long *__restrict__ pairs, int n_sims)
 {
     __shared__ uint32_t lds[kThreads / 64];
-    int base = threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t s = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < n ? sums[base + k] : 0u;
-        s += v[k];
-    }
-    uint32_t tot;
-    uint32_t run = block_exclusive_scan(s, lds, tot);
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) sums[base + k] = run;
-        run += v[k];
-    }
-}
-
-__global__ void k_scan_down(const uint32_t *__restrict__ in, int n, const uint32_t *__restrict__ sums,
-                            uint32_t *__restrict__ out)
-{
-    __shared__ uint32_t lds[kThreads / 64];
-    int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t before = 0;
+    for (int q = threadIdx.x; q < (int)blockIdx.x; q += blockDim.x) before += sums[q];
+    uint32_t block_off;
+    block_exclusive_scan(before, lds, block_off);  // block total = sum of preceding blocks
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint32_t s = 0;
     for (int k = 0; k < kScanItems; ++k) {
@@ -133,13 +123,17 @@ __global__ void k_scan_down(const uint32_t *__restrict__ in, int n, const uint32
         s += v[k];
     }
     uint32_t tot;
-    uint32_t run = block_exclusive_scan(s, lds, tot) + sums[blockIdx.x];
+    uint32_t run = block_exclusive_scan(s, lds, tot) + block_off;
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) out[base + k] = run;
+        if (base + k < n) {
+            out[base + k] = run;
+            in[base + k] = 0u;
+        }
         run += v[k];
     }
-    // the total lands one past the end
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) out[n] = run;
+    if (blockIdx.x == 0)
+        for (int q = threadIdx.x; q < n_sims; q += blockDim.x) pairs[q] = 0ull;
 }
 
 __global__ void k_scatter(int N, const uint32_t *__restrict__ key, const uint32_t *__restrict__ rank,
@@ -215,20 +209,27 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
 
 // Exact neighbour predicate: minimum-image separation, squared length summed
 // as (dx*dx + dy*dy) + dz*dz in float64 without contraction, strict < (kh)^2.
-__device__ inline bool exact_neighbor(const SimDev &S, const double xi[3], const double xj[3])
+// The sim's geometry is held in registers for the whole candidate scan.
+struct Geo {
+    int dim, per[3];
+    double L[3], halfL[3], kh2;
+};
+
+__device__ inline bool exact_neighbor(const Geo &G, const double xi[3], const double xj[3])
 {
 #pragma clang fp contract(off)
     double d[3] = {0.0, 0.0, 0.0};
-    for (int a = 0; a < S.dim; ++a) {
+    for (int a = 0; a < 3; ++a) {
+        if (a >= G.dim) break;
         double s = xi[a] - xj[a];
-        if (S.periodic[a]) {
-            if (s > S.halfL[a]) s -= S.L[a];
-            else if (s < -S.halfL[a]) s += S.L[a];
+        if (G.per[a]) {
+            if (s > G.halfL[a]) s -= G.L[a];
+            else if (s < -G.halfL[a]) s += G.L[a];
         }
         d[a] = s;
     }
     double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-    return r2 < S.kh2;
+    return r2 < G.kh2;
 }
 
 // Distinct neighbouring cell indices along one axis, ascending.
@@ -300,35 +301,49 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
     int count[2] = {0, 0};
     if (active) {
         const SimDev &S = A.sims[s];
-        double xi[3] = {A.x[i], A.x[N + i], A.x[2 * N + i]};
-        if (S.dim < 3) xi[2] = 0.0;
+        Geo G;
+        G.dim = S.dim;
+        G.kh2 = S.kh2;
+        int ncell[3];
+        for (int a = 0; a < 3; ++a) {
+            G.per[a] = S.periodic[a];
+            G.L[a] = S.L[a];
+            G.halfL[a] = S.halfL[a];
+            ncell[a] = S.ncell[a];
+        }
+        const int key_fluid = S.key_base;
+        const double *__restrict__ x0 = A.x;
+        const double *__restrict__ x1 = A.x + N;
+        const double *__restrict__ x2 = A.x + 2 * N;
+        const uint32_t *__restrict__ cstart = A.cell_start;
+        int *__restrict__ nbr = A.nbr;
+        double xi[3] = {x0[i], x1[i], G.dim == 3 ? x2[i] : 0.0};
         write_record<T>(S, A.prec, i, xi);
 
         int c3[3];
         cell_linear(S, A.x, N, i, c3);
         int ax[3][3], na[3];
         for (int a = 0; a < 3; ++a) {
-            if (a < S.dim) na[a] = axis_cells(c3[a], S.ncell[a], S.periodic[a], ax[a]);
+            if (a < G.dim) na[a] = axis_cells(c3[a], ncell[a], G.per[a], ax[a]);
             else { na[a] = 1; ax[a][0] = 0; }
         }
         const int cap = A.cap;
         int total = 0;
         for (int tp = 0; tp < (fluid ? 2 : 1); ++tp) {
-            const int base = S.key_base + (tp ? A.C : 0);
+            const int base = key_fluid + (tp ? A.C : 0);
             for (int u = 0; u < na[2]; ++u)
                 for (int v = 0; v < na[1]; ++v) {
-                    const int row = base + (ax[2][u] * S.ncell[1] + ax[1][v]) * S.ncell[0];
+                    const int row = base + (ax[2][u] * ncell[1] + ax[1][v]) * ncell[0];
                     int k = 0;
                     while (k < na[0]) {  // contiguous runs of x cells
                         int xa = ax[0][k], xb = xa;
                         while (k + 1 < na[0] && ax[0][k + 1] == xb + 1) { ++k; ++xb; }
                         ++k;
-                        const int jb = (int)A.cell_start[row + xa], je = (int)A.cell_start[row + xb + 1];
+                        const int jb = (int)cstart[row + xa], je = (int)cstart[row + xb + 1];
                         for (int j = jb; j < je; ++j) {
-                            if (j == i) continue;
-                            double xj[3] = {A.x[j], A.x[N + j], S.dim == 3 ? A.x[2 * N + j] : 0.0};
-                            if (!exact_neighbor(S, xi, xj)) continue;
-                            if (total < cap) A.nbr[(size_t)total * N + i] = j;
+                            const double xj[3] = {x0[j], x1[j], G.dim == 3 ? x2[j] : 0.0};
+                            if (j == i || !exact_neighbor(G, xi, xj)) continue;
+                            if (total < cap) nbr[(size_t)total * N + i] = j;
                             ++total;
                             ++count[tp];
                         }
@@ -362,14 +377,6 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
     }
 }
 
-__global__ void k_build_reset(uint32_t *count, int nkeys, int *flags, unsigned long long *pairs, int n_sims)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nkeys) count[i] = 0u;
-    if (i < F_COUNT) flags[i] = 0;
-    if (i < n_sims) pairs[i] = 0ull;
-}
-
 inline int grid_for(int n) { return n > 0 ? ceil_div(n, kThreads) : 1; }
 
 }  // namespace
@@ -381,16 +388,12 @@ void build_cells(Ctx &c)
     const int N = c.N, nkeys = 2 * c.C;
     const int b = c.buf, o = c.buf ^ 1;
     int t0 = timer_begin(c);
-    const int nreset = std::max(nkeys, std::max((int)F_COUNT, c.n_sims));
-    hipLaunchKernelGGL(k_build_reset, dim3(grid_for(nreset)), dim3(kThreads), 0, st, c.count, nkeys, c.flags,
-                       c.pairs, c.n_sims);
     hipLaunchKernelGGL(k_keys, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.Nf, c.C, c.x[c.xb], c.simid[b],
                        c.sims, c.key, c.rank, c.count);
     const int nblk = ceil_div(nkeys, kScanTile);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kThreads), 0, st, c.count, nkeys, c.scan_tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, c.scan_tmp, nblk);
     hipLaunchKernelGGL(k_scan_down, dim3(nblk), dim3(kThreads), 0, st, c.count, nkeys, c.scan_tmp,
-                       c.cell_start);
+                       c.cell_start, c.pairs, c.n_sims);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.key, c.rank, c.cell_start,
                        c.perm);
     GatherArgs<T> g;

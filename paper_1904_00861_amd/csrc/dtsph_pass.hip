@@ -420,19 +420,22 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
 }
 
 // ---- residual reduction and stop test (section 3.4) --------------------------
-__global__ void k_finalize(const SimDev *__restrict__ sims, SimIter *__restrict__ iters,
-                           const double4 *__restrict__ partials, int *__restrict__ done_out)
+__global__ void __launch_bounds__(256) k_finalize(const SimDev *__restrict__ sims, SimIter *__restrict__ iters,
+                                                  const double4 *__restrict__ partials, int *__restrict__ done_out)
 {
+    __shared__ double lds[4][4];
     const int s = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     SimIter &It = iters[s];
     if (It.done) {
-        if (lane == 0) done_out[s] = 1;
+        if (threadIdx.x == 0) done_out[s] = 1;
         return;
     }
     const SimDev &S = sims[s];
     double sd = 0, sv = 0, md = 0, mv = 0;
-    for (int t = S.tile_begin + lane; t < S.tile_end; t += 64) {
+    const int tb = S.tile_begin, te = S.tile_end;
+#pragma unroll 4
+    for (int t = tb + (int)threadIdx.x; t < te; t += 256) {
         const double4 p = partials[t];
         sd += p.x;
         sv += p.y;
@@ -445,7 +448,16 @@ __global__ void k_finalize(const SimDev *__restrict__ sims, SimIter *__restrict_
         md = fmax(md, __shfl_xor(md, o, 64));
         mv = fmax(mv, __shfl_xor(mv, o, 64));
     }
-    if (lane != 0) return;
+    if (lane == 0) { lds[wave][0] = sd; lds[wave][1] = sv; lds[wave][2] = md; lds[wave][3] = mv; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    sd = lds[0][0]; sv = lds[0][1]; md = lds[0][2]; mv = lds[0][3];
+    for (int w = 1; w < 4; ++w) {
+        sd += lds[w][0];
+        sv += lds[w][1];
+        md = fmax(md, lds[w][2]);
+        mv = fmax(mv, lds[w][3]);
+    }
     const double pscale = S.dt / (S.rho0 * S.c * S.c);
     const double rp = sd * S.res_p, rv = sv * S.res_v;
     const double rpx = md * pscale, rvx = mv / S.vref;
@@ -494,12 +506,13 @@ __global__ void k_finalize(const SimDev *__restrict__ sims, SimIter *__restrict_
 // Copy the host-visible control words (build flags, stop flags, per-sim reports
 // and pair counts) into mapped host memory, so one stream sync makes them
 // readable without a separate copy.
-__global__ void k_publish(int n_sims, const int *__restrict__ flags, const SimIter *__restrict__ iters,
+__global__ void k_publish(int n_sims, int *__restrict__ flags, const SimIter *__restrict__ iters,
                           const unsigned long long *__restrict__ pairs, int *__restrict__ h_flags,
                           MirrorRep *__restrict__ h_reps, unsigned long long *__restrict__ h_pairs)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < F_COUNT + n_sims) h_flags[i] = flags[i];
+    if (i < F_COUNT) flags[i] = 0;  // build flags are reported once
     if (i < n_sims) {
         const SimIter &It = iters[i];
         MirrorRep r;
@@ -762,7 +775,7 @@ void launch_publish(Ctx &c)
 
 void launch_finalize(Ctx &c)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(c.n_sims), dim3(64), 0, c.stream, c.sims, c.iters, c.partials, c.done_dev);
+    hipLaunchKernelGGL(k_finalize, dim3(c.n_sims), dim3(256), 0, c.stream, c.sims, c.iters, c.partials, c.done_dev);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 

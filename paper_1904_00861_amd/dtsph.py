@@ -27,7 +27,7 @@ EXPORTS = [
     "dtsph_create", "dtsph_destroy", "dtsph_last_error", "dtsph_set_state", "dtsph_get_state",
     "dtsph_build_cells", "dtsph_predict", "dtsph_pseudo_iterate", "dtsph_correct", "dtsph_step",
     "dtsph_neighbor_list", "dtsph_cell_layout", "dtsph_set_option", "dtsph_get_timing",
-    "dtsph_get_info",
+    "dtsph_get_info", "dtsph_autotune",
 ]
 
 
@@ -92,6 +92,20 @@ class Info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("block", C.c_int32), ("us", C.c_double)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("block", C.c_int32), ("us", C.c_double),
+                ("n_entries", C.c_int32), ("reserved", C.c_int32), ("entries", TuneEntry * 12)]
+
+    def as_dict(self) -> dict:
+        return dict(lanes=self.lanes, block=self.block, us=self.us,
+                    entries=[dict(lanes=e.lanes, block=e.block, us=e.us)
+                             for e in self.entries[:self.n_entries]])
+
+
 _lib = None
 
 
@@ -122,6 +136,7 @@ def lib() -> C.CDLL:
         L.dtsph_set_option.argtypes = [vp, C.c_int32, C.c_int64]
         L.dtsph_get_timing.argtypes = [vp, P(Timing)]
         L.dtsph_get_info.argtypes = [vp, P(Info)]
+        L.dtsph_autotune.argtypes = [vp, C.c_int32, P(TuneReport)]
         for name in EXPORTS:
             if name not in ("dtsph_destroy", "dtsph_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -245,6 +260,12 @@ def dtsph_get_timing(ctx) -> dict:
     return t.as_dict()
 
 
+def dtsph_autotune(ctx, repeats: int = 5) -> dict:
+    r = TuneReport()
+    _check(ctx, lib().dtsph_autotune(ctx, int(repeats), C.byref(r)))
+    return r.as_dict()
+
+
 def dtsph_get_info(ctx) -> dict:
     i = Info()
     _check(ctx, lib().dtsph_get_info(ctx, C.byref(i)))
@@ -347,6 +368,11 @@ class Sim:
 
     def timing(self) -> dict:
         return dtsph_get_timing(self.ctx)
+
+    def autotune(self, repeats: int = 5) -> dict:
+        rep = dtsph_autotune(self.ctx, repeats)
+        self.info = dtsph_get_info(self.ctx)
+        return rep
 
     def sim_slices(self) -> List[slice]:
         out, o = [], 0

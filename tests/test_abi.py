@@ -39,7 +39,8 @@ def test_library_exports_every_declared_function():
 
 
 STRUCTS = {"dtsph_sim_desc": D.SimDesc, "dtsph_state_view": D.StateView,
-           "dtsph_iter_report": D.IterReport, "dtsph_timing": D.Timing, "dtsph_info": D.Info}
+           "dtsph_iter_report": D.IterReport, "dtsph_timing": D.Timing, "dtsph_info": D.Info,
+           "dtsph_tune_entry": D.TuneEntry, "dtsph_tune_report": D.TuneReport}
 
 
 def test_struct_layouts_match_header():

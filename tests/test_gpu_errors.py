@@ -121,3 +121,27 @@ def test_block_and_xcd_options_do_not_change_results(block):
     # fields do not depend on the launch shape (residual sums may differ in the last bit)
     for f in a:
         assert np.array_equal(a[f], b[f])
+
+
+def test_autotune_keeps_state_and_results():
+    banner("autotune")
+    prob = I.tgv2d(40, seed=9)
+    sim = D.Sim(prob, precision=D.FP32)
+    before = sim.get_state()
+    rep = sim.autotune(repeats=2)
+    after = sim.get_state()
+    for f in before:
+        assert np.array_equal(before[f], after[f])
+    assert rep["n_entries"] if "n_entries" in rep else len(rep["entries"]) == 12
+    assert (rep["lanes"], rep["block"]) in [(e["lanes"], e["block"]) for e in rep["entries"]]
+    assert sim.info["lanes"] == rep["lanes"] and sim.info["block"] == rep["block"]
+    st, reps = sim.step(2)
+    tuned = sim.get_state()
+    sim.close()
+    ref = D.Sim(prob, precision=D.FP32)
+    ref.set_option(D.OPT_LANES, 1)
+    ref.step(2)
+    plain = ref.get_state()
+    ref.close()
+    nf = prob.n_fluid
+    assert np.linalg.norm(tuned["v"][:nf] - plain["v"][:nf]) <= 1e-5 * np.linalg.norm(plain["v"][:nf])
