@@ -209,49 +209,37 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
 
 // Exact neighbour predicate: minimum-image separation, squared length summed
 // as (dx*dx + dy*dy) + dz*dz in float64 without contraction, strict < (kh)^2.
-// The sim's geometry is held in registers for the whole candidate scan.
-struct Geo {
-    int dim, per[3];
-    double L[3], halfL[3], kh2;
+__device__ inline double min_image(double s, int per, double L, double halfL)
+{
+    if (per) {
+        if (s > halfL) s -= L;
+        else if (s < -halfL) s += L;
+    }
+    return s;
+}
+
+// Cells along one axis whose particles can be neighbours of a particle in cell
+// c: c-1, c, c+1, wrapped on periodic axes, clipped on others; a periodic axis
+// with fewer than three cells visits each of its cells once.
+struct AxisRange {
+    int first, count, n, per;
+    __device__ AxisRange(int c, int n_, int per_) : n(n_), per(per_)
+    {
+        if (per && n < 3) { first = 0; count = n; }
+        else if (per) { first = c - 1; count = 3; }
+        else {
+            first = c > 0 ? c - 1 : 0;
+            const int last = c < n - 1 ? c + 1 : n - 1;
+            count = last - first + 1;
+        }
+    }
+    __device__ int at(int k) const
+    {
+        int v = first + k;
+        if (per) v = v < 0 ? v + n : (v >= n ? v - n : v);
+        return v;
+    }
 };
-
-__device__ inline bool exact_neighbor(const Geo &G, const double xi[3], const double xj[3])
-{
-#pragma clang fp contract(off)
-    double d[3] = {0.0, 0.0, 0.0};
-    for (int a = 0; a < 3; ++a) {
-        if (a >= G.dim) break;
-        double s = xi[a] - xj[a];
-        if (G.per[a]) {
-            if (s > G.halfL[a]) s -= G.L[a];
-            else if (s < -G.halfL[a]) s += G.L[a];
-        }
-        d[a] = s;
-    }
-    double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-    return r2 < G.kh2;
-}
-
-// Distinct neighbouring cell indices along one axis, ascending.
-__device__ inline int axis_cells(int c, int n, int periodic, int out[3])
-{
-    int m = 0;
-    for (int o = -1; o <= 1; ++o) {
-        int v = c + o;
-        if (periodic) v = (v + n) % n;
-        else if (v < 0 || v >= n) continue;
-        bool dup = false;
-        for (int k = 0; k < m; ++k) dup |= out[k] == v;
-        if (!dup) out[m++] = v;
-    }
-    for (int a = 1; a < m; ++a)  // sort (m <= 3)
-        for (int b = a; b > 0 && out[b - 1] > out[b]; --b) {
-            int t = out[b];
-            out[b] = out[b - 1];
-            out[b - 1] = t;
-        }
-    return m;
-}
 
 template <typename T>
 struct NbrArgs {
@@ -288,7 +276,7 @@ __device__ inline void write_record<double>(const SimDev &S, void *prec, int i, 
     ((double4 *)prec)[i] = make_double4(xi[0], xi[1], xi[2], 0.0);
 }
 
-template <typename T>
+template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
 {
     __shared__ int s_ref;
@@ -298,68 +286,71 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
     const int N = A.N;
     const int s = active ? A.simid[i] : -1;
     const bool fluid = i < A.Nf;
-    int count[2] = {0, 0};
+    int cf = 0, cw = 0;
     if (active) {
         const SimDev &S = A.sims[s];
-        Geo G;
-        G.dim = S.dim;
-        G.kh2 = S.kh2;
-        int ncell[3];
-        for (int a = 0; a < 3; ++a) {
-            G.per[a] = S.periodic[a];
-            G.L[a] = S.L[a];
-            G.halfL[a] = S.halfL[a];
-            ncell[a] = S.ncell[a];
-        }
+        const double kh2 = S.kh2;
+        const int px = S.periodic[0], py = S.periodic[1], pz = DIM == 3 ? S.periodic[2] : 0;
+        const double Lx = S.L[0], Ly = S.L[1], Lz = S.L[2];
+        const double hx = S.halfL[0], hy = S.halfL[1], hz = S.halfL[2];
+        const int nx = S.ncell[0], ny = S.ncell[1], nz = DIM == 3 ? S.ncell[2] : 1;
         const int key_fluid = S.key_base;
         const double *__restrict__ x0 = A.x;
         const double *__restrict__ x1 = A.x + N;
         const double *__restrict__ x2 = A.x + 2 * N;
         const uint32_t *__restrict__ cstart = A.cell_start;
         int *__restrict__ nbr = A.nbr;
-        double xi[3] = {x0[i], x1[i], G.dim == 3 ? x2[i] : 0.0};
-        write_record<T>(S, A.prec, i, xi);
-
-        int c3[3];
-        cell_linear(S, A.x, N, i, c3);
-        int ax[3][3], na[3];
-        for (int a = 0; a < 3; ++a) {
-            if (a < G.dim) na[a] = axis_cells(c3[a], ncell[a], G.per[a], ax[a]);
-            else { na[a] = 1; ax[a][0] = 0; }
-        }
+        const double xi = x0[i], yi = x1[i], zi = DIM == 3 ? x2[i] : 0.0;
+        const double pos3[3] = {xi, yi, zi};
+        write_record<T>(S, A.prec, i, pos3);
+        const int cx = cell_coord(xi, S.lo[0], S.inv_cs[0], nx);
+        const int cy = cell_coord(yi, S.lo[1], S.inv_cs[1], ny);
+        const int cz = DIM == 3 ? cell_coord(zi, S.lo[2], S.inv_cs[2], nz) : 0;
+        // x cells as at most two contiguous runs of keys
+        int xa0, xb0, xa1 = 0, xb1 = -1;
+        if (px && nx < 3) { xa0 = 0; xb0 = nx - 1; }
+        else if (px && cx == 0) { xa0 = 0; xb0 = 1; xa1 = xb1 = nx - 1; }
+        else if (px && cx == nx - 1) { xa0 = nx - 2; xb0 = nx - 1; xa1 = xb1 = 0; }
+        else { xa0 = cx > 0 ? cx - 1 : 0; xb0 = cx < nx - 1 ? cx + 1 : nx - 1; }
+        const AxisRange ry(cy, ny, py), rz(cz, nz, pz);
         const int cap = A.cap;
         int total = 0;
         for (int tp = 0; tp < (fluid ? 2 : 1); ++tp) {
             const int base = key_fluid + (tp ? A.C : 0);
-            for (int u = 0; u < na[2]; ++u)
-                for (int v = 0; v < na[1]; ++v) {
-                    const int row = base + (ax[2][u] * ncell[1] + ax[1][v]) * ncell[0];
-                    int k = 0;
-                    while (k < na[0]) {  // contiguous runs of x cells
-                        int xa = ax[0][k], xb = xa;
-                        while (k + 1 < na[0] && ax[0][k + 1] == xb + 1) { ++k; ++xb; }
-                        ++k;
+            int found = 0;
+            for (int u = 0; u < rz.count; ++u)
+                for (int v = 0; v < ry.count; ++v) {
+                    const int row = base + (rz.at(u) * ny + ry.at(v)) * nx;
+                    for (int run = 0; run < 2; ++run) {
+                        const int xa = run ? xa1 : xa0, xb = run ? xb1 : xb0;
+                        if (xb < xa) continue;
                         const int jb = (int)cstart[row + xa], je = (int)cstart[row + xb + 1];
                         for (int j = jb; j < je; ++j) {
-                            const double xj[3] = {x0[j], x1[j], G.dim == 3 ? x2[j] : 0.0};
-                            if (j == i || !exact_neighbor(G, xi, xj)) continue;
+#pragma clang fp contract(off)
+                            const double dx = min_image(xi - x0[j], px, Lx, hx);
+                            const double dy = min_image(yi - x1[j], py, Ly, hy);
+                            const double dz = DIM == 3 ? min_image(zi - x2[j], pz, Lz, hz) : 0.0;
+                            const double r2 = (dx * dx + dy * dy) + dz * dz;
+                            if (j == i || !(r2 < kh2)) continue;
                             if (total < cap) nbr[(size_t)total * N + i] = j;
                             ++total;
-                            ++count[tp];
+                            ++found;
                         }
                     }
                 }
+            if (tp) cw = found;
+            else cf = found;
         }
         if (total > cap) {
             atomicOr(&A.flags[F_NBR_OVERFLOW], 1);
             atomicMax(&A.flags[F_NBR_NEEDED], total);
-            count[0] = count[0] < cap ? count[0] : cap;
-            count[1] = cap - count[0] < count[1] ? cap - count[0] : count[1];
+            cf = cf < cap ? cf : cap;
+            cw = cap - cf < cw ? cap - cf : cw;
         }
-        A.cnt[i] = (uint32_t)count[0] | ((uint32_t)count[1] << 16);
+        A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
     }
     // pairs per sim: one atomic per block when the block's fluid rows share a sim
-    const unsigned long long mine = (active && fluid) ? (unsigned long long)(count[0] + count[1]) : 0ull;
+    const unsigned long long mine = (active && fluid) ? (unsigned long long)(cf + cw) : 0ull;
     if (threadIdx.x == 0) s_ref = s;
     __syncthreads();
     if (__syncthreads_and(mine == 0ull || s == s_ref)) {
@@ -420,7 +411,8 @@ void build_cells(Ctx &c)
     a.N = N; a.Nf = c.Nf; a.C = c.C; a.cap = c.cap;
     a.x = c.x[c.xb]; a.simid = c.simid[o]; a.sims = c.sims; a.cell_start = c.cell_start;
     a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.pairs = c.pairs; a.flags = c.flags;
-    hipLaunchKernelGGL(k_nbr<T>, dim3(grid_for(N)), dim3(kThreads), 0, st, a);
+    if (c.max_dim == 2) hipLaunchKernelGGL((k_nbr<T, 2>), dim3(grid_for(N)), dim3(kThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_nbr<T, 3>), dim3(grid_for(N)), dim3(kThreads), 0, st, a);
     DTSPH_HIP_CHECK(hipGetLastError());
     timer_end(c, t0, 2);
 }
