@@ -116,6 +116,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batched legs")
     ap.add_argument("--no-timing", action="store_true", help="no HIP events in the timed region")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain elementwise copy of MIB MiB (float32) five times, for "
+                         "scaling the HBM byte counters of a profiler; prints its bytes")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -129,6 +132,16 @@ def main():
     from paper_1904_00861_amd import inputs as I
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.rand(n, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.add(src, 0.0, out=dst)  # reads 4n bytes, writes 4n bytes
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "elementwise copy", "read_bytes_per_launch": 4 * n,
+                          "write_bytes_per_launch": 4 * n, "launches": 5}))
+        return
     D.lib()
     prec = D.FP32 if args.precision == "fp32" else D.FP64
     dtype = "f32" if args.precision == "fp32" else "f64"

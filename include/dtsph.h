@@ -217,9 +217,13 @@ int dtsph_get_state(dtsph_ctx *ctx, const dtsph_state_view *state);
  * neighbour list N(i) = { j != i : |r_ij| < kappa h } (minimum image on
  * periodic axes; fluid rows take fluid and wall j, wall rows fluid j only).
  * The predicate is evaluated in float64 without fused multiply-add, so the
- * sets equal those of any implementation of that formula. Neighbour search
- * is needed once per position change: Algorithm 2 rebuilds once at r^n and
- * once at r^(0); the pseudo-time loop reuses the list (frozen particles).
+ * sets equal those of any implementation of that formula. The lists are
+ * needed once per position change: at r^n and at r^(0) in each step; the
+ * pseudo-time loop reuses them (frozen particles). A build also keeps
+ * candidate lists of radius kappa*h + skin (skin = 0.1 h); since
+ * r^{n+1} - r^(0) = dt/2 (V^{n+1} - V^(0)), the loop knows how far particles
+ * will move, and the lists at r^{n+1} are then the candidates filtered by
+ * the same exact predicate (no sort) whenever that distance is below 0.4 skin.
  * Other calls build on demand; calling it explicitly is optional.
  * Errors: EOVERFLOW (capacity; the message names the needed max_neighbors),
  * EHIP.                                                                     */
@@ -273,6 +277,9 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
 #define DTSPH_OPT_XCD_REMAP 5  /* 1: map consecutive tiles to one XCD (default) */
 #define DTSPH_OPT_LANES 6      /* lanes per particle in the pair pass: 1, 2, 4, 8
                                   (default: smallest giving >= 512k threads)  */
+#define DTSPH_OPT_SKIN 7       /* candidate-list skin in thousandths of h, at
+                                  most the default 100 (0: rebuild the cell
+                                  lists at every position change)            */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the pair pass's launch shape. Between steps only (EINVAL in

@@ -110,6 +110,14 @@ SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
     S.nw = (int)nw;
     S.edac_reg_literal = d.edac_reg_literal;
     const double kh = d.kappa * d.h;
+    // candidate lists reach kappa h + skin: skin = 0.1 h, reduced so that the
+    // candidate radius stays below half of every period
+    double skin = 0.1 * d.h;
+    for (int a = 0; a < d.dim; ++a)
+        if (d.periodic[a]) skin = std::min(skin, 0.5 * (0.5 * (d.hi[a] - d.lo[a]) - kh));
+    S.skin = std::max(0.0, skin);
+    const double kc = kh + S.skin;
+    S.cand_r2 = kc * kc;
     for (int a = 0; a < 3; ++a) {
         if (a < d.dim) {
             S.lo[a] = d.lo[a];
@@ -117,8 +125,8 @@ SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
             S.L[a] = d.hi[a] - d.lo[a];
             S.halfL[a] = 0.5 * S.L[a];
             S.periodic[a] = d.periodic[a] ? 1 : 0;
-            // cells no smaller than kappa*h (small margin against rounding)
-            int n = (int)std::floor(S.L[a] / (kh * (1.0 + 1e-6)));
+            // cells no smaller than the candidate radius (small margin against rounding)
+            int n = (int)std::floor(S.L[a] / (kc * (1.0 + 1e-6)));
             S.ncell[a] = std::max(1, n);
             S.cs[a] = S.L[a] / S.ncell[a];
             S.inv_cs[a] = 1.0 / S.cs[a];
@@ -206,6 +214,7 @@ template <typename T> void alloc_state(Ctx &c)
         c.vn[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
         c.dv[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
         c.w[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
+        c.w0[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
         c.pm[b] = (double *)dev_alloc(c, 8 * Nf);
         c.pn[b] = (double *)dev_alloc(c, 8 * Nf);
         c.dp[b] = dev_alloc(c, sizeof(T) * Nf);
@@ -255,10 +264,14 @@ void readback_flags(Ctx &c)
                                         "box or clumped); particle state is undefined");
 }
 
+// Exact neighbour lists for the current positions: a filter of the candidate
+// lists when every particle is known to be within skin/2 of where the lists
+// were built, else a full cell build.
 template <typename T> void ensure_cells(Ctx &c)
 {
     if (!c.cells_valid) {
-        build_cells<T>(c);
+        if (c.cand_ok) filter_lists<T>(c);
+        else build_cells<T>(c);
         c.cells_valid = true;
     }
 }
@@ -273,6 +286,7 @@ template <typename T> void do_predict(Ctx &c)
     c.xb ^= 1;
     c.in_loop = true;
     c.cells_valid = false;
+    c.cand_ok = false;
 }
 
 template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
@@ -303,8 +317,12 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
     }
     launch_loop_end<T>(c);
     int status = DTSPH_OK, most = 1;
+    bool cand = true;
     for (int s = 0; s < c.n_sims; ++s) {
         const MirrorRep &it = c.reps_host[s];
+        // r^{n+1} - r^(0) = dt/2 (V^{n+1} - V^(0)): within skin/2 (with margin) the
+        // candidate lists built at r^(0) still hold every neighbour at r^{n+1}
+        cand = cand && c.sims_h[s].skin > 0 && it.disp < 0.4 * c.sims_h[s].skin;
         const int64_t pairs = (int64_t)c.pairs_host[s];
         most = std::max(most, it.iters);
         c.tstats.pass_pairs += pairs * it.iters;
@@ -322,6 +340,7 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
         else if (it.reason == DTSPH_MAXITER && status == DTSPH_OK) status = DTSPH_WARN_MAXITER;
     }
     c.last_iters = most;
+    c.cand_next = cand;
     if (status == DTSPH_ENONFINITE) c.err = "non-finite residual in the pseudo-time loop";
     return status;
 }
@@ -332,6 +351,7 @@ template <typename T> void do_correct(Ctx &c)
     launch_correct<T>(c);
     c.in_loop = false;
     c.cells_valid = false;
+    c.cand_ok = c.cand_next;
 }
 
 template <typename T> int do_step(Ctx &c, int n_steps, dtsph_iter_report *reps)
@@ -447,7 +467,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             if (d.max_neighbors > 0) {
                 est = d.max_neighbors;
             } else {
-                const double dx = std::pow(d.mass / d.rho0, 1.0 / d.dim), kh = d.kappa * d.h;
+                const double dx = std::pow(d.mass / d.rho0, 1.0 / d.dim), kh = d.kappa * d.h * 1.04;
                 const double lat = d.dim == 2 ? 3.14159265358979 * kh * kh / (dx * dx)
                                               : 4.0 / 3.0 * 3.14159265358979 * kh * kh * kh / (dx * dx * dx);
                 est = 1.5 * lat + 8.0;
@@ -470,6 +490,9 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         c.scan_tmp = (uint32_t *)dev_alloc(c, 4 * (size_t)(4096 + 1));
         c.nbr = (int *)dev_alloc(c, 4 * (size_t)c.cap * (size_t)N);
         c.cnt = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
+        c.capc = c.cap;
+        c.cand = (int *)dev_alloc(c, 4 * (size_t)c.capc * (size_t)N);
+        c.ccnt = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
         c.pairs = (unsigned long long *)dev_alloc(c, 8 * (size_t)n_sims);
         // lanes per particle: enough threads for ~8 waves per SIMD on 256 CUs
         {
@@ -486,6 +509,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         const size_t max_tiles = (size_t)(Nf + n_sims + 8);
         c.tiles = (int2 *)dev_alloc(c, sizeof(int2) * max_tiles);
         c.partials = (double4 *)dev_alloc(c, sizeof(double4) * max_tiles);
+        c.partials2 = (double *)dev_alloc(c, sizeof(double) * max_tiles);
         c.flags = (int *)dev_alloc(c, sizeof(int) * (F_COUNT + n_sims));
         c.done_dev = c.flags + F_COUNT;
         c.init_slot = (int *)dev_alloc(c, sizeof(int) * 2 * (size_t)N);
@@ -559,6 +583,8 @@ int dtsph_set_state(dtsph_ctx *ctx, const dtsph_state_view *s)
         });
         c.in_loop = lp;
         c.cells_valid = false;
+        c.cand_ok = false;
+        c.cand_next = false;
         c.cur = 0;
         DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
         return DTSPH_OK;
@@ -729,6 +755,20 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
         case DTSPH_OPT_XCD_REMAP:
             c.xcd_remap = value != 0;
             break;
+        case DTSPH_OPT_SKIN: {
+            if (value < 0) throw ApiError(DTSPH_EINVAL, "skin must be >= 0");
+            for (int s = 0; s < c.n_sims; ++s) {
+                SimDev &S = c.sims_h[s];
+                const double kh = std::sqrt(S.kh2);
+                S.skin = std::min(S.skin, 1e-3 * (double)value * S.h);
+                S.cand_r2 = (kh + S.skin) * (kh + S.skin);
+            }
+            DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+            DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
+            c.cand_ok = c.cand_next = false;
+            c.cells_valid = false;
+            break;
+        }
         case DTSPH_OPT_LANES:
             if (value != 1 && value != 2 && value != 4 && value != 8)
                 throw ApiError(DTSPH_EINVAL, "lanes per particle must be 1, 2, 4 or 8");

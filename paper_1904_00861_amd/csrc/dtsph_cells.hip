@@ -6,7 +6,11 @@
 //          -> k_scatter (provisional slot: cell start + arrival order)
 //          -> k_rank_gather (final slot: cell start + rank of the caller index
 //             among the cell's particles; every state array moved there)
-//          -> k_nbr (exact neighbour lists, position records, pair counts).
+//          -> k_nbr (exact neighbour lists, candidate lists of radius kappa h +
+//             skin, position records, pair counts).
+// Between builds, k_filter re-derives the exact lists from the candidate lists
+// at new positions, valid while no particle has moved more than skin/2 since
+// the build (checked by the caller).
 // The sort is a counting sort over the whole key (one radix digit holding the
 // cell id): keys are dense and each cell holds a handful of particles, so one
 // histogram + scan + scatter moves the data once instead of once per 8-bit digit.
@@ -156,8 +160,8 @@ struct GatherArgs {
     int *orig_out, *simid_out;
     const double *x_in, *xn_in;
     double *x_out, *xn_out;
-    const T *vn_in, *dv_in, *w_in, *dp_in;
-    T *vn_out, *dv_out, *w_out, *dp_out;
+    const T *vn_in, *dv_in, *w_in, *w0_in, *dp_in;
+    T *vn_out, *dv_out, *w_out, *w0_out, *dp_out;
     const double *pm_in, *pn_in;
     double *pm_out, *pn_out;
     const T *vw_in, *pw_in;
@@ -196,6 +200,7 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
             A.vn_out[a * Nf + d] = A.vn_in[a * Nf + s];
             A.dv_out[a * Nf + d] = A.dv_in[a * Nf + s];
             A.w_out[a * Nf + d] = A.w_in[a * Nf + s];
+            A.w0_out[a * Nf + d] = A.w0_in[a * Nf + s];
         }
         A.pm_out[d] = A.pm_in[s];
         A.pn_out[d] = A.pn_in[s];
@@ -241,6 +246,28 @@ struct AxisRange {
     }
 };
 
+// Pairs per sim: one atomic per block when the block's fluid rows share a sim.
+__device__ inline void add_pairs(unsigned long long mine, int s, unsigned long long *pairs)
+{
+    __shared__ int s_ref;
+    __shared__ unsigned long long wsum[kThreads / 64];
+    if (threadIdx.x == 0) s_ref = s;
+    __syncthreads();
+    if (__syncthreads_and(mine == 0ull || s == s_ref)) {
+        unsigned long long v = mine;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
+            if (tot) atomicAdd(&pairs[s_ref], tot);
+        }
+    } else if (mine) {
+        atomicAdd(&pairs[s], mine);
+    }
+}
+
 template <typename T>
 struct NbrArgs {
     int N, Nf, C, cap;
@@ -250,6 +277,9 @@ struct NbrArgs {
     const uint32_t *cell_start;
     int *nbr;
     uint32_t *cnt;
+    int capc;
+    int *cand;
+    uint32_t *ccnt;
     void *prec;
     unsigned long long *pairs;
     int *flags;
@@ -279,8 +309,6 @@ __device__ inline void write_record<double>(const SimDev &S, void *prec, int i, 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
 {
-    __shared__ int s_ref;
-    __shared__ unsigned long long wsum[kThreads / 64];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = i < A.N;
     const int N = A.N;
@@ -289,7 +317,7 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
     int cf = 0, cw = 0;
     if (active) {
         const SimDev &S = A.sims[s];
-        const double kh2 = S.kh2;
+        const double kh2 = S.kh2, cr2 = S.cand_r2;
         const int px = S.periodic[0], py = S.periodic[1], pz = DIM == 3 ? S.periodic[2] : 0;
         const double Lx = S.L[0], Ly = S.L[1], Lz = S.L[2];
         const double hx = S.halfL[0], hy = S.halfL[1], hz = S.halfL[2];
@@ -313,11 +341,12 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
         else if (px && cx == nx - 1) { xa0 = nx - 2; xb0 = nx - 1; xa1 = xb1 = 0; }
         else { xa0 = cx > 0 ? cx - 1 : 0; xb0 = cx < nx - 1 ? cx + 1 : nx - 1; }
         const AxisRange ry(cy, ny, py), rz(cz, nz, pz);
-        const int cap = A.cap;
-        int total = 0;
+        const int cap = A.cap, capc = A.capc;
+        int *__restrict__ cand = A.cand;
+        int total = 0, ctotal = 0, ccf = 0, ccw = 0;
         for (int tp = 0; tp < (fluid ? 2 : 1); ++tp) {
             const int base = key_fluid + (tp ? A.C : 0);
-            int found = 0;
+            int found = 0, cfound = 0;
             for (int u = 0; u < rz.count; ++u)
                 for (int v = 0; v < ry.count; ++v) {
                     const int row = base + (rz.at(u) * ny + ry.at(v)) * nx;
@@ -331,41 +360,78 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
                             const double dy = min_image(yi - x1[j], py, Ly, hy);
                             const double dz = DIM == 3 ? min_image(zi - x2[j], pz, Lz, hz) : 0.0;
                             const double r2 = (dx * dx + dy * dy) + dz * dz;
-                            if (j == i || !(r2 < kh2)) continue;
+                            if (j == i || !(r2 < cr2)) continue;
+                            if (ctotal < capc) cand[(size_t)ctotal * N + i] = j;
+                            ++ctotal;
+                            ++cfound;
+                            if (!(r2 < kh2)) continue;
                             if (total < cap) nbr[(size_t)total * N + i] = j;
                             ++total;
                             ++found;
                         }
                     }
                 }
-            if (tp) cw = found;
-            else cf = found;
+            if (tp) { cw = found; ccw = cfound; }
+            else { cf = found; ccf = cfound; }
         }
-        if (total > cap) {
+        if (total > cap || ctotal > capc) {
             atomicOr(&A.flags[F_NBR_OVERFLOW], 1);
             atomicMax(&A.flags[F_NBR_NEEDED], total);
             cf = cf < cap ? cf : cap;
             cw = cap - cf < cw ? cap - cf : cw;
+            ccf = ccf < capc ? ccf : capc;
+            ccw = capc - ccf < ccw ? capc - ccf : ccw;
+        }
+        A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
+        A.ccnt[i] = (uint32_t)ccf | ((uint32_t)ccw << 16);
+    }
+    add_pairs((active && fluid) ? (unsigned long long)(cf + cw) : 0ull, s, A.pairs);
+}
+
+// Exact lists at the current positions from the candidate lists of the last
+// build (same predicate, same order), plus new position records.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kThreads) k_filter(NbrArgs<T> A)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < A.N;
+    const int N = A.N;
+    const int s = active ? A.simid[i] : -1;
+    const bool fluid = i < A.Nf;
+    int cf = 0, cw = 0;
+    if (active) {
+        const SimDev &S = A.sims[s];
+        const double kh2 = S.kh2;
+        const int px = S.periodic[0], py = S.periodic[1], pz = DIM == 3 ? S.periodic[2] : 0;
+        const double Lx = S.L[0], Ly = S.L[1], Lz = S.L[2];
+        const double hx = S.halfL[0], hy = S.halfL[1], hz = S.halfL[2];
+        const double *__restrict__ x0 = A.x;
+        const double *__restrict__ x1 = A.x + N;
+        const double *__restrict__ x2 = A.x + 2 * N;
+        const int *__restrict__ cand = A.cand + i;
+        int *__restrict__ nbr = A.nbr + i;
+        const double xi = x0[i], yi = x1[i], zi = DIM == 3 ? x2[i] : 0.0;
+        const double pos3[3] = {xi, yi, zi};
+        write_record<T>(S, A.prec, i, pos3);
+        const uint32_t cc = A.ccnt[i];
+        const int ncf = (int)(cc & 0xffffu), nct = ncf + (int)(cc >> 16);
+        int total = 0;
+        for (int k = 0; k < nct; ++k) {
+#pragma clang fp contract(off)
+            const int j = cand[(size_t)k * N];
+            const double dx = min_image(xi - x0[j], px, Lx, hx);
+            const double dy = min_image(yi - x1[j], py, Ly, hy);
+            const double dz = DIM == 3 ? min_image(zi - x2[j], pz, Lz, hz) : 0.0;
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            if (!(r2 < kh2)) continue;
+            nbr[(size_t)total * N] = j;  // never beyond the candidate count <= capacity
+            ++total;
+            if (k < ncf) ++cf;
+            else ++cw;
         }
         A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
     }
-    // pairs per sim: one atomic per block when the block's fluid rows share a sim
-    const unsigned long long mine = (active && fluid) ? (unsigned long long)(cf + cw) : 0ull;
-    if (threadIdx.x == 0) s_ref = s;
-    __syncthreads();
-    if (__syncthreads_and(mine == 0ull || s == s_ref)) {
-        unsigned long long v = mine;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long tot = 0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
-            if (tot) atomicAdd(&A.pairs[s_ref], tot);
-        }
-    } else if (mine) {
-        atomicAdd(&A.pairs[s], mine);
-    }
+    add_pairs((active && fluid) ? (unsigned long long)(cf + cw) : 0ull, s, A.pairs);
 }
 
 inline int grid_for(int n) { return n > 0 ? ceil_div(n, kThreads) : 1; }
@@ -399,6 +465,7 @@ void build_cells(Ctx &c)
     g.vn_in = (const T *)c.vn[b]; g.vn_out = (T *)c.vn[o];
     g.dv_in = (const T *)c.dv[b]; g.dv_out = (T *)c.dv[o];
     g.w_in = (const T *)c.w[b]; g.w_out = (T *)c.w[o];
+    g.w0_in = (const T *)c.w0[b]; g.w0_out = (T *)c.w0[o];
     g.dp_in = (const T *)c.dp[b]; g.dp_out = (T *)c.dp[o];
     g.pm_in = c.pm[b]; g.pm_out = c.pm[o];
     g.pn_in = c.pn[b]; g.pn_out = c.pn[o];
@@ -411,12 +478,39 @@ void build_cells(Ctx &c)
     a.N = N; a.Nf = c.Nf; a.C = c.C; a.cap = c.cap;
     a.x = c.x[c.xb]; a.simid = c.simid[o]; a.sims = c.sims; a.cell_start = c.cell_start;
     a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.pairs = c.pairs; a.flags = c.flags;
+    a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt;
     if (c.max_dim == 2) hipLaunchKernelGGL((k_nbr<T, 2>), dim3(grid_for(N)), dim3(kThreads), 0, st, a);
     else hipLaunchKernelGGL((k_nbr<T, 3>), dim3(grid_for(N)), dim3(kThreads), 0, st, a);
     DTSPH_HIP_CHECK(hipGetLastError());
     timer_end(c, t0, 2);
 }
 
+// Exact lists from the candidate lists (no sort); the per-sim pair counters
+// are cleared by a one-block kernel first.
+__global__ void k_zero_pairs(unsigned long long *pairs, int n)
+{
+    for (int q = threadIdx.x; q < n; q += blockDim.x) pairs[q] = 0ull;
+}
+
+template <typename T>
+void filter_lists(Ctx &c)
+{
+    const int N = c.N;
+    int t0 = timer_begin(c);
+    hipLaunchKernelGGL(k_zero_pairs, dim3(1), dim3(kThreads), 0, c.stream, c.pairs, c.n_sims);
+    NbrArgs<T> a;
+    a.N = N; a.Nf = c.Nf; a.C = c.C; a.cap = c.cap;
+    a.x = c.x[c.xb]; a.simid = c.simid[c.buf]; a.sims = c.sims; a.cell_start = c.cell_start;
+    a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.pairs = c.pairs; a.flags = c.flags;
+    a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt;
+    if (c.max_dim == 2) hipLaunchKernelGGL((k_filter<T, 2>), dim3(grid_for(N)), dim3(kThreads), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_filter<T, 3>), dim3(grid_for(N)), dim3(kThreads), 0, c.stream, a);
+    DTSPH_HIP_CHECK(hipGetLastError());
+    timer_end(c, t0, 2);
+}
+
+template void filter_lists<float>(Ctx &);
+template void filter_lists<double>(Ctx &);
 template void build_cells<float>(Ctx &);
 template void build_cells<double>(Ctx &);
 

@@ -47,6 +47,7 @@ struct SimDev {
     int edac_reg_literal;
     double lo[3], hi[3], L[3], halfL[3], cs[3], inv_cs[3];
     double kh2;          // (kappa h)^2, exact neighbour predicate
+    double skin, cand_r2; // candidate lists reach kappa h + skin (squared radius)
     double h, inv_h, rho0, mass, c, nu, nu_e;
     double g[3];
     double dt, dtau, gamma, inv2dt, tol, vref;
@@ -67,12 +68,13 @@ struct SimIter {
     int iters, done, reason, fixed;
     double hp[kHist], hv[kHist];
     double rp_mean, rv_mean, rp_max, rv_max;
+    double disp;   // max |r^{n+1} - r^(0)| = dt/2 max |V^{k} - V^(0)| at the last iteration
 };
 
 // Per-sim report as published to mapped host memory.
 struct MirrorRep {
     int iters, reason;
-    double rp_mean, rv_mean, rp_max, rv_max;
+    double rp_mean, rv_mean, rp_max, rv_max, disp;
 };
 
 // Context (host object owning device memory).
@@ -98,7 +100,9 @@ struct Ctx {
 
     // phase
     bool in_loop = false;
-    bool cells_valid = false;
+    bool cells_valid = false;  // exact lists match the current positions
+    bool cand_ok = false;      // candidate lists cover the current positions
+    bool cand_next = false;    // ... will cover r^{n+1} (decided by the loop)
     int cur = 0;             // which vp buffer is current
     int last_iters = 4;      // adaptive chunking
 
@@ -114,6 +118,7 @@ struct Ctx {
     void *vn[2] = {nullptr, nullptr};     // V^n (3 x Nf, type T)
     void *dv[2] = {nullptr, nullptr};     // V^n - V^{n-1}
     void *w[2] = {nullptr, nullptr};      // V^k - V^n
+    void *w0[2] = {nullptr, nullptr};     // V^(0) - V^n (predictor), for the skin test
     double *pm[2] = {nullptr, nullptr};   // p^n, or p^{k+1/2} inside the loop
     double *pn[2] = {nullptr, nullptr};   // p^n kept during the loop
     void *dp[2] = {nullptr, nullptr};     // (dp/dtau)^k (type T)
@@ -127,12 +132,16 @@ struct Ctx {
     uint32_t *count = nullptr, *cell_start = nullptr, *scan_tmp = nullptr;
     int *nbr = nullptr;
     uint32_t *cnt = nullptr;
+    int *cand = nullptr;                  // candidate lists (radius kappa h + skin)
+    uint32_t *ccnt = nullptr;
+    int capc = 0;
     unsigned long long *pairs = nullptr;  // per sim
     int2 *tiles = nullptr;
     int n_tiles = 0;
     int2 *wtiles = nullptr;
     int n_wtiles = 0;
     double4 *partials = nullptr;
+    double *partials2 = nullptr;          // per tile: max |V^{k+1} - V^(0)|^2
     int *flags = nullptr;
     int *done_dev = nullptr;
     int *init_slot = nullptr;             // caller index -> slot before any sort
@@ -158,6 +167,7 @@ struct Ctx {
 
 // ---- launchers (defined in the .hip files) ---------------------------------
 template <typename T> void build_cells(Ctx &c);        // dtsph_cells.hip
+template <typename T> void filter_lists(Ctx &c);
 template <typename T> void launch_pre_records(Ctx &c);
 template <typename T> void launch_wall(Ctx &c, int mode);
 template <typename T> void launch_pass(Ctx &c, int mode);

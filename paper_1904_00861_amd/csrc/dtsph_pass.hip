@@ -177,11 +177,12 @@ template <typename T> struct PassArgs {
     Q *vout;
     const T *vwall;
     const T *vn, *dv;
-    T *w, *dp;
+    T *w, *w0, *dp;
     double *pm, *pn;
     const double *x;
     double *x_alt, *xn;
     double4 *partials;
+    double *partials2;
 };
 
 template <typename T> __device__ inline void lane_sum(T &v, int lpp)
@@ -211,7 +212,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
 
     if (MODE == MODE_PSEUDO && A.iters[s].done) {  // uniform per block
         if (owner) A.vout[i] = A.vin[i];
-        if (threadIdx.x == 0) A.partials[t] = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (threadIdx.x == 0) { A.partials[t] = make_double4(0.0, 0.0, 0.0, 0.0); A.partials2[t] = 0.0; }
         return;
     }
 
@@ -269,7 +270,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
         }
     }
 
-    T Dv = 0, R[3] = {0, 0, 0}, vt2 = 0;
+    T Dv = 0, R[3] = {0, 0, 0}, vt2 = 0, dw2 = 0;
     if (owner) {
         Dv = (T)S.k_div * acc.div + (T)S.k_lap * acc.lap;
         for (int d = 0; d < DIM; ++d) R[d] = (T)S.k_grad * acc.grad[d] + (T)S.k_visc * acc.vis[d] + (T)S.g[d];
@@ -284,6 +285,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
                 const T wn = wk + dtau * dvdtau;
                 const T vt = dt * dvdtau;
                 vt2 += vt * vt;
+                const T dw = wn - A.w0[d * Nf + i];
+                dw2 += dw * dw;
                 A.w[d * Nf + i] = wn;
                 vnew[d] = A.vn[d * Nf + i] + wn;
             }
@@ -303,7 +306,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
                 }
                 A.x_alt[d * N + i] = x0;
                 A.xn[d * N + i] = xv;
-                A.w[d * Nf + i] = (T)(dt * (double)R[d]);
+                const T w0 = (T)(dt * (double)R[d]);
+                A.w[d * Nf + i] = w0;
+                A.w0[d * Nf + i] = w0;
             }
             if (DIM == 2) { A.x_alt[2 * N + i] = 0.0; A.xn[2 * N + i] = 0.0; }
             A.dp[i] = Dv;
@@ -313,28 +318,33 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
 
     if (MODE == MODE_PSEUDO) {
         // fixed-order block reduction of {sum |D|, sum |Vtilde|, max |D|, max |Vtilde|}
-        __shared__ double lds[kMaxBlock / 64][4];
+        __shared__ double lds[kMaxBlock / 64][5];
         double sd = owner ? fabs((double)Dv) : 0.0;
         double sv = owner ? sqrt((double)vt2) : 0.0;
-        double md = sd, mv = sv;
+        double md = sd, mv = sv, mw = owner ? (double)dw2 : 0.0;
         for (int o = 32; o > 0; o >>= 1) {
             sd += __shfl_xor(sd, o, 64);
             sv += __shfl_xor(sv, o, 64);
             md = fmax(md, __shfl_xor(md, o, 64));
             mv = fmax(mv, __shfl_xor(mv, o, 64));
+            mw = fmax(mw, __shfl_xor(mw, o, 64));
         }
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        if (lane == 0) { lds[wave][0] = sd; lds[wave][1] = sv; lds[wave][2] = md; lds[wave][3] = mv; }
+        if (lane == 0) {
+            lds[wave][0] = sd; lds[wave][1] = sv; lds[wave][2] = md; lds[wave][3] = mv; lds[wave][4] = mw;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
             for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) {
                 a0 += lds[wv][0];
                 a1 += lds[wv][1];
                 a2 = fmax(a2, lds[wv][2]);
                 a3 = fmax(a3, lds[wv][3]);
+                a4 = fmax(a4, lds[wv][4]);
             }
             A.partials[t] = make_double4(a0, a1, a2, a3);
+            A.partials2[t] = a4;
         }
     }
 }
@@ -421,9 +431,10 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
 
 // ---- residual reduction and stop test (section 3.4) --------------------------
 __global__ void __launch_bounds__(256) k_finalize(const SimDev *__restrict__ sims, SimIter *__restrict__ iters,
-                                                  const double4 *__restrict__ partials, int *__restrict__ done_out)
+                                                  const double4 *__restrict__ partials,
+                                                  const double *__restrict__ partials2, int *__restrict__ done_out)
 {
-    __shared__ double lds[4][4];
+    __shared__ double lds[4][5];
     const int s = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     SimIter &It = iters[s];
@@ -432,7 +443,7 @@ __global__ void __launch_bounds__(256) k_finalize(const SimDev *__restrict__ sim
         return;
     }
     const SimDev &S = sims[s];
-    double sd = 0, sv = 0, md = 0, mv = 0;
+    double sd = 0, sv = 0, md = 0, mv = 0, mw = 0;
     const int tb = S.tile_begin, te = S.tile_end;
 #pragma unroll 4
     for (int t = tb + (int)threadIdx.x; t < te; t += 256) {
@@ -441,23 +452,27 @@ __global__ void __launch_bounds__(256) k_finalize(const SimDev *__restrict__ sim
         sv += p.y;
         md = fmax(md, p.z);
         mv = fmax(mv, p.w);
+        mw = fmax(mw, partials2[t]);
     }
     for (int o = 32; o > 0; o >>= 1) {
         sd += __shfl_xor(sd, o, 64);
         sv += __shfl_xor(sv, o, 64);
         md = fmax(md, __shfl_xor(md, o, 64));
         mv = fmax(mv, __shfl_xor(mv, o, 64));
+        mw = fmax(mw, __shfl_xor(mw, o, 64));
     }
-    if (lane == 0) { lds[wave][0] = sd; lds[wave][1] = sv; lds[wave][2] = md; lds[wave][3] = mv; }
+    if (lane == 0) { lds[wave][0] = sd; lds[wave][1] = sv; lds[wave][2] = md; lds[wave][3] = mv; lds[wave][4] = mw; }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    sd = lds[0][0]; sv = lds[0][1]; md = lds[0][2]; mv = lds[0][3];
+    sd = lds[0][0]; sv = lds[0][1]; md = lds[0][2]; mv = lds[0][3]; mw = lds[0][4];
     for (int w = 1; w < 4; ++w) {
         sd += lds[w][0];
         sv += lds[w][1];
         md = fmax(md, lds[w][2]);
         mv = fmax(mv, lds[w][3]);
+        mw = fmax(mw, lds[w][4]);
     }
+    It.disp = 0.5 * S.dt * sqrt(mw);
     const double pscale = S.dt / (S.rho0 * S.c * S.c);
     const double rp = sd * S.res_p, rv = sv * S.res_v;
     const double rpx = md * pscale, rvx = mv / S.vref;
@@ -522,6 +537,7 @@ __global__ void k_publish(int n_sims, int *__restrict__ flags, const SimIter *__
         r.rv_mean = It.rv_mean;
         r.rp_max = It.rp_max;
         r.rv_max = It.rv_max;
+        r.disp = It.disp;
         h_reps[i] = r;
         h_pairs[i] = pairs[i];
     }
@@ -679,10 +695,11 @@ template <typename T> PassArgs<T> pass_args(Ctx &c)
     a.vout = (Q *)c.vp[c.cur ^ 1];
     a.vwall = (const T *)c.vw[b];
     a.vn = (const T *)c.vn[b]; a.dv = (const T *)c.dv[b];
-    a.w = (T *)c.w[b]; a.dp = (T *)c.dp[b];
+    a.w = (T *)c.w[b]; a.w0 = (T *)c.w0[b]; a.dp = (T *)c.dp[b];
     a.pm = c.pm[b]; a.pn = c.pn[b];
     a.x = c.x[c.xb]; a.x_alt = c.x[c.xb ^ 1]; a.xn = c.xn[b];
     a.partials = c.partials;
+    a.partials2 = c.partials2;
     return a;
 }
 
@@ -775,7 +792,8 @@ void launch_publish(Ctx &c)
 
 void launch_finalize(Ctx &c)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(c.n_sims), dim3(256), 0, c.stream, c.sims, c.iters, c.partials, c.done_dev);
+    hipLaunchKernelGGL(k_finalize, dim3(c.n_sims), dim3(256), 0, c.stream, c.sims, c.iters, c.partials, c.partials2,
+                       c.done_dev);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 

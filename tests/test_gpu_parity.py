@@ -275,3 +275,35 @@ def test_checkpoint_restart(prec):
     tol = 1e-11 if prec == "fp64" else 1e-4
     assert rel_l2(end["v"][:nf], full["v"][:nf]) <= tol
     assert rel_l2(end["p"][:nf], full["p"][:nf]) <= tol
+
+
+@pytest.mark.parametrize("case", ["tgv2d_50", "cavity_16", "dam_0.05", "tgv3d_10"])
+def test_filtered_neighbour_lists_stay_exact(case):
+    # after real steps the lists at r^{n+1} come from filtering the candidate lists
+    # of the r^(0) build; they must equal the definition at those positions
+    prob = CASES[case]()
+    banner(f"filtered lists {case}")
+    sim = D.Sim(prob, precision=D.FP32)
+    sim.step(3)
+    x = sim.get_state()["x"]
+    off, idx = sim.neighbor_list()
+    sim.close()
+    ob, ib = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, x, "brute")
+    assert np.array_equal(off, ob) and np.array_equal(idx, ib)
+
+
+def test_skin_zero_rebuilds_and_agrees():
+    prob = I.cavity(16)
+    banner("skin 0")
+    a = D.Sim(prob, precision=D.FP64)
+    a.step(4)
+    ga = a.get_state()
+    a.close()
+    b = D.Sim(prob, precision=D.FP64)
+    b.set_option(D.OPT_SKIN, 0)
+    b.step(4)
+    gb = b.get_state()
+    b.close()
+    nf = prob.n_fluid
+    assert rel_l2(ga["v"][:nf], gb["v"][:nf]) <= 1e-12
+    assert rel_l2(ga["p"][:nf], gb["p"][:nf]) <= 1e-12
