@@ -306,10 +306,26 @@ __device__ inline void write_record<double>(const SimDev &S, void *prec, int i, 
     ((double4 *)prec)[i] = make_double4(xi[0], xi[1], xi[2], 0.0);
 }
 
-template <typename T, int DIM>
+// G consecutive lanes share one particle and test its candidates G at a time;
+// a wave ballot gives each lane the number of accepted candidates before it in
+// the group, so the list keeps the sequential scan order.
+template <int G> struct Group {
+    int sub, g0;
+    __device__ Group() : sub((int)threadIdx.x & (G - 1)), g0((int)(threadIdx.x & 63) & ~(G - 1)) {}
+    // bits of the group's lanes for which pred holds (bit k = lane sub k)
+    __device__ unsigned bits(bool pred) const
+    {
+        const unsigned long long b = __ballot(pred);
+        return G == 64 ? 0u : (unsigned)(b >> g0) & ((1u << G) - 1u);
+    }
+    __device__ int before(unsigned gb) const { return __popc(gb & ((1u << sub) - 1u)); }
+};
+
+template <typename T, int DIM, int G>
 __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const Group<G> grp;
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / G;
     const bool active = i < A.N;
     const int N = A.N;
     const int s = active ? A.simid[i] : -1;
@@ -328,9 +344,12 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
         const double *__restrict__ x2 = A.x + 2 * N;
         const uint32_t *__restrict__ cstart = A.cell_start;
         int *__restrict__ nbr = A.nbr;
+        int *__restrict__ cand = A.cand;
         const double xi = x0[i], yi = x1[i], zi = DIM == 3 ? x2[i] : 0.0;
-        const double pos3[3] = {xi, yi, zi};
-        write_record<T>(S, A.prec, i, pos3);
+        if (grp.sub == 0) {
+            const double pos3[3] = {xi, yi, zi};
+            write_record<T>(S, A.prec, i, pos3);
+        }
         const int cx = cell_coord(xi, S.lo[0], S.inv_cs[0], nx);
         const int cy = cell_coord(yi, S.lo[1], S.inv_cs[1], ny);
         const int cz = DIM == 3 ? cell_coord(zi, S.lo[2], S.inv_cs[2], nz) : 0;
@@ -342,7 +361,6 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
         else { xa0 = cx > 0 ? cx - 1 : 0; xb0 = cx < nx - 1 ? cx + 1 : nx - 1; }
         const AxisRange ry(cy, ny, py), rz(cz, nz, pz);
         const int cap = A.cap, capc = A.capc;
-        int *__restrict__ cand = A.cand;
         int total = 0, ctotal = 0, ccf = 0, ccw = 0;
         for (int tp = 0; tp < (fluid ? 2 : 1); ++tp) {
             const int base = key_fluid + (tp ? A.C : 0);
@@ -354,20 +372,31 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
                         const int xa = run ? xa1 : xa0, xb = run ? xb1 : xb0;
                         if (xb < xa) continue;
                         const int jb = (int)cstart[row + xa], je = (int)cstart[row + xb + 1];
-                        for (int j = jb; j < je; ++j) {
+                        for (int j0 = jb; j0 < je; j0 += G) {
 #pragma clang fp contract(off)
-                            const double dx = min_image(xi - x0[j], px, Lx, hx);
-                            const double dy = min_image(yi - x1[j], py, Ly, hy);
-                            const double dz = DIM == 3 ? min_image(zi - x2[j], pz, Lz, hz) : 0.0;
-                            const double r2 = (dx * dx + dy * dy) + dz * dz;
-                            if (j == i || !(r2 < cr2)) continue;
-                            if (ctotal < capc) cand[(size_t)ctotal * N + i] = j;
-                            ++ctotal;
-                            ++cfound;
-                            if (!(r2 < kh2)) continue;
-                            if (total < cap) nbr[(size_t)total * N + i] = j;
-                            ++total;
-                            ++found;
+                            const int j = j0 + grp.sub;
+                            bool in_c = false, in_x = false;
+                            if (j < je && j != i) {
+                                const double dx = min_image(xi - x0[j], px, Lx, hx);
+                                const double dy = min_image(yi - x1[j], py, Ly, hy);
+                                const double dz = DIM == 3 ? min_image(zi - x2[j], pz, Lz, hz) : 0.0;
+                                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                                in_c = r2 < cr2;
+                                in_x = r2 < kh2;
+                            }
+                            const unsigned bc = grp.bits(in_c), bx = grp.bits(in_x);
+                            if (in_c) {
+                                const int q = ctotal + grp.before(bc);
+                                if (q < capc) cand[(size_t)q * N + i] = j;
+                            }
+                            if (in_x) {
+                                const int q = total + grp.before(bx);
+                                if (q < cap) nbr[(size_t)q * N + i] = j;
+                            }
+                            ctotal += __popc(bc);
+                            cfound += __popc(bc);
+                            total += __popc(bx);
+                            found += __popc(bx);
                         }
                     }
                 }
@@ -375,25 +404,30 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
             else { cf = found; ccf = cfound; }
         }
         if (total > cap || ctotal > capc) {
-            atomicOr(&A.flags[F_NBR_OVERFLOW], 1);
-            atomicMax(&A.flags[F_NBR_NEEDED], total);
+            if (grp.sub == 0) {
+                atomicOr(&A.flags[F_NBR_OVERFLOW], 1);
+                atomicMax(&A.flags[F_NBR_NEEDED], total > ctotal ? total : ctotal);
+            }
             cf = cf < cap ? cf : cap;
             cw = cap - cf < cw ? cap - cf : cw;
             ccf = ccf < capc ? ccf : capc;
             ccw = capc - ccf < ccw ? capc - ccf : ccw;
         }
-        A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
-        A.ccnt[i] = (uint32_t)ccf | ((uint32_t)ccw << 16);
+        if (grp.sub == 0) {
+            A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
+            A.ccnt[i] = (uint32_t)ccf | ((uint32_t)ccw << 16);
+        }
     }
-    add_pairs((active && fluid) ? (unsigned long long)(cf + cw) : 0ull, s, A.pairs);
+    add_pairs((active && fluid && grp.sub == 0) ? (unsigned long long)(cf + cw) : 0ull, s, A.pairs);
 }
 
 // Exact lists at the current positions from the candidate lists of the last
 // build (same predicate, same order), plus new position records.
-template <typename T, int DIM>
+template <typename T, int DIM, int G>
 __global__ void __launch_bounds__(kThreads) k_filter(NbrArgs<T> A)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const Group<G> grp;
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / G;
     const bool active = i < A.N;
     const int N = A.N;
     const int s = active ? A.simid[i] : -1;
@@ -411,30 +445,64 @@ __global__ void __launch_bounds__(kThreads) k_filter(NbrArgs<T> A)
         const int *__restrict__ cand = A.cand + i;
         int *__restrict__ nbr = A.nbr + i;
         const double xi = x0[i], yi = x1[i], zi = DIM == 3 ? x2[i] : 0.0;
-        const double pos3[3] = {xi, yi, zi};
-        write_record<T>(S, A.prec, i, pos3);
+        if (grp.sub == 0) {
+            const double pos3[3] = {xi, yi, zi};
+            write_record<T>(S, A.prec, i, pos3);
+        }
         const uint32_t cc = A.ccnt[i];
         const int ncf = (int)(cc & 0xffffu), nct = ncf + (int)(cc >> 16);
         int total = 0;
-        for (int k = 0; k < nct; ++k) {
+        for (int k0 = 0; k0 < nct; k0 += G) {  // same trip count for the whole group
 #pragma clang fp contract(off)
-            const int j = cand[(size_t)k * N];
-            const double dx = min_image(xi - x0[j], px, Lx, hx);
-            const double dy = min_image(yi - x1[j], py, Ly, hy);
-            const double dz = DIM == 3 ? min_image(zi - x2[j], pz, Lz, hz) : 0.0;
-            const double r2 = (dx * dx + dy * dy) + dz * dz;
-            if (!(r2 < kh2)) continue;
-            nbr[(size_t)total * N] = j;  // never beyond the candidate count <= capacity
-            ++total;
-            if (k < ncf) ++cf;
-            else ++cw;
+            const int k = k0 + grp.sub;
+            bool in_x = false;
+            int j = 0;
+            if (k < nct) {
+                j = cand[(size_t)k * N];
+                const double dx = min_image(xi - x0[j], px, Lx, hx);
+                const double dy = min_image(yi - x1[j], py, Ly, hy);
+                const double dz = DIM == 3 ? min_image(zi - x2[j], pz, Lz, hz) : 0.0;
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                in_x = r2 < kh2;
+            }
+            const unsigned bx = grp.bits(in_x), bf = grp.bits(in_x && k < ncf);
+            // the exact list is a subset of the candidates, so it fits the capacity
+            if (in_x) nbr[(size_t)(total + grp.before(bx)) * N] = j;
+            total += __popc(bx);
+            cf += __popc(bf);
         }
-        A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
+        cw = total - cf;
+        if (grp.sub == 0) A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
     }
-    add_pairs((active && fluid) ? (unsigned long long)(cf + cw) : 0ull, s, A.pairs);
+    add_pairs((active && fluid && grp.sub == 0) ? (unsigned long long)(cf + cw) : 0ull, s, A.pairs);
 }
 
 inline int grid_for(int n) { return n > 0 ? ceil_div(n, kThreads) : 1; }
+
+template <typename T, int DIM, int G> void launch_g(Ctx &c, const NbrArgs<T> &a, bool filter)
+{
+    const dim3 grid(grid_for((int)std::min<int64_t>((int64_t)a.N * G, INT32_MAX)));
+    if (filter) hipLaunchKernelGGL((k_filter<T, DIM, G>), grid, dim3(kThreads), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_nbr<T, DIM, G>), grid, dim3(kThreads), 0, c.stream, a);
+}
+
+// lanes per particle in the neighbour kernels: enough threads for ~8 waves per SIMD
+template <typename T> void launch_grouped(Ctx &c, const NbrArgs<T> &a, bool filter)
+{
+    int g = 1;
+    while (g < 8 && (int64_t)g * a.N < (int64_t)256 * 2048) g *= 2;
+    if (c.max_dim == 2) {
+        if (g == 1) launch_g<T, 2, 1>(c, a, filter);
+        else if (g == 2) launch_g<T, 2, 2>(c, a, filter);
+        else if (g == 4) launch_g<T, 2, 4>(c, a, filter);
+        else launch_g<T, 2, 8>(c, a, filter);
+    } else {
+        if (g == 1) launch_g<T, 3, 1>(c, a, filter);
+        else if (g == 2) launch_g<T, 3, 2>(c, a, filter);
+        else if (g == 4) launch_g<T, 3, 4>(c, a, filter);
+        else launch_g<T, 3, 8>(c, a, filter);
+    }
+}
 
 }  // namespace
 
@@ -479,8 +547,7 @@ void build_cells(Ctx &c)
     a.x = c.x[c.xb]; a.simid = c.simid[o]; a.sims = c.sims; a.cell_start = c.cell_start;
     a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.pairs = c.pairs; a.flags = c.flags;
     a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt;
-    if (c.max_dim == 2) hipLaunchKernelGGL((k_nbr<T, 2>), dim3(grid_for(N)), dim3(kThreads), 0, st, a);
-    else hipLaunchKernelGGL((k_nbr<T, 3>), dim3(grid_for(N)), dim3(kThreads), 0, st, a);
+    launch_grouped<T>(c, a, false);
     DTSPH_HIP_CHECK(hipGetLastError());
     timer_end(c, t0, 2);
 }
@@ -503,8 +570,7 @@ void filter_lists(Ctx &c)
     a.x = c.x[c.xb]; a.simid = c.simid[c.buf]; a.sims = c.sims; a.cell_start = c.cell_start;
     a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.pairs = c.pairs; a.flags = c.flags;
     a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt;
-    if (c.max_dim == 2) hipLaunchKernelGGL((k_filter<T, 2>), dim3(grid_for(N)), dim3(kThreads), 0, c.stream, a);
-    else hipLaunchKernelGGL((k_filter<T, 3>), dim3(grid_for(N)), dim3(kThreads), 0, c.stream, a);
+    launch_grouped<T>(c, a, true);
     DTSPH_HIP_CHECK(hipGetLastError());
     timer_end(c, t0, 2);
 }
