@@ -223,6 +223,7 @@ template <typename T> void alloc_state(Ctx &c)
         c.vp[b] = dev_alloc(c, sizeof(T) * 4 * N);
     }
     c.prec = dev_alloc(c, (sizeof(T) == 4 ? 16 : 32) * N);
+    c.xr = dev_alloc(c, 32 * N);
 }
 
 // ---- timing -------------------------------------------------------------------

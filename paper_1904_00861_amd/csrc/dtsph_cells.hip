@@ -160,6 +160,8 @@ struct GatherArgs {
     int *orig_out, *simid_out;
     const double *x_in, *xn_in;
     double *x_out, *xn_out;
+    void *xr;
+    int dim;
     const T *vn_in, *dv_in, *w_in, *w0_in, *dp_in;
     T *vn_out, *dv_out, *w_out, *w0_out, *dp_out;
     const double *pm_in, *pn_in;
@@ -195,6 +197,8 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
         A.x_out[a * N + d] = A.x_in[a * N + s];
         A.xn_out[a * N + d] = A.xn_in[a * N + s];
     }
+    if (A.dim == 2) ((double2 *)A.xr)[d] = make_double2(A.x_in[s], A.x_in[N + s]);
+    else ((double4 *)A.xr)[d] = make_double4(A.x_in[s], A.x_in[N + s], A.x_in[2 * N + s], 0.0);
     if (d < Nf) {
         for (int a = 0; a < 3; ++a) {
             A.vn_out[a * Nf + d] = A.vn_in[a * Nf + s];
@@ -216,12 +220,24 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
 // as (dx*dx + dy*dy) + dz*dz in float64 without contraction, strict < (kh)^2.
 __device__ inline double min_image(double s, int per, double L, double halfL)
 {
-    if (per) {
-        if (s > halfL) s -= L;
-        else if (s < -halfL) s += L;
-    }
-    return s;
+    // s - L, s + L or s, selected without branches (same roundings as the
+    // conditional subtraction/addition)
+    const double sh = s > halfL ? -L : (s < -halfL ? L : 0.0);
+    return s + (per ? sh : 0.0);
 }
+
+// packed positions: xr[i] = (x, y) in 2D, (x, y, z, 0) in 3D
+template <int DIM> struct XR;
+template <> struct XR<2> {
+    using type = double2;
+    __device__ static double z(const double2 &) { return 0.0; }
+    __device__ static double2 make(double x, double y, double) { return make_double2(x, y); }
+};
+template <> struct XR<3> {
+    using type = double4;
+    __device__ static double z(const double4 &v) { return v.z; }
+    __device__ static double4 make(double x, double y, double z) { return make_double4(x, y, z, 0.0); }
+};
 
 // Cells along one axis whose particles can be neighbours of a particle in cell
 // c: c-1, c, c+1, wrapped on periodic axes, clipped on others; a periodic axis
@@ -272,6 +288,7 @@ template <typename T>
 struct NbrArgs {
     int N, Nf, C, cap;
     const double *x;
+    const void *xr;
     const int *simid;
     const SimDev *sims;
     const uint32_t *cell_start;
@@ -321,9 +338,38 @@ template <int G> struct Group {
     __device__ int before(unsigned gb) const { return __popc(gb & ((1u << sub) - 1u)); }
 };
 
+// Candidates are taken U at a time per lane: all U position loads are in
+// flight before the first test, and list writes happen after the batch.
+constexpr int kBatch = 8;
+
+template <int DIM> struct Probe {
+    double xi, yi, zi, kh2;
+    int px, py, pz;
+    double Lx, Ly, Lz, hx, hy, hz;
+    __device__ double r2(const typename XR<DIM>::type &q) const
+    {
+#pragma clang fp contract(off)
+        const double dx = min_image(xi - q.x, px, Lx, hx);
+        const double dy = min_image(yi - q.y, py, Ly, hy);
+        const double dz = DIM == 3 ? min_image(zi - XR<DIM>::z(q), pz, Lz, hz) : 0.0;
+        return (dx * dx + dy * dy) + dz * dz;
+    }
+};
+
+template <int DIM> __device__ inline Probe<DIM> make_probe(const SimDev &S, double xi, double yi, double zi)
+{
+    Probe<DIM> P;
+    P.xi = xi; P.yi = yi; P.zi = zi; P.kh2 = S.kh2;
+    P.px = S.periodic[0]; P.py = S.periodic[1]; P.pz = DIM == 3 ? S.periodic[2] : 0;
+    P.Lx = S.L[0]; P.Ly = S.L[1]; P.Lz = S.L[2];
+    P.hx = S.halfL[0]; P.hy = S.halfL[1]; P.hz = S.halfL[2];
+    return P;
+}
+
 template <typename T, int DIM, int G>
 __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
 {
+    using Q = typename XR<DIM>::type;
     const Group<G> grp;
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) / G;
     const bool active = i < A.N;
@@ -333,37 +379,32 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
     int cf = 0, cw = 0;
     if (active) {
         const SimDev &S = A.sims[s];
-        const double kh2 = S.kh2, cr2 = S.cand_r2;
-        const int px = S.periodic[0], py = S.periodic[1], pz = DIM == 3 ? S.periodic[2] : 0;
-        const double Lx = S.L[0], Ly = S.L[1], Lz = S.L[2];
-        const double hx = S.halfL[0], hy = S.halfL[1], hz = S.halfL[2];
+        const Q *__restrict__ xr = (const Q *)A.xr;
+        const Q me = xr[i];
+        const Probe<DIM> P = make_probe<DIM>(S, me.x, me.y, XR<DIM>::z(me));
+        const double cr2 = S.cand_r2;
         const int nx = S.ncell[0], ny = S.ncell[1], nz = DIM == 3 ? S.ncell[2] : 1;
-        const int key_fluid = S.key_base;
-        const double *__restrict__ x0 = A.x;
-        const double *__restrict__ x1 = A.x + N;
-        const double *__restrict__ x2 = A.x + 2 * N;
         const uint32_t *__restrict__ cstart = A.cell_start;
         int *__restrict__ nbr = A.nbr;
         int *__restrict__ cand = A.cand;
-        const double xi = x0[i], yi = x1[i], zi = DIM == 3 ? x2[i] : 0.0;
         if (grp.sub == 0) {
-            const double pos3[3] = {xi, yi, zi};
+            const double pos3[3] = {P.xi, P.yi, P.zi};
             write_record<T>(S, A.prec, i, pos3);
         }
-        const int cx = cell_coord(xi, S.lo[0], S.inv_cs[0], nx);
-        const int cy = cell_coord(yi, S.lo[1], S.inv_cs[1], ny);
-        const int cz = DIM == 3 ? cell_coord(zi, S.lo[2], S.inv_cs[2], nz) : 0;
+        const int cx = cell_coord(P.xi, S.lo[0], S.inv_cs[0], nx);
+        const int cy = cell_coord(P.yi, S.lo[1], S.inv_cs[1], ny);
+        const int cz = DIM == 3 ? cell_coord(P.zi, S.lo[2], S.inv_cs[2], nz) : 0;
         // x cells as at most two contiguous runs of keys
         int xa0, xb0, xa1 = 0, xb1 = -1;
-        if (px && nx < 3) { xa0 = 0; xb0 = nx - 1; }
-        else if (px && cx == 0) { xa0 = 0; xb0 = 1; xa1 = xb1 = nx - 1; }
-        else if (px && cx == nx - 1) { xa0 = nx - 2; xb0 = nx - 1; xa1 = xb1 = 0; }
+        if (P.px && nx < 3) { xa0 = 0; xb0 = nx - 1; }
+        else if (P.px && cx == 0) { xa0 = 0; xb0 = 1; xa1 = xb1 = nx - 1; }
+        else if (P.px && cx == nx - 1) { xa0 = nx - 2; xb0 = nx - 1; xa1 = xb1 = 0; }
         else { xa0 = cx > 0 ? cx - 1 : 0; xb0 = cx < nx - 1 ? cx + 1 : nx - 1; }
-        const AxisRange ry(cy, ny, py), rz(cz, nz, pz);
+        const AxisRange ry(cy, ny, P.py), rz(cz, nz, P.pz);
         const int cap = A.cap, capc = A.capc;
         int total = 0, ctotal = 0, ccf = 0, ccw = 0;
         for (int tp = 0; tp < (fluid ? 2 : 1); ++tp) {
-            const int base = key_fluid + (tp ? A.C : 0);
+            const int base = S.key_base + (tp ? A.C : 0);
             int found = 0, cfound = 0;
             for (int u = 0; u < rz.count; ++u)
                 for (int v = 0; v < ry.count; ++v) {
@@ -372,31 +413,33 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
                         const int xa = run ? xa1 : xa0, xb = run ? xb1 : xb0;
                         if (xb < xa) continue;
                         const int jb = (int)cstart[row + xa], je = (int)cstart[row + xb + 1];
-                        for (int j0 = jb; j0 < je; j0 += G) {
-#pragma clang fp contract(off)
-                            const int j = j0 + grp.sub;
-                            bool in_c = false, in_x = false;
-                            if (j < je && j != i) {
-                                const double dx = min_image(xi - x0[j], px, Lx, hx);
-                                const double dy = min_image(yi - x1[j], py, Ly, hy);
-                                const double dz = DIM == 3 ? min_image(zi - x2[j], pz, Lz, hz) : 0.0;
-                                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                                in_c = r2 < cr2;
-                                in_x = r2 < kh2;
+                        for (int j0 = jb; j0 < je; j0 += G * kBatch) {  // uniform in the group
+                            Q q[kBatch];
+#pragma unroll
+                            for (int m = 0; m < kBatch; ++m) {
+                                const int j = j0 + m * G + grp.sub;
+                                q[m] = xr[j < je ? j : jb];
                             }
-                            const unsigned bc = grp.bits(in_c), bx = grp.bits(in_x);
-                            if (in_c) {
-                                const int q = ctotal + grp.before(bc);
-                                if (q < capc) cand[(size_t)q * N + i] = j;
+#pragma unroll
+                            for (int m = 0; m < kBatch; ++m) {
+                                const int j = j0 + m * G + grp.sub;
+                                const double r2 = P.r2(q[m]);
+                                const bool ok = j < je && j != i;
+                                const bool in_c = ok && r2 < cr2, in_x = ok && r2 < P.kh2;
+                                const unsigned bc = grp.bits(in_c), bx = grp.bits(in_x);
+                                if (in_c) {
+                                    const int qq = ctotal + grp.before(bc);
+                                    if (qq < capc) cand[(size_t)qq * N + i] = j;
+                                }
+                                if (in_x) {
+                                    const int qq = total + grp.before(bx);
+                                    if (qq < cap) nbr[(size_t)qq * N + i] = j;
+                                }
+                                ctotal += __popc(bc);
+                                cfound += __popc(bc);
+                                total += __popc(bx);
+                                found += __popc(bx);
                             }
-                            if (in_x) {
-                                const int q = total + grp.before(bx);
-                                if (q < cap) nbr[(size_t)q * N + i] = j;
-                            }
-                            ctotal += __popc(bc);
-                            cfound += __popc(bc);
-                            total += __popc(bx);
-                            found += __popc(bx);
                         }
                     }
                 }
@@ -426,6 +469,7 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
 template <typename T, int DIM, int G>
 __global__ void __launch_bounds__(kThreads) k_filter(NbrArgs<T> A)
 {
+    using Q = typename XR<DIM>::type;
     const Group<G> grp;
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) / G;
     const bool active = i < A.N;
@@ -435,41 +479,38 @@ __global__ void __launch_bounds__(kThreads) k_filter(NbrArgs<T> A)
     int cf = 0, cw = 0;
     if (active) {
         const SimDev &S = A.sims[s];
-        const double kh2 = S.kh2;
-        const int px = S.periodic[0], py = S.periodic[1], pz = DIM == 3 ? S.periodic[2] : 0;
-        const double Lx = S.L[0], Ly = S.L[1], Lz = S.L[2];
-        const double hx = S.halfL[0], hy = S.halfL[1], hz = S.halfL[2];
-        const double *__restrict__ x0 = A.x;
-        const double *__restrict__ x1 = A.x + N;
-        const double *__restrict__ x2 = A.x + 2 * N;
+        const Q *__restrict__ xr = (const Q *)A.xr;
+        const Q me = xr[i];
+        const Probe<DIM> P = make_probe<DIM>(S, me.x, me.y, XR<DIM>::z(me));
         const int *__restrict__ cand = A.cand + i;
         int *__restrict__ nbr = A.nbr + i;
-        const double xi = x0[i], yi = x1[i], zi = DIM == 3 ? x2[i] : 0.0;
         if (grp.sub == 0) {
-            const double pos3[3] = {xi, yi, zi};
+            const double pos3[3] = {P.xi, P.yi, P.zi};
             write_record<T>(S, A.prec, i, pos3);
         }
         const uint32_t cc = A.ccnt[i];
         const int ncf = (int)(cc & 0xffffu), nct = ncf + (int)(cc >> 16);
         int total = 0;
-        for (int k0 = 0; k0 < nct; k0 += G) {  // same trip count for the whole group
-#pragma clang fp contract(off)
-            const int k = k0 + grp.sub;
-            bool in_x = false;
-            int j = 0;
-            if (k < nct) {
-                j = cand[(size_t)k * N];
-                const double dx = min_image(xi - x0[j], px, Lx, hx);
-                const double dy = min_image(yi - x1[j], py, Ly, hy);
-                const double dz = DIM == 3 ? min_image(zi - x2[j], pz, Lz, hz) : 0.0;
-                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                in_x = r2 < kh2;
+        for (int k0 = 0; k0 < nct; k0 += G * kBatch) {  // same trip count for the whole group
+            int jj[kBatch];
+            Q q[kBatch];
+#pragma unroll
+            for (int m = 0; m < kBatch; ++m) {
+                const int k = k0 + m * G + grp.sub;
+                jj[m] = k < nct ? cand[(size_t)k * N] : i;
             }
-            const unsigned bx = grp.bits(in_x), bf = grp.bits(in_x && k < ncf);
-            // the exact list is a subset of the candidates, so it fits the capacity
-            if (in_x) nbr[(size_t)(total + grp.before(bx)) * N] = j;
-            total += __popc(bx);
-            cf += __popc(bf);
+#pragma unroll
+            for (int m = 0; m < kBatch; ++m) q[m] = xr[jj[m]];
+#pragma unroll
+            for (int m = 0; m < kBatch; ++m) {
+                const int k = k0 + m * G + grp.sub;
+                const bool in_x = k < nct && P.r2(q[m]) < P.kh2;
+                const unsigned bx = grp.bits(in_x), bf = grp.bits(in_x && k < ncf);
+                // the exact list is a subset of the candidates, so it fits the capacity
+                if (in_x) nbr[(size_t)(total + grp.before(bx)) * N] = jj[m];
+                total += __popc(bx);
+                cf += __popc(bf);
+            }
         }
         cw = total - cf;
         if (grp.sub == 0) A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
@@ -530,6 +571,7 @@ void build_cells(Ctx &c)
     g.simid_in = c.simid[b]; g.simid_out = c.simid[o];
     g.x_in = c.x[c.xb]; g.x_out = c.x[c.xb ^ 1];
     g.xn_in = c.xn[b]; g.xn_out = c.xn[o];
+    g.xr = c.xr; g.dim = c.max_dim;
     g.vn_in = (const T *)c.vn[b]; g.vn_out = (T *)c.vn[o];
     g.dv_in = (const T *)c.dv[b]; g.dv_out = (T *)c.dv[o];
     g.w_in = (const T *)c.w[b]; g.w_out = (T *)c.w[o];
@@ -546,7 +588,7 @@ void build_cells(Ctx &c)
     a.N = N; a.Nf = c.Nf; a.C = c.C; a.cap = c.cap;
     a.x = c.x[c.xb]; a.simid = c.simid[o]; a.sims = c.sims; a.cell_start = c.cell_start;
     a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.pairs = c.pairs; a.flags = c.flags;
-    a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt;
+    a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt; a.xr = c.xr;
     launch_grouped<T>(c, a, false);
     DTSPH_HIP_CHECK(hipGetLastError());
     timer_end(c, t0, 2);
@@ -569,7 +611,7 @@ void filter_lists(Ctx &c)
     a.N = N; a.Nf = c.Nf; a.C = c.C; a.cap = c.cap;
     a.x = c.x[c.xb]; a.simid = c.simid[c.buf]; a.sims = c.sims; a.cell_start = c.cell_start;
     a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.pairs = c.pairs; a.flags = c.flags;
-    a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt;
+    a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt; a.xr = c.xr;
     launch_grouped<T>(c, a, true);
     DTSPH_HIP_CHECK(hipGetLastError());
     timer_end(c, t0, 2);

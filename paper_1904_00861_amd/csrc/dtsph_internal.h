@@ -115,6 +115,8 @@ struct Ctx {
     int *simid[2] = {nullptr, nullptr};
     double *x[2] = {nullptr, nullptr};    // active positions (3 x N SoA)
     double *xn[2] = {nullptr, nullptr};   // r^n during the loop (3 x N)
+    void *xr = nullptr;                   // packed float64 positions for the neighbour
+                                          // kernels (double2 in 2D, double4 in 3D)
     void *vn[2] = {nullptr, nullptr};     // V^n (3 x Nf, type T)
     void *dv[2] = {nullptr, nullptr};     // V^n - V^{n-1}
     void *w[2] = {nullptr, nullptr};      // V^k - V^n

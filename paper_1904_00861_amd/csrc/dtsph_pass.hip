@@ -233,8 +233,32 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
         const uint32_t cn = A.cnt[i];
         const int nfl = (int)(cn & 0xffffu), nwl = (int)(cn >> 16);
         const int *__restrict__ nb = A.nbr + i;
-#pragma unroll 2
-        for (int k = sub; k < nfl; k += LPP) {
+        // fluid neighbours in batches of U: U index loads, then 2U record
+        // gathers in flight, then U pair evaluations
+        constexpr int U = sizeof(T) == 4 ? 4 : 2;
+        int k = sub;
+        for (; k + (U - 1) * LPP < nfl; k += U * LPP) {
+            int jj[U];
+#pragma unroll
+            for (int m = 0; m < U; ++m) jj[m] = nb[(size_t)(k + m * LPP) * N];
+            Rec rj[U];
+            Q vj[U];
+#pragma unroll
+            for (int m = 0; m < U; ++m) {
+                rj[m] = prec[jj[m]];
+                vj[m] = vin[jj[m]];
+            }
+#pragma unroll
+            for (int m = 0; m < U; ++m) {
+                T r[3], vd[3];
+                pos.delta(ri, rj[m], r);
+                vd[0] = vi[0] - vj[m].x;
+                vd[1] = vi[1] - vj[m].y;
+                vd[2] = DIM == 3 ? vi[2] - vj[m].z : T(0);
+                pair_terms<T, DIM, AV, SEPDEN>(K, r, vd, vd, pi, pres<DIM>(vj[m]), acc);
+            }
+        }
+        for (; k < nfl; k += LPP) {
             const int j = nb[(size_t)k * N];
             const Rec rj = prec[j];
             const Q vj = vin[j];
@@ -583,11 +607,12 @@ __global__ void k_loop_end(int Nf, const int *__restrict__ simid, const SimDev *
 template <typename T>
 __global__ void k_correct(int N, int Nf, const int *__restrict__ simid, const SimDev *__restrict__ sims,
                           double *__restrict__ x, const double *__restrict__ xn, T *__restrict__ vn,
-                          T *__restrict__ dv, T *__restrict__ w)
+                          T *__restrict__ dv, T *__restrict__ w, void *__restrict__ xr)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Nf) return;
     const SimDev &S = sims[simid[i]];
+    double xo[3] = {0.0, 0.0, 0.0};
     for (int d = 0; d < S.dim; ++d) {
         const T v0 = vn[d * Nf + i];
         const T v1 = v0 + w[d * Nf + i];
@@ -597,10 +622,13 @@ __global__ void k_correct(int N, int Nf, const int *__restrict__ simid, const Si
             else if (xv < S.lo[d]) xv += S.L[d];
         }
         x[d * N + i] = xv;
+        xo[d] = xv;
         dv[d * Nf + i] = v1 - v0;
         vn[d * Nf + i] = v1;
         w[d * Nf + i] = T(0);
     }
+    if (S.dim == 2) ((double2 *)xr)[i] = make_double2(xo[0], xo[1]);
+    else ((double4 *)xr)[i] = make_double4(xo[0], xo[1], xo[2], 0.0);
 }
 
 template <typename T>
@@ -840,7 +868,7 @@ void launch_correct(Ctx &c)
 {
     const int b = c.buf;
     hipLaunchKernelGGL(k_correct<T>, dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.N, c.Nf, c.simid[b], c.sims,
-                       c.x[c.xb], c.xn[b], (T *)c.vn[b], (T *)c.dv[b], (T *)c.w[b]);
+                       c.x[c.xb], c.xn[b], (T *)c.vn[b], (T *)c.dv[b], (T *)c.w[b], c.xr);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
