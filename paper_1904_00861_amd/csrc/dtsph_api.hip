@@ -494,7 +494,6 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         c.capc = c.cap;
         c.cand = (int *)dev_alloc(c, 4 * (size_t)c.capc * (size_t)N);
         c.ccnt = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
-        c.pairs = (unsigned long long *)dev_alloc(c, 8 * (size_t)n_sims);
         // lanes per particle: enough threads for ~8 waves per SIMD on 256 CUs
         {
             int lpp = 1;
@@ -510,7 +509,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         const size_t max_tiles = (size_t)(Nf + n_sims + 8);
         c.tiles = (int2 *)dev_alloc(c, sizeof(int2) * max_tiles);
         c.partials = (double4 *)dev_alloc(c, sizeof(double4) * max_tiles);
-        c.partials2 = (double *)dev_alloc(c, sizeof(double) * max_tiles);
+        c.partials2 = (double2 *)dev_alloc(c, sizeof(double2) * max_tiles);
         c.flags = (int *)dev_alloc(c, sizeof(int) * (F_COUNT + n_sims));
         c.done_dev = c.flags + F_COUNT;
         c.init_slot = (int *)dev_alloc(c, sizeof(int) * 2 * (size_t)N);
@@ -535,7 +534,6 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         DTSPH_HIP_CHECK(hipMemset(c.cell_start, 0, 4 * (size_t)(2 * C + 1)));
         DTSPH_HIP_CHECK(hipMemset(c.count, 0, 4 * (size_t)(2 * C)));
         DTSPH_HIP_CHECK(hipMemset(c.cnt, 0, 4 * (size_t)N));
-        DTSPH_HIP_CHECK(hipMemset(c.pairs, 0, 8 * (size_t)n_sims));
         setup_tiles(c);
         DTSPH_HIP_CHECK(hipDeviceSynchronize());
         *out = ctx;

@@ -108,11 +108,10 @@ __global__ void k_scan_reduce(const uint32_t *__restrict__ in, int n, uint32_t *
 
 // Block b adds the sums of blocks 0..b-1 (read directly: there are at most a few
 // hundred), scans its own tile, writes the cell-start table, and leaves the
-// counts (and the per-sim pair counters) zeroed for the next build.
+// counts zeroed for the next build.
 __global__ void __launch_bounds__(kThreads) k_scan_down(uint32_t *__restrict__ in, int n,
                                                         const uint32_t *__restrict__ sums,
-                                                        uint32_t *__restrict__ out,
-                                                        unsigned long long *__restrict__ pairs, int n_sims)
+                                                        uint32_t *__restrict__ out)
 {
     __shared__ uint32_t lds[kThreads / 64];
     uint32_t before = 0;
@@ -136,8 +135,6 @@ __global__ void __launch_bounds__(kThreads) k_scan_down(uint32_t *__restrict__ i
         run += v[k];
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) out[n] = run;
-    if (blockIdx.x == 0)
-        for (int q = threadIdx.x; q < n_sims; q += blockDim.x) pairs[q] = 0ull;
 }
 
 __global__ void k_scatter(int N, const uint32_t *__restrict__ key, const uint32_t *__restrict__ rank,
@@ -262,28 +259,6 @@ struct AxisRange {
     }
 };
 
-// Pairs per sim: one atomic per block when the block's fluid rows share a sim.
-__device__ inline void add_pairs(unsigned long long mine, int s, unsigned long long *pairs)
-{
-    __shared__ int s_ref;
-    __shared__ unsigned long long wsum[kThreads / 64];
-    if (threadIdx.x == 0) s_ref = s;
-    __syncthreads();
-    if (__syncthreads_and(mine == 0ull || s == s_ref)) {
-        unsigned long long v = mine;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long tot = 0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
-            if (tot) atomicAdd(&pairs[s_ref], tot);
-        }
-    } else if (mine) {
-        atomicAdd(&pairs[s], mine);
-    }
-}
-
 template <typename T>
 struct NbrArgs {
     int N, Nf, C, cap;
@@ -298,7 +273,7 @@ struct NbrArgs {
     int *cand;
     uint32_t *ccnt;
     void *prec;
-    unsigned long long *pairs;
+
     int *flags;
 };
 
@@ -461,7 +436,6 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
             A.ccnt[i] = (uint32_t)ccf | ((uint32_t)ccw << 16);
         }
     }
-    add_pairs((active && fluid && grp.sub == 0) ? (unsigned long long)(cf + cw) : 0ull, s, A.pairs);
 }
 
 // Exact lists at the current positions from the candidate lists of the last
@@ -515,7 +489,6 @@ __global__ void __launch_bounds__(kThreads) k_filter(NbrArgs<T> A)
         cw = total - cf;
         if (grp.sub == 0) A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
     }
-    add_pairs((active && fluid && grp.sub == 0) ? (unsigned long long)(cf + cw) : 0ull, s, A.pairs);
 }
 
 inline int grid_for(int n) { return n > 0 ? ceil_div(n, kThreads) : 1; }
@@ -559,7 +532,7 @@ void build_cells(Ctx &c)
     const int nblk = ceil_div(nkeys, kScanTile);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kThreads), 0, st, c.count, nkeys, c.scan_tmp);
     hipLaunchKernelGGL(k_scan_down, dim3(nblk), dim3(kThreads), 0, st, c.count, nkeys, c.scan_tmp,
-                       c.cell_start, c.pairs, c.n_sims);
+                       c.cell_start);
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.key, c.rank, c.cell_start,
                        c.perm);
     GatherArgs<T> g;
@@ -587,30 +560,23 @@ void build_cells(Ctx &c)
     NbrArgs<T> a;
     a.N = N; a.Nf = c.Nf; a.C = c.C; a.cap = c.cap;
     a.x = c.x[c.xb]; a.simid = c.simid[o]; a.sims = c.sims; a.cell_start = c.cell_start;
-    a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.pairs = c.pairs; a.flags = c.flags;
+    a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.flags = c.flags;
     a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt; a.xr = c.xr;
     launch_grouped<T>(c, a, false);
     DTSPH_HIP_CHECK(hipGetLastError());
     timer_end(c, t0, 2);
 }
 
-// Exact lists from the candidate lists (no sort); the per-sim pair counters
-// are cleared by a one-block kernel first.
-__global__ void k_zero_pairs(unsigned long long *pairs, int n)
-{
-    for (int q = threadIdx.x; q < n; q += blockDim.x) pairs[q] = 0ull;
-}
-
+// Exact lists from the candidate lists (no sort).
 template <typename T>
 void filter_lists(Ctx &c)
 {
     const int N = c.N;
     int t0 = timer_begin(c);
-    hipLaunchKernelGGL(k_zero_pairs, dim3(1), dim3(kThreads), 0, c.stream, c.pairs, c.n_sims);
     NbrArgs<T> a;
     a.N = N; a.Nf = c.Nf; a.C = c.C; a.cap = c.cap;
     a.x = c.x[c.xb]; a.simid = c.simid[c.buf]; a.sims = c.sims; a.cell_start = c.cell_start;
-    a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.pairs = c.pairs; a.flags = c.flags;
+    a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.flags = c.flags;
     a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt; a.xr = c.xr;
     launch_grouped<T>(c, a, true);
     DTSPH_HIP_CHECK(hipGetLastError());

@@ -69,6 +69,7 @@ struct SimIter {
     double hp[kHist], hv[kHist];
     double rp_mean, rv_mean, rp_max, rv_max;
     double disp;   // max |r^{n+1} - r^(0)| = dt/2 max |V^{k} - V^(0)| at the last iteration
+    long long pairs;  // fluid-row neighbour pairs of the last iteration
 };
 
 // Per-sim report as published to mapped host memory.
@@ -137,13 +138,12 @@ struct Ctx {
     int *cand = nullptr;                  // candidate lists (radius kappa h + skin)
     uint32_t *ccnt = nullptr;
     int capc = 0;
-    unsigned long long *pairs = nullptr;  // per sim
     int2 *tiles = nullptr;
     int n_tiles = 0;
     int2 *wtiles = nullptr;
     int n_wtiles = 0;
     double4 *partials = nullptr;
-    double *partials2 = nullptr;          // per tile: max |V^{k+1} - V^(0)|^2
+    double2 *partials2 = nullptr;         // per tile: max |V^{k+1} - V^(0)|^2, pairs
     int *flags = nullptr;
     int *done_dev = nullptr;
     int *init_slot = nullptr;             // caller index -> slot before any sort

@@ -182,7 +182,7 @@ template <typename T> struct PassArgs {
     const double *x;
     double *x_alt, *xn;
     double4 *partials;
-    double *partials2;
+    double2 *partials2;   // per tile: {max |V^{k+1} - V^(0)|^2, neighbour pairs}
 };
 
 template <typename T> __device__ inline void lane_sum(T &v, int lpp)
@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
 
     if (MODE == MODE_PSEUDO && A.iters[s].done) {  // uniform per block
         if (owner) A.vout[i] = A.vin[i];
-        if (threadIdx.x == 0) { A.partials[t] = make_double4(0.0, 0.0, 0.0, 0.0); A.partials2[t] = 0.0; }
+        if (threadIdx.x == 0) { A.partials[t] = make_double4(0.0, 0.0, 0.0, 0.0); A.partials2[t] = make_double2(0.0, 0.0); }
         return;
     }
 
@@ -223,6 +223,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
 
     Acc<T> acc;
     T pi = 0, vi[3] = {0, 0, 0};
+    int npairs = 0;
     if (active) {
         const Rec ri = prec[i];
         const Q me = vin[i];
@@ -232,6 +233,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
         pi = pres<DIM>(me);
         const uint32_t cn = A.cnt[i];
         const int nfl = (int)(cn & 0xffffu), nwl = (int)(cn >> 16);
+        npairs = nfl + nwl;
         const int *__restrict__ nb = A.nbr + i;
         // fluid neighbours in batches of U: U index loads, then 2U record
         // gathers in flight, then U pair evaluations
@@ -342,13 +344,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
 
     if (MODE == MODE_PSEUDO) {
         // fixed-order block reduction of {sum |D|, sum |Vtilde|, max |D|, max |Vtilde|}
-        __shared__ double lds[kMaxBlock / 64][5];
+        __shared__ double lds[kMaxBlock / 64][6];
         double sd = owner ? fabs((double)Dv) : 0.0;
         double sv = owner ? sqrt((double)vt2) : 0.0;
         double md = sd, mv = sv, mw = owner ? (double)dw2 : 0.0;
+        double np = owner ? (double)npairs : 0.0;
         for (int o = 32; o > 0; o >>= 1) {
             sd += __shfl_xor(sd, o, 64);
             sv += __shfl_xor(sv, o, 64);
+            np += __shfl_xor(np, o, 64);
             md = fmax(md, __shfl_xor(md, o, 64));
             mv = fmax(mv, __shfl_xor(mv, o, 64));
             mw = fmax(mw, __shfl_xor(mw, o, 64));
@@ -356,19 +360,21 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         if (lane == 0) {
             lds[wave][0] = sd; lds[wave][1] = sv; lds[wave][2] = md; lds[wave][3] = mv; lds[wave][4] = mw;
+            lds[wave][5] = np;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+            double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
             for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) {
                 a0 += lds[wv][0];
                 a1 += lds[wv][1];
                 a2 = fmax(a2, lds[wv][2]);
                 a3 = fmax(a3, lds[wv][3]);
                 a4 = fmax(a4, lds[wv][4]);
+                a5 += lds[wv][5];
             }
             A.partials[t] = make_double4(a0, a1, a2, a3);
-            A.partials2[t] = a4;
+            A.partials2[t] = make_double2(a4, a5);
         }
     }
 }
@@ -456,9 +462,9 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
 // ---- residual reduction and stop test (section 3.4) --------------------------
 __global__ void __launch_bounds__(256) k_finalize(const SimDev *__restrict__ sims, SimIter *__restrict__ iters,
                                                   const double4 *__restrict__ partials,
-                                                  const double *__restrict__ partials2, int *__restrict__ done_out)
+                                                  const double2 *__restrict__ partials2, int *__restrict__ done_out)
 {
-    __shared__ double lds[4][5];
+    __shared__ double lds[4][6];
     const int s = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     SimIter &It = iters[s];
@@ -467,36 +473,44 @@ __global__ void __launch_bounds__(256) k_finalize(const SimDev *__restrict__ sim
         return;
     }
     const SimDev &S = sims[s];
-    double sd = 0, sv = 0, md = 0, mv = 0, mw = 0;
+    double sd = 0, sv = 0, md = 0, mv = 0, mw = 0, np = 0;
     const int tb = S.tile_begin, te = S.tile_end;
 #pragma unroll 4
     for (int t = tb + (int)threadIdx.x; t < te; t += 256) {
         const double4 p = partials[t];
+        const double2 p2 = partials2[t];
         sd += p.x;
         sv += p.y;
         md = fmax(md, p.z);
         mv = fmax(mv, p.w);
-        mw = fmax(mw, partials2[t]);
+        mw = fmax(mw, p2.x);
+        np += p2.y;
     }
     for (int o = 32; o > 0; o >>= 1) {
         sd += __shfl_xor(sd, o, 64);
         sv += __shfl_xor(sv, o, 64);
+        np += __shfl_xor(np, o, 64);
         md = fmax(md, __shfl_xor(md, o, 64));
         mv = fmax(mv, __shfl_xor(mv, o, 64));
         mw = fmax(mw, __shfl_xor(mw, o, 64));
     }
-    if (lane == 0) { lds[wave][0] = sd; lds[wave][1] = sv; lds[wave][2] = md; lds[wave][3] = mv; lds[wave][4] = mw; }
+    if (lane == 0) {
+        lds[wave][0] = sd; lds[wave][1] = sv; lds[wave][2] = md; lds[wave][3] = mv; lds[wave][4] = mw;
+        lds[wave][5] = np;
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    sd = lds[0][0]; sv = lds[0][1]; md = lds[0][2]; mv = lds[0][3]; mw = lds[0][4];
+    sd = lds[0][0]; sv = lds[0][1]; md = lds[0][2]; mv = lds[0][3]; mw = lds[0][4]; np = lds[0][5];
     for (int w = 1; w < 4; ++w) {
         sd += lds[w][0];
         sv += lds[w][1];
         md = fmax(md, lds[w][2]);
         mv = fmax(mv, lds[w][3]);
         mw = fmax(mw, lds[w][4]);
+        np += lds[w][5];
     }
     It.disp = 0.5 * S.dt * sqrt(mw);
+    It.pairs = (long long)np;
     const double pscale = S.dt / (S.rho0 * S.c * S.c);
     const double rp = sd * S.res_p, rv = sv * S.res_v;
     const double rpx = md * pscale, rvx = mv / S.vref;
@@ -546,8 +560,8 @@ __global__ void __launch_bounds__(256) k_finalize(const SimDev *__restrict__ sim
 // and pair counts) into mapped host memory, so one stream sync makes them
 // readable without a separate copy.
 __global__ void k_publish(int n_sims, int *__restrict__ flags, const SimIter *__restrict__ iters,
-                          const unsigned long long *__restrict__ pairs, int *__restrict__ h_flags,
-                          MirrorRep *__restrict__ h_reps, unsigned long long *__restrict__ h_pairs)
+                          int *__restrict__ h_flags, MirrorRep *__restrict__ h_reps,
+                          unsigned long long *__restrict__ h_pairs)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < F_COUNT + n_sims) h_flags[i] = flags[i];
@@ -563,7 +577,7 @@ __global__ void k_publish(int n_sims, int *__restrict__ flags, const SimIter *__
         r.rv_max = It.rv_max;
         r.disp = It.disp;
         h_reps[i] = r;
-        h_pairs[i] = pairs[i];
+        h_pairs[i] = (unsigned long long)It.pairs;
     }
 }
 
@@ -813,7 +827,7 @@ void launch_wall(Ctx &c, int mode)
 void launch_publish(Ctx &c)
 {
     const int n = F_COUNT + c.n_sims;
-    hipLaunchKernelGGL(k_publish, dim3(grid_for(n)), dim3(256), 0, c.stream, c.n_sims, c.flags, c.iters, c.pairs,
+    hipLaunchKernelGGL(k_publish, dim3(grid_for(n)), dim3(256), 0, c.stream, c.n_sims, c.flags, c.iters,
                        c.m_flags_d, c.m_reps_d, c.m_pairs_d);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
