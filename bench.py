@@ -58,8 +58,10 @@ def run_leg(problems, precision, steps, warmup, timing):
 
     sim = D.Sim(problems, precision=precision)
     tune = sim.autotune()
-    log(f"autotune: lanes {tune['lanes']} block {tune['block']} ({tune['us']:.2f} us/pass); " +
-        " ".join(f"{e['lanes']}x{e['block']}:{e['us']:.1f}" for e in tune["entries"]))
+    log(f"autotune: pass lanes {tune['lanes']} block {tune['block']} ({tune['us']:.2f} us); " +
+        " ".join(f"{e['lanes']}x{e['block']}:{e['us']:.1f}" for e in tune["entries"]) +
+        f"; neighbour build lanes {tune['nbr_lanes']} ({tune['nbr_us']:.1f} us), "
+        f"filter lanes {tune['filter_lanes']} ({tune['filter_us']:.1f} us)")
     if warmup:
         sim.step(warmup)
     sim.set_option(D.OPT_TIMING, 1 if timing else 0)

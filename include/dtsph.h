@@ -287,7 +287,8 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
  * predictor (it writes only scratch between steps, so the state is unchanged)
  * for every lanes-per-particle in {1, 2, 4, 8} and workgroup size in {64, 128,
  * 256}, `repeats` launches each (<= 0: 5), and keeps the fastest for this
- * context. The choice is cached per process by (dim, precision, walls,
+ * context; then the lanes per particle (1, 2, 4, 8) of the neighbour-list
+ * kernel and of the candidate filter (they rewrite the same lists). The choice is cached per process by (dim, precision, walls,
  * artificial viscosity, fluid-count bucket) and applied to later contexts of
  * the same kind. out (host, may be NULL) receives every timing.             */
 typedef struct dtsph_tune_entry {
@@ -296,10 +297,13 @@ typedef struct dtsph_tune_entry {
 } dtsph_tune_entry;
 
 typedef struct dtsph_tune_report {
-    int32_t lanes, block; /* the choice */
+    int32_t lanes, block; /* the pair-pass choice */
     double us;
     int32_t n_entries, reserved;
     dtsph_tune_entry entries[12];
+    int32_t nbr_lanes, filter_lanes; /* lanes per particle of the neighbour-list
+                                        build and of the candidate filter */
+    double nbr_us, filter_us;
 } dtsph_tune_report;
 
 int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out);

@@ -4,6 +4,7 @@
 // the host only orders launches and reads back per-sim stop flags.
 #include <algorithm>
 #include <cmath>
+#include <array>
 #include <map>
 #include <mutex>
 #include <cstdio>
@@ -21,9 +22,9 @@ namespace {
 
 std::string g_create_error = "no error";
 
-// autotuner choices of this process: key -> (lanes per particle, block)
+// autotuner choices of this process: key -> (pass lanes, pass block, neighbour-kernel lanes, filter lanes)
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune_cache;
+std::map<std::string, std::array<int, 4>> g_tune_cache;
 
 std::string tune_key(const Ctx &c)
 {
@@ -251,18 +252,27 @@ void resolve_timers(Ctx &c)
 }
 
 // ---- flags / sync -------------------------------------------------------------
+// Build flags moved to mapped host memory by k_finalize / k_publish; the host
+// clears them after reading.
+void check_host_flags(Ctx &c)
+{
+    if (c.timing) resolve_timers(c);
+    const int over = c.flags_host[F_NBR_OVERFLOW], need = c.flags_host[F_NBR_NEEDED];
+    const int cell = c.flags_host[F_CELL_OVERFLOW];
+    for (int k = 0; k < F_COUNT; ++k) c.flags_host[k] = 0;
+    if (over)
+        throw ApiError(DTSPH_EOVERFLOW, "neighbour list capacity " + std::to_string(c.cap) + " exceeded; needs " +
+                                            std::to_string(need) + " (set max_neighbors); particle state is undefined");
+    if (cell)
+        throw ApiError(DTSPH_EOVERFLOW, "a cell holds more than 4096 particles (particles far outside the grid "
+                                        "box or clumped); particle state is undefined");
+}
+
 void readback_flags(Ctx &c)
 {
     launch_publish(c);
     DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
-    if (c.timing) resolve_timers(c);
-    if (c.flags_host[F_NBR_OVERFLOW])
-        throw ApiError(DTSPH_EOVERFLOW, "neighbour list capacity " + std::to_string(c.cap) + " exceeded; needs " +
-                                            std::to_string(c.flags_host[F_NBR_NEEDED]) +
-                                            " (set max_neighbors); particle state is undefined");
-    if (c.flags_host[F_CELL_OVERFLOW])
-        throw ApiError(DTSPH_EOVERFLOW, "a cell holds more than 4096 particles (particles far outside the grid "
-                                        "box or clumped); particle state is undefined");
+    check_host_flags(c);
 }
 
 // Exact neighbour lists for the current positions: a filter of the candidate
@@ -310,7 +320,8 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
             launch_finalize(c);
         }
         launched += n;
-        readback_flags(c);
+        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));  // k_finalize wrote the mapped reports
+        check_host_flags(c);
         bool all = true;
         for (int s = 0; s < c.n_sims; ++s) all = all && c.flags_host[F_COUNT + s];
         if (all || launched >= max_it) break;
@@ -502,8 +513,10 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune_cache.find(tune_key(c));
             if (it != g_tune_cache.end()) {
-                c.lpp = it->second.first;
-                c.block = it->second.second;
+                c.lpp = it->second[0];
+                c.block = it->second[1];
+                c.g_nbr = it->second[2];
+                c.g_filter = it->second[3];
             }
         }
         const size_t max_tiles = (size_t)(Nf + n_sims + 8);
@@ -826,15 +839,42 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
                     rep.block = c.block;
                 }
             }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         c.lpp = rep.lanes;
         c.block = rep.block;
         setup_tiles(c);
+        // lanes per particle of the neighbour-list kernel and of the filter: both
+        // rewrite the same lists at unchanged positions, so repeats are harmless
+        for (int f = 0; f < 2; ++f) {
+            double best = 1e300;
+            int best_g = 1;
+            for (int g = 1; g <= 8; g *= 2) {
+                (f ? c.g_filter : c.g_nbr) = g;
+                float ms = 0.f;
+                by_precision(c, [&](auto t) {
+                    using T = decltype(t);
+                    launch_nbr_lists<T>(c, f == 1);
+                    DTSPH_HIP_CHECK(hipEventRecord(e0, c.stream));
+                    for (int r = 0; r < reps; ++r) launch_nbr_lists<T>(c, f == 1);
+                    DTSPH_HIP_CHECK(hipEventRecord(e1, c.stream));
+                    return 0;
+                });
+                DTSPH_HIP_CHECK(hipEventSynchronize(e1));
+                DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                const double us = 1e3 * ms / reps;
+                if (us < best) { best = us; best_g = g; }
+            }
+            (f ? c.g_filter : c.g_nbr) = best_g;
+            (f ? rep.filter_us : rep.nbr_us) = best;
+        }
+        rep.nbr_lanes = c.g_nbr;
+        rep.filter_lanes = c.g_filter;
+        readback_flags(c);  // a capacity overflow in the trials surfaces here
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         c.timing = timing;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tune_cache[tune_key(c)] = {c.lpp, c.block};
+            g_tune_cache[tune_key(c)] = {c.lpp, c.block, c.g_nbr, c.g_filter};
         }
         if (out) *out = rep;
         return DTSPH_OK;

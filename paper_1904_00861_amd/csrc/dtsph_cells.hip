@@ -185,7 +185,13 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
     }
     const int os = A.orig_in[s];
     int r = 0;
-    for (int q = b; q < e; ++q) r += A.orig_in[A.perm[q]] < os;
+    for (int q0 = b; q0 < e; q0 += 8) {  // 8 members in flight at a time
+        uint32_t pm[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) pm[m] = A.perm[q0 + m < e ? q0 + m : b];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) r += (q0 + m < e) && A.orig_in[pm[m]] < os;
+    }
     const int d = b + r;
     A.src_of[d] = (uint32_t)s;
     A.orig_out[d] = os;
@@ -500,11 +506,15 @@ template <typename T, int DIM, int G> void launch_g(Ctx &c, const NbrArgs<T> &a,
     else hipLaunchKernelGGL((k_nbr<T, DIM, G>), grid, dim3(kThreads), 0, c.stream, a);
 }
 
-// lanes per particle in the neighbour kernels: enough threads for ~8 waves per SIMD
+// lanes per particle in the neighbour kernels: the autotuner's choice, else
+// enough threads for ~8 waves per SIMD
 template <typename T> void launch_grouped(Ctx &c, const NbrArgs<T> &a, bool filter)
 {
-    int g = 1;
-    while (g < 8 && (int64_t)g * a.N < (int64_t)256 * 2048) g *= 2;
+    int g = filter ? c.g_filter : c.g_nbr;
+    if (g <= 0) {
+        g = 1;
+        while (g < 8 && (int64_t)g * a.N < (int64_t)256 * 2048) g *= 2;
+    }
     if (c.max_dim == 2) {
         if (g == 1) launch_g<T, 2, 1>(c, a, filter);
         else if (g == 2) launch_g<T, 2, 2>(c, a, filter);
@@ -557,13 +567,7 @@ void build_cells(Ctx &c)
     hipLaunchKernelGGL(k_rank_gather<T>, dim3(grid_for(N)), dim3(kThreads), 0, st, g);
     c.buf = o;
     c.xb ^= 1;
-    NbrArgs<T> a;
-    a.N = N; a.Nf = c.Nf; a.C = c.C; a.cap = c.cap;
-    a.x = c.x[c.xb]; a.simid = c.simid[o]; a.sims = c.sims; a.cell_start = c.cell_start;
-    a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.flags = c.flags;
-    a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt; a.xr = c.xr;
-    launch_grouped<T>(c, a, false);
-    DTSPH_HIP_CHECK(hipGetLastError());
+    launch_nbr_lists<T>(c, false);
     timer_end(c, t0, 2);
 }
 
@@ -571,20 +575,29 @@ void build_cells(Ctx &c)
 template <typename T>
 void filter_lists(Ctx &c)
 {
-    const int N = c.N;
     int t0 = timer_begin(c);
+    launch_nbr_lists<T>(c, true);
+    timer_end(c, t0, 2);
+}
+
+// The neighbour-list kernel alone (filter = false; needs a valid cell table) or
+// the filter (needs candidate lists covering the current positions).
+template <typename T>
+void launch_nbr_lists(Ctx &c, bool filter)
+{
     NbrArgs<T> a;
-    a.N = N; a.Nf = c.Nf; a.C = c.C; a.cap = c.cap;
+    a.N = c.N; a.Nf = c.Nf; a.C = c.C; a.cap = c.cap;
     a.x = c.x[c.xb]; a.simid = c.simid[c.buf]; a.sims = c.sims; a.cell_start = c.cell_start;
     a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.flags = c.flags;
     a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt; a.xr = c.xr;
-    launch_grouped<T>(c, a, true);
+    launch_grouped<T>(c, a, filter);
     DTSPH_HIP_CHECK(hipGetLastError());
-    timer_end(c, t0, 2);
 }
 
 template void filter_lists<float>(Ctx &);
 template void filter_lists<double>(Ctx &);
+template void launch_nbr_lists<float>(Ctx &, bool);
+template void launch_nbr_lists<double>(Ctx &, bool);
 template void build_cells<float>(Ctx &);
 template void build_cells<double>(Ctx &);
 

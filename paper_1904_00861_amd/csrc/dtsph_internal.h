@@ -87,6 +87,7 @@ struct Ctx {
     int cap = 0;             // neighbour-list capacity per particle
     int block = 256;
     int lpp = 1;             // lanes per particle in the pair pass
+    int g_nbr = 0, g_filter = 0;  // lanes per particle in the neighbour kernels (0: heuristic)
     int chunk = 0;           // 0 = adaptive
     int xcd_remap = 1;
     int max_dim = 2;
@@ -170,6 +171,7 @@ struct Ctx {
 // ---- launchers (defined in the .hip files) ---------------------------------
 template <typename T> void build_cells(Ctx &c);        // dtsph_cells.hip
 template <typename T> void filter_lists(Ctx &c);
+template <typename T> void launch_nbr_lists(Ctx &c, bool filter);
 template <typename T> void launch_pre_records(Ctx &c);
 template <typename T> void launch_wall(Ctx &c, int mode);
 template <typename T> void launch_pass(Ctx &c, int mode);

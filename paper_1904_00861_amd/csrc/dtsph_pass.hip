@@ -460,16 +460,31 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
 }
 
 // ---- residual reduction and stop test (section 3.4) --------------------------
+// Also writes each sim's report and stop flag into mapped host memory (and
+// moves any build flag there), so the host only needs a stream sync.
 __global__ void __launch_bounds__(256) k_finalize(const SimDev *__restrict__ sims, SimIter *__restrict__ iters,
                                                   const double4 *__restrict__ partials,
-                                                  const double2 *__restrict__ partials2, int *__restrict__ done_out)
+                                                  const double2 *__restrict__ partials2, int *__restrict__ done_out,
+                                                  int *__restrict__ flags, int n_sims, int *__restrict__ h_flags,
+                                                  MirrorRep *__restrict__ h_reps,
+                                                  unsigned long long *__restrict__ h_pairs)
 {
     __shared__ double lds[4][6];
     const int s = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     SimIter &It = iters[s];
+    if (s == 0 && threadIdx.x < F_COUNT) {
+        const int f = flags[threadIdx.x];
+        if (f) {
+            h_flags[threadIdx.x] = f;
+            flags[threadIdx.x] = 0;
+        }
+    }
     if (It.done) {
-        if (threadIdx.x == 0) done_out[s] = 1;
+        if (threadIdx.x == 0) {
+            done_out[s] = 1;
+            h_flags[F_COUNT + s] = 1;
+        }
         return;
     }
     const SimDev &S = sims[s];
@@ -554,6 +569,17 @@ __global__ void __launch_bounds__(256) k_finalize(const SimDev *__restrict__ sim
         It.reason = reason;
     }
     done_out[s] = It.done;
+    h_flags[F_COUNT + s] = It.done;
+    MirrorRep r;
+    r.iters = It.iters;
+    r.reason = It.reason;
+    r.rp_mean = It.rp_mean;
+    r.rv_mean = It.rv_mean;
+    r.rp_max = It.rp_max;
+    r.rv_max = It.rv_max;
+    r.disp = It.disp;
+    h_reps[s] = r;
+    h_pairs[s] = (unsigned long long)It.pairs;
 }
 
 // Copy the host-visible control words (build flags, stop flags, per-sim reports
@@ -564,8 +590,11 @@ __global__ void k_publish(int n_sims, int *__restrict__ flags, const SimIter *__
                           unsigned long long *__restrict__ h_pairs)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < F_COUNT + n_sims) h_flags[i] = flags[i];
-    if (i < F_COUNT) flags[i] = 0;  // build flags are reported once
+    if (i < F_COUNT && flags[i]) {  // build flags are moved to the host once
+        h_flags[i] = flags[i];
+        flags[i] = 0;
+    }
+    if (i >= F_COUNT && i < F_COUNT + n_sims) h_flags[i] = flags[i];
     if (i < n_sims) {
         const SimIter &It = iters[i];
         MirrorRep r;
@@ -582,22 +611,22 @@ __global__ void k_publish(int n_sims, int *__restrict__ flags, const SimIter *__
 }
 
 // ---- per-particle kernels -------------------------------------------------------
-__global__ void k_iter_reset(SimIter *iters, int n_sims, int fixed)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_sims) return;
-    SimIter z{};
-    z.fixed = fixed;
-    for (int k = 0; k < kHist; ++k) { z.hp[k] = 0.0; z.hv[k] = 0.0; }
-    iters[s] = z;
-}
 
+// {V, p} records of the fluid; at the start of a loop (half_step) also the
+// stage-1 half step of p and the reset of every sim's loop state.
 template <typename T, int DIM>
 __global__ void k_records(int Nf, const int *__restrict__ simid, const SimDev *__restrict__ sims,
                           const T *__restrict__ vn, const T *__restrict__ w, double *__restrict__ pm,
-                          const T *__restrict__ dp, typename V4<T>::type *__restrict__ vout, int half_step)
+                          const T *__restrict__ dp, typename V4<T>::type *__restrict__ vout, int half_step,
+                          SimIter *__restrict__ iters, int n_sims, int fixed)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (half_step && i < n_sims) {
+        SimIter z{};
+        z.fixed = fixed;
+        for (int k = 0; k < kHist; ++k) { z.hp[k] = 0.0; z.hv[k] = 0.0; }
+        iters[i] = z;
+    }
     if (i >= Nf) return;
     double p = pm[i];
     if (half_step) {  // p^{k+1/2} = p^k + dtau/2 (dp/dtau)^k
@@ -835,7 +864,7 @@ void launch_publish(Ctx &c)
 void launch_finalize(Ctx &c)
 {
     hipLaunchKernelGGL(k_finalize, dim3(c.n_sims), dim3(256), 0, c.stream, c.sims, c.iters, c.partials, c.partials2,
-                       c.done_dev);
+                       c.done_dev, c.flags, c.n_sims, c.m_flags_d, c.m_reps_d, c.m_pairs_d);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -846,10 +875,12 @@ void launch_pre_records(Ctx &c)
     const int b = c.buf;
     if (c.max_dim == 2)
         hipLaunchKernelGGL((k_records<T, 2>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
-                           (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0);
+                           (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0,
+                           c.iters, c.n_sims, 0);
     else
         hipLaunchKernelGGL((k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
-                           (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0);
+                           (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0,
+                           c.iters, c.n_sims, 0);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -858,13 +889,14 @@ void launch_loop_begin(Ctx &c, int fixed_iters)
 {
     using Q = typename V4<T>::type;
     const int b = c.buf;
-    hipLaunchKernelGGL(k_iter_reset, dim3(grid_for(c.n_sims)), dim3(256), 0, c.stream, c.iters, c.n_sims, fixed_iters);
     if (c.max_dim == 2)
         hipLaunchKernelGGL((k_records<T, 2>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
-                           (const T *)c.vn[b], (const T *)c.w[b], c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 1);
+                           (const T *)c.vn[b], (const T *)c.w[b], c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 1,
+                           c.iters, c.n_sims, fixed_iters);
     else
         hipLaunchKernelGGL((k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
-                           (const T *)c.vn[b], (const T *)c.w[b], c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 1);
+                           (const T *)c.vn[b], (const T *)c.w[b], c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 1,
+                           c.iters, c.n_sims, fixed_iters);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 

@@ -98,10 +98,13 @@ class TuneEntry(C.Structure):
 
 class TuneReport(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("block", C.c_int32), ("us", C.c_double),
-                ("n_entries", C.c_int32), ("reserved", C.c_int32), ("entries", TuneEntry * 12)]
+                ("n_entries", C.c_int32), ("reserved", C.c_int32), ("entries", TuneEntry * 12),
+                ("nbr_lanes", C.c_int32), ("filter_lanes", C.c_int32),
+                ("nbr_us", C.c_double), ("filter_us", C.c_double)]
 
     def as_dict(self) -> dict:
-        return dict(lanes=self.lanes, block=self.block, us=self.us,
+        return dict(lanes=self.lanes, block=self.block, us=self.us, nbr_lanes=self.nbr_lanes,
+                    filter_lanes=self.filter_lanes, nbr_us=self.nbr_us, filter_us=self.filter_us,
                     entries=[dict(lanes=e.lanes, block=e.block, us=e.us)
                              for e in self.entries[:self.n_entries]])
 
