@@ -60,6 +60,7 @@ def run_leg(problems, precision, steps, warmup, timing):
     tune = sim.autotune()
     log(f"autotune: pass lanes {tune['lanes']} block {tune['block']} ({tune['us']:.2f} us); " +
         " ".join(f"{e['lanes']}x{e['block']}:{e['us']:.1f}" for e in tune["entries"]) +
+        f"; cell subdivision {tune['cell_div']} (full build {tune['build_us']:.1f} us)"
         f"; neighbour build lanes {tune['nbr_lanes']} ({tune['nbr_us']:.1f} us), "
         f"filter lanes {tune['filter_lanes']} ({tune['filter_us']:.1f} us)")
     if warmup:

@@ -280,6 +280,9 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
 #define DTSPH_OPT_SKIN 7       /* candidate-list skin in thousandths of h, at
                                   most the default 100 (0: rebuild the cell
                                   lists at every position change)            */
+#define DTSPH_OPT_CELL_DIV 8   /* cell side >= (kappa h + skin) / value, value
+                                  in {1, 2, 3} (default 2); the search visits
+                                  +-value cells per axis                      */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the pair pass's launch shape. Between steps only (EINVAL in
@@ -304,6 +307,8 @@ typedef struct dtsph_tune_report {
     int32_t nbr_lanes, filter_lanes; /* lanes per particle of the neighbour-list
                                         build and of the candidate filter */
     double nbr_us, filter_us;
+    int32_t cell_div, reserved2;     /* cell subdivision and its full-build time */
+    double build_us;
 } dtsph_tune_report;
 
 int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out);

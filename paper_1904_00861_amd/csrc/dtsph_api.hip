@@ -22,9 +22,10 @@ namespace {
 
 std::string g_create_error = "no error";
 
-// autotuner choices of this process: key -> (pass lanes, pass block, neighbour-kernel lanes, filter lanes)
+// autotuner choices of this process: key -> (pass lanes, pass block, neighbour-kernel
+// lanes, filter lanes, cell subdivision)
 std::mutex g_tune_mu;
-std::map<std::string, std::array<int, 4>> g_tune_cache;
+std::map<std::string, std::array<int, 5>> g_tune_cache;
 
 std::string tune_key(const Ctx &c)
 {
@@ -102,6 +103,39 @@ void check_desc(const dtsph_sim_desc &d, int s, int64_t nf, int64_t nw)
     }
 }
 
+// Cell grid: cells no smaller than (kappa h + skin) / m (small margin against
+// rounding), so every candidate of a particle lies within m cells of its own.
+void set_grid(SimDev &S, int m)
+{
+    const double kc = std::sqrt(S.cand_r2);
+    S.cell_div = m;
+    for (int a = 0; a < 3; ++a) {
+        if (a < S.dim) {
+            const int n = (int)std::floor(S.L[a] / (kc / m * (1.0 + 1e-6)));
+            S.ncell[a] = std::max(1, n);
+            S.cs[a] = S.L[a] / S.ncell[a];
+            S.inv_cs[a] = 1.0 / S.cs[a];
+        } else {
+            S.ncell[a] = 1;
+            S.cs[a] = S.inv_cs[a] = 1.0;
+        }
+    }
+}
+
+// Key bases for the current subdivision: sim s's fluid cells are keys
+// [key_base, key_base + cells); wall cells add the total C.
+void setup_keys(Ctx &c, int m)
+{
+    int64_t C = 0;
+    for (int s = 0; s < c.n_sims; ++s) {
+        set_grid(c.sims_h[s], m);
+        c.sims_h[s].key_base = (int)C;
+        C += (int64_t)c.sims_h[s].ncell[0] * c.sims_h[s].ncell[1] * c.sims_h[s].ncell[2];
+    }
+    c.C = (int)C;
+    c.cell_div = m;
+}
+
 SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
 {
     SimDev S;
@@ -126,11 +160,6 @@ SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
             S.L[a] = d.hi[a] - d.lo[a];
             S.halfL[a] = 0.5 * S.L[a];
             S.periodic[a] = d.periodic[a] ? 1 : 0;
-            // cells no smaller than the candidate radius (small margin against rounding)
-            int n = (int)std::floor(S.L[a] / (kc * (1.0 + 1e-6)));
-            S.ncell[a] = std::max(1, n);
-            S.cs[a] = S.L[a] / S.ncell[a];
-            S.inv_cs[a] = 1.0 / S.cs[a];
             // fixed-point frame: a length q_len maps onto 2^32 units; on periodic
             // axes q_len divides the period so wrap-around is exact
             if (S.periodic[a]) {
@@ -455,7 +484,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             const dtsph_sim_desc &d = sims[s];
             SimDev S = make_simdev(d, n_fluid[s], n_wall[s]);
             S.fluid_begin = (int)fb;
-            S.key_base = (int)C;
+            set_grid(S, 3);  // the finest subdivision sizes the key tables
             int64_t cells = (int64_t)S.ncell[0] * S.ncell[1] * S.ncell[2];
             C += cells;
             if (2 * C > (int64_t)4096 * 4096)
@@ -486,7 +515,8 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             }
             cap_est = std::max(cap_est, est);
         }
-        c.C = (int)C;
+        c.C_max = (int)C;
+        setup_keys(c, 2);
         c.cap = std::min(65535, ((int)std::ceil(cap_est) + 3) / 4 * 4);
 
         // device memory
@@ -497,8 +527,8 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         c.key = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
         c.rank = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
         c.perm = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
-        c.count = (uint32_t *)dev_alloc(c, 4 * (size_t)(2 * C));
-        c.cell_start = (uint32_t *)dev_alloc(c, 4 * (size_t)(2 * C + 1));
+        c.count = (uint32_t *)dev_alloc(c, 4 * (size_t)(2 * c.C_max));
+        c.cell_start = (uint32_t *)dev_alloc(c, 4 * (size_t)(2 * c.C_max + 1));
         c.scan_tmp = (uint32_t *)dev_alloc(c, 4 * (size_t)(4096 + 1));
         c.nbr = (int *)dev_alloc(c, 4 * (size_t)c.cap * (size_t)N);
         c.cnt = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
@@ -517,6 +547,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
                 c.block = it->second[1];
                 c.g_nbr = it->second[2];
                 c.g_filter = it->second[3];
+                setup_keys(c, it->second[4]);
             }
         }
         const size_t max_tiles = (size_t)(Nf + n_sims + 8);
@@ -544,8 +575,8 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         }
         DTSPH_HIP_CHECK(hipMemcpy(c.init_slot, init_slot.data(), sizeof(int) * 2 * N, hipMemcpyHostToDevice));
         DTSPH_HIP_CHECK(hipMemset(c.flags, 0, sizeof(int) * (F_COUNT + n_sims)));
-        DTSPH_HIP_CHECK(hipMemset(c.cell_start, 0, 4 * (size_t)(2 * C + 1)));
-        DTSPH_HIP_CHECK(hipMemset(c.count, 0, 4 * (size_t)(2 * C)));
+        DTSPH_HIP_CHECK(hipMemset(c.cell_start, 0, 4 * (size_t)(2 * c.C_max + 1)));
+        DTSPH_HIP_CHECK(hipMemset(c.count, 0, 4 * (size_t)(2 * c.C_max)));
         DTSPH_HIP_CHECK(hipMemset(c.cnt, 0, 4 * (size_t)N));
         setup_tiles(c);
         DTSPH_HIP_CHECK(hipDeviceSynchronize());
@@ -781,6 +812,14 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
             c.cells_valid = false;
             break;
         }
+        case DTSPH_OPT_CELL_DIV:
+            if (value < 1 || value > 3) throw ApiError(DTSPH_EINVAL, "cell subdivision must be 1, 2 or 3");
+            DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+            setup_keys(c, (int)value);
+            DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
+            c.cells_valid = false;
+            c.cand_ok = c.cand_next = false;
+            break;
         case DTSPH_OPT_LANES:
             if (value != 1 && value != 2 && value != 4 && value != 8)
                 throw ApiError(DTSPH_EINVAL, "lanes per particle must be 1, 2, 4 or 8");
@@ -813,6 +852,41 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
         DTSPH_HIP_CHECK(hipEventCreate(&e0));
         DTSPH_HIP_CHECK(hipEventCreate(&e1));
         dtsph_tune_report rep{};
+        // cell subdivision: time full builds (sort + lists; they only reorder the state)
+        {
+            double best = 1e300;
+            int best_m = c.cell_div;
+            for (int m = 1; m <= 3; ++m) {
+                setup_keys(c, m);
+                DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
+                float ms = 0.f;
+                by_precision(c, [&](auto t) {
+                    using T = decltype(t);
+                    build_cells<T>(c);
+                    DTSPH_HIP_CHECK(hipEventRecord(e0, c.stream));
+                    for (int r = 0; r < reps; ++r) build_cells<T>(c);
+                    DTSPH_HIP_CHECK(hipEventRecord(e1, c.stream));
+                    return 0;
+                });
+                DTSPH_HIP_CHECK(hipEventSynchronize(e1));
+                DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                const double us = 1e3 * ms / reps;
+                if (us < best) { best = us; best_m = m; }
+            }
+            setup_keys(c, best_m);
+            DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
+            by_precision(c, [&](auto t) {
+                using T = decltype(t);
+                build_cells<T>(c);
+                launch_pre_records<T>(c);
+                launch_wall<T>(c, MODE_PRE);
+                return 0;
+            });
+            c.cells_valid = true;
+            c.cand_ok = c.cand_next = false;
+            rep.cell_div = best_m;
+            rep.build_us = best;
+        }
         rep.us = 1e300;
         const int lanes[4] = {1, 2, 4, 8}, blocks[3] = {64, 128, 256};
         for (int li = 0; li < 4; ++li)
@@ -874,7 +948,7 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
         c.timing = timing;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tune_cache[tune_key(c)] = {c.lpp, c.block, c.g_nbr, c.g_filter};
+            g_tune_cache[tune_key(c)] = {c.lpp, c.block, c.g_nbr, c.g_filter, c.cell_div};
         }
         if (out) *out = rep;
         return DTSPH_OK;

@@ -243,17 +243,17 @@ template <> struct XR<3> {
 };
 
 // Cells along one axis whose particles can be neighbours of a particle in cell
-// c: c-1, c, c+1, wrapped on periodic axes, clipped on others; a periodic axis
-// with fewer than three cells visits each of its cells once.
+// c: c-m .. c+m, wrapped on periodic axes, clipped on others; a periodic axis
+// with fewer than 2m+1 cells visits each of its cells once.
 struct AxisRange {
     int first, count, n, per;
-    __device__ AxisRange(int c, int n_, int per_) : n(n_), per(per_)
+    __device__ AxisRange(int c, int n_, int per_, int m) : n(n_), per(per_)
     {
-        if (per && n < 3) { first = 0; count = n; }
-        else if (per) { first = c - 1; count = 3; }
+        if (per && n < 2 * m + 1) { first = 0; count = n; }
+        else if (per) { first = c - m; count = 2 * m + 1; }
         else {
-            first = c > 0 ? c - 1 : 0;
-            const int last = c < n - 1 ? c + 1 : n - 1;
+            first = c > m ? c - m : 0;
+            const int last = c < n - 1 - m ? c + m : n - 1;
             count = last - first + 1;
         }
     }
@@ -375,13 +375,14 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
         const int cx = cell_coord(P.xi, S.lo[0], S.inv_cs[0], nx);
         const int cy = cell_coord(P.yi, S.lo[1], S.inv_cs[1], ny);
         const int cz = DIM == 3 ? cell_coord(P.zi, S.lo[2], S.inv_cs[2], nz) : 0;
-        // x cells as at most two contiguous runs of keys
+        // x cells cx-m .. cx+m as at most two contiguous runs of keys
+        const int md = S.cell_div;
         int xa0, xb0, xa1 = 0, xb1 = -1;
-        if (P.px && nx < 3) { xa0 = 0; xb0 = nx - 1; }
-        else if (P.px && cx == 0) { xa0 = 0; xb0 = 1; xa1 = xb1 = nx - 1; }
-        else if (P.px && cx == nx - 1) { xa0 = nx - 2; xb0 = nx - 1; xa1 = xb1 = 0; }
-        else { xa0 = cx > 0 ? cx - 1 : 0; xb0 = cx < nx - 1 ? cx + 1 : nx - 1; }
-        const AxisRange ry(cy, ny, P.py), rz(cz, nz, P.pz);
+        if (P.px && nx < 2 * md + 1) { xa0 = 0; xb0 = nx - 1; }
+        else if (P.px && cx - md < 0) { xa0 = 0; xb0 = cx + md; xa1 = nx + cx - md; xb1 = nx - 1; }
+        else if (P.px && cx + md > nx - 1) { xa0 = cx - md; xb0 = nx - 1; xa1 = 0; xb1 = cx + md - nx; }
+        else { xa0 = cx > md ? cx - md : 0; xb0 = cx < nx - 1 - md ? cx + md : nx - 1; }
+        const AxisRange ry(cy, ny, P.py, md), rz(cz, nz, P.pz, DIM == 3 ? md : 0);
         const int cap = A.cap, capc = A.capc;
         int total = 0, ctotal = 0, ccf = 0, ccw = 0;
         for (int tp = 0; tp < (fluid ? 2 : 1); ++tp) {

@@ -43,6 +43,7 @@ struct SimDev {
     int key_base;        // first fluid key; wall keys add the total cell count
     int tile_begin, tile_end;  // fluid tiles of this sim (residual partials)
     int ncell[3];
+    int cell_div;        // cells of side >= (kappa h + skin) / cell_div; blocks of +-cell_div cells
     int periodic[3];
     int edac_reg_literal;
     double lo[3], hi[3], L[3], halfL[3], cs[3], inv_cs[3];
@@ -84,6 +85,8 @@ struct Ctx {
     int n_sims = 0;
     int N = 0, Nf = 0, Nw = 0;
     int C = 0;               // fluid cells of all sims; keys 0..2C-1
+    int C_max = 0;           // C at the finest subdivision (sizes the key tables)
+    int cell_div = 2;
     int cap = 0;             // neighbour-list capacity per particle
     int block = 256;
     int lpp = 1;             // lanes per particle in the pair pass

@@ -22,6 +22,7 @@ EINVAL, ENOMEM, EHIP, ENONFINITE, EOVERFLOW = -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 REASONS = {0: "running", 1: "converged", 2: "stalled", 3: "max_iter", 4: "nonfinite", 5: "fixed"}
 OPT_TIMING, OPT_RESET_TIMING, OPT_CHUNK, OPT_BLOCK, OPT_XCD_REMAP, OPT_LANES, OPT_SKIN = 1, 2, 3, 4, 5, 6, 7
+OPT_CELL_DIV = 8
 
 EXPORTS = [
     "dtsph_create", "dtsph_destroy", "dtsph_last_error", "dtsph_set_state", "dtsph_get_state",
@@ -100,10 +101,12 @@ class TuneReport(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("block", C.c_int32), ("us", C.c_double),
                 ("n_entries", C.c_int32), ("reserved", C.c_int32), ("entries", TuneEntry * 12),
                 ("nbr_lanes", C.c_int32), ("filter_lanes", C.c_int32),
-                ("nbr_us", C.c_double), ("filter_us", C.c_double)]
+                ("nbr_us", C.c_double), ("filter_us", C.c_double),
+                ("cell_div", C.c_int32), ("reserved2", C.c_int32), ("build_us", C.c_double)]
 
     def as_dict(self) -> dict:
         return dict(lanes=self.lanes, block=self.block, us=self.us, nbr_lanes=self.nbr_lanes,
+                    cell_div=self.cell_div, build_us=self.build_us,
                     filter_lanes=self.filter_lanes, nbr_us=self.nbr_us, filter_us=self.filter_us,
                     entries=[dict(lanes=e.lanes, block=e.block, us=e.us)
                              for e in self.entries[:self.n_entries]])

@@ -307,3 +307,29 @@ def test_skin_zero_rebuilds_and_agrees():
     nf = prob.n_fluid
     assert rel_l2(ga["v"][:nf], gb["v"][:nf]) <= 1e-12
     assert rel_l2(ga["p"][:nf], gb["p"][:nf]) <= 1e-12
+
+
+@pytest.mark.parametrize("div", [1, 2, 3])
+@pytest.mark.parametrize("case", ["tgv2d_16_j03", "tgv2d_perfect", "tgv3d_10", "dam_outside", "tank_10"])
+def test_neighbour_lists_bit_exact_every_cell_subdivision(case, div):
+    prob = CASES[case]()
+    banner(f"neighbours {case} cell subdivision {div}")
+    ob, ib = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, prob.x, "brute")
+    sim = D.Sim(prob, precision=D.FP32)
+    sim.set_option(D.OPT_CELL_DIV, div)
+    off, idx = sim.neighbor_list()
+    sim.close()
+    assert np.array_equal(off, ob) and np.array_equal(idx, ib)
+
+
+def test_tiny_periodic_box_visits_each_cell_once():
+    # 7 x 7 particles: kappa h = 3/7 of a unit period, so each axis has fewer
+    # cells than a +-m block; every cell must be visited exactly once
+    prob = I.tgv2d(7, seed=2, jitter=0.2)
+    ob, ib = O.neighbors(prob.params, prob.n_fluid, 0, prob.x, "brute")
+    for div in (1, 2, 3):
+        sim = D.Sim(prob, precision=D.FP64)
+        sim.set_option(D.OPT_CELL_DIV, div)
+        off, idx = sim.neighbor_list()
+        sim.close()
+        assert np.array_equal(off, ob) and np.array_equal(idx, ib)
