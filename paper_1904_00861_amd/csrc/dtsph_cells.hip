@@ -385,16 +385,30 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
         const AxisRange ry(cy, ny, P.py, md), rz(cz, nz, P.pz, DIM == 3 ? md : 0);
         const int cap = A.cap, capc = A.capc;
         int total = 0, ctotal = 0, ccf = 0, ccw = 0;
-        for (int tp = 0; tp < (fluid ? 2 : 1); ++tp) {
+        const int ntp = (fluid && S.nw > 0) ? 2 : 1;  // wall cells only where walls exist
+        for (int tp = 0; tp < ntp; ++tp) {
             const int base = S.key_base + (tp ? A.C : 0);
             int found = 0, cfound = 0;
-            for (int u = 0; u < rz.count; ++u)
-                for (int v = 0; v < ry.count; ++v) {
-                    const int row = base + (rz.at(u) * ny + ry.at(v)) * nx;
+            for (int u = 0; u < rz.count; ++u) {
+                // bounds of every run of this plane, loaded before any is used
+                constexpr int kMaxRows = 7;
+                int rb[kMaxRows][2], re[kMaxRows][2];
+#pragma unroll
+                for (int v = 0; v < kMaxRows; ++v) {
+                    const int row = base + (rz.at(u) * ny + ry.at(v < ry.count ? v : 0)) * nx;
+#pragma unroll
                     for (int run = 0; run < 2; ++run) {
                         const int xa = run ? xa1 : xa0, xb = run ? xb1 : xb0;
-                        if (xb < xa) continue;
-                        const int jb = (int)cstart[row + xa], je = (int)cstart[row + xb + 1];
+                        const bool use = v < ry.count && xb >= xa;
+                        rb[v][run] = use ? (int)cstart[row + xa] : 0;
+                        re[v][run] = use ? (int)cstart[row + xb + 1] : 0;
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < kMaxRows; ++v)
+#pragma unroll
+                    for (int run = 0; run < 2; ++run) {
+                        const int jb = rb[v][run], je = re[v][run];
                         for (int j0 = jb; j0 < je; j0 += G * kBatch) {  // uniform in the group
                             Q q[kBatch];
 #pragma unroll
@@ -424,7 +438,7 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
                             }
                         }
                     }
-                }
+            }
             if (tp) { cw = found; ccw = cfound; }
             else { cf = found; ccf = cfound; }
         }
