@@ -183,7 +183,7 @@ typedef struct dtsph_info {
     int32_t block;          /* pair-pass workgroup size                       */
     int32_t lanes;          /* lanes per particle in the pair pass            */
     int32_t reserved;
-    int64_t device_bytes;   /* device memory owned by the context             */
+    int64_t device_bytes;   /* bytes of the context's device arrays          */
 } dtsph_info;
 
 typedef struct dtsph_ctx dtsph_ctx;
@@ -315,6 +315,24 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out);
 
 int dtsph_get_timing(const dtsph_ctx *ctx, dtsph_timing *out);
 int dtsph_get_info(const dtsph_ctx *ctx, dtsph_info *out);
+
+/* Caller-supplied device memory (for callers whose allocator owns all device
+ * memory, e.g. a caching allocator). dtsph_workspace_bytes writes the number of
+ * bytes that holds every device array of the context (state, cell tables,
+ * neighbour lists, partials; fixed at creation). dtsph_set_workspace moves all
+ * of them into `dev` (device memory of the context's device, 256-byte aligned,
+ * at least that many bytes), copying their contents on the context's stream
+ * and freeing the library's own allocations; dev == NULL moves them back into
+ * library allocations. The caller owns `dev` and must keep it alive and
+ * untouched until the context is destroyed or another workspace is set; a new
+ * workspace must not overlap the current one. Allowed at any point, also inside
+ * the pseudo-time loop; synchronises the stream. The context still owns a small
+ * block of mapped host memory (reports) and its events.
+ * Errors: EINVAL (NULL ctx/bytes, misaligned or non-device memory, overlap),
+ * ENOMEM (bytes too small, or library allocation failed with dev == NULL),
+ * EHIP; on error the context keeps its previous memory and state.            */
+int dtsph_workspace_bytes(const dtsph_ctx *ctx, size_t *bytes);
+int dtsph_set_workspace(dtsph_ctx *ctx, void *dev, size_t bytes);
 
 #ifdef __cplusplus
 }

@@ -56,22 +56,77 @@ template <typename F> int guarded(dtsph_ctx *ctx, F &&f)
     }
 }
 
-void *dev_alloc(Ctx &c, size_t bytes)
+constexpr size_t kWsAlign = 256;
+
+size_t ws_round(size_t b) { return (std::max<size_t>(b, 16) + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+void *raw_alloc(size_t bytes)
 {
     void *p = nullptr;
-    if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 16));
     if (e != hipSuccess) throw ApiError(DTSPH_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
                                                           hipGetErrorString(e));
-    c.allocs.push_back(p);
-    c.device_bytes += (int64_t)bytes;
     return p;
+}
+
+// Allocate a device array owned by the library and register the field that
+// holds it (see Ctx::arrays).
+template <typename P> void dev_alloc(Ctx &c, P *&slot, size_t bytes)
+{
+    void *p = raw_alloc(bytes);
+    c.owned.push_back(p);
+    c.arrays.push_back({(void **)&slot, bytes});
+    c.device_bytes += (int64_t)bytes;
+    slot = (P *)p;
+}
+
+size_t workspace_need(const Ctx &c)
+{
+    size_t total = 0;
+    for (const auto &a : c.arrays) total += ws_round(a.bytes);
+    return total;
+}
+
+// Move every device array to `base` (a caller workspace of workspace_need(c)
+// bytes) or, with base == nullptr, to fresh library allocations; contents are
+// copied on the context's stream, old library allocations freed.
+void relocate(Ctx &c, char *base, size_t size)
+{
+    std::vector<void *> fresh(c.arrays.size(), nullptr);
+    std::vector<void *> fresh_owned;
+    try {
+        size_t off = 0;
+        for (size_t i = 0; i < c.arrays.size(); ++i) {
+            if (base) {
+                fresh[i] = base + off;
+                off += ws_round(c.arrays[i].bytes);
+            } else {
+                fresh[i] = raw_alloc(c.arrays[i].bytes);
+                fresh_owned.push_back(fresh[i]);
+            }
+        }
+        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+        for (size_t i = 0; i < c.arrays.size(); ++i)
+            DTSPH_HIP_CHECK(hipMemcpyAsync(fresh[i], *c.arrays[i].slot, c.arrays[i].bytes, hipMemcpyDeviceToDevice,
+                                           c.stream));
+        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+    } catch (...) {
+        for (void *p : fresh_owned) (void)hipFree(p);
+        throw;
+    }
+    for (void *p : c.owned) (void)hipFree(p);
+    c.owned = std::move(fresh_owned);
+    for (size_t i = 0; i < c.arrays.size(); ++i) *c.arrays[i].slot = fresh[i];
+    c.done_dev = c.flags + F_COUNT;
+    c.workspace = base;
+    c.workspace_size = base ? size : 0;
 }
 
 void free_all(Ctx &c)
 {
-    for (void *p : c.allocs) (void)hipFree(p);
-    c.allocs.clear();
+    for (void *p : c.owned) (void)hipFree(p);
+    c.owned.clear();
+    c.arrays.clear();
     if (c.mirror_h) (void)hipHostFree(c.mirror_h);
     c.mirror_h = nullptr;
     c.flags_host = nullptr;
@@ -237,23 +292,23 @@ template <typename T> void alloc_state(Ctx &c)
 {
     const size_t N = c.N, Nf = c.Nf, Nw = std::max(c.Nw, 1);
     for (int b = 0; b < 2; ++b) {
-        c.orig[b] = (int *)dev_alloc(c, 4 * N);
-        c.simid[b] = (int *)dev_alloc(c, 4 * N);
-        c.x[b] = (double *)dev_alloc(c, 8 * 3 * N);
-        c.xn[b] = (double *)dev_alloc(c, 8 * 3 * N);
-        c.vn[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
-        c.dv[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
-        c.w[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
-        c.w0[b] = dev_alloc(c, sizeof(T) * 3 * Nf);
-        c.pm[b] = (double *)dev_alloc(c, 8 * Nf);
-        c.pn[b] = (double *)dev_alloc(c, 8 * Nf);
-        c.dp[b] = dev_alloc(c, sizeof(T) * Nf);
-        c.vw[b] = dev_alloc(c, sizeof(T) * 3 * Nw);
-        c.pw[b] = dev_alloc(c, sizeof(T) * Nw);
-        c.vp[b] = dev_alloc(c, sizeof(T) * 4 * N);
+        dev_alloc(c, c.orig[b], 4 * N);
+        dev_alloc(c, c.simid[b], 4 * N);
+        dev_alloc(c, c.x[b], 8 * 3 * N);
+        dev_alloc(c, c.xn[b], 8 * 3 * N);
+        dev_alloc(c, c.vn[b], sizeof(T) * 3 * Nf);
+        dev_alloc(c, c.dv[b], sizeof(T) * 3 * Nf);
+        dev_alloc(c, c.w[b], sizeof(T) * 3 * Nf);
+        dev_alloc(c, c.w0[b], sizeof(T) * 3 * Nf);
+        dev_alloc(c, c.pm[b], 8 * Nf);
+        dev_alloc(c, c.pn[b], 8 * Nf);
+        dev_alloc(c, c.dp[b], sizeof(T) * Nf);
+        dev_alloc(c, c.vw[b], sizeof(T) * 3 * Nw);
+        dev_alloc(c, c.pw[b], sizeof(T) * Nw);
+        dev_alloc(c, c.vp[b], sizeof(T) * 4 * N);
     }
-    c.prec = dev_alloc(c, (sizeof(T) == 4 ? 16 : 32) * N);
-    c.xr = dev_alloc(c, 32 * N);
+    dev_alloc(c, c.prec, (sizeof(T) == 4 ? 16 : 32) * N);
+    dev_alloc(c, c.xr, 32 * N);
 }
 
 // ---- timing -------------------------------------------------------------------
@@ -520,21 +575,21 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         c.cap = std::min(65535, ((int)std::ceil(cap_est) + 3) / 4 * 4);
 
         // device memory
-        c.sims = (SimDev *)dev_alloc(c, sizeof(SimDev) * n_sims);
-        c.iters = (SimIter *)dev_alloc(c, sizeof(SimIter) * n_sims);
+        dev_alloc(c, c.sims, sizeof(SimDev) * n_sims);
+        dev_alloc(c, c.iters, sizeof(SimIter) * n_sims);
         if (precision == DTSPH_FP32) alloc_state<float>(c);
         else alloc_state<double>(c);
-        c.key = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
-        c.rank = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
-        c.perm = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
-        c.count = (uint32_t *)dev_alloc(c, 4 * (size_t)(2 * c.C_max));
-        c.cell_start = (uint32_t *)dev_alloc(c, 4 * (size_t)(2 * c.C_max + 1));
-        c.scan_tmp = (uint32_t *)dev_alloc(c, 4 * (size_t)(4096 + 1));
-        c.nbr = (int *)dev_alloc(c, 4 * (size_t)c.cap * (size_t)N);
-        c.cnt = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
+        dev_alloc(c, c.key, 4 * (size_t)N);
+        dev_alloc(c, c.rank, 4 * (size_t)N);
+        dev_alloc(c, c.perm, 4 * (size_t)N);
+        dev_alloc(c, c.count, 4 * (size_t)(2 * c.C_max));
+        dev_alloc(c, c.cell_start, 4 * (size_t)(2 * c.C_max + 1));
+        dev_alloc(c, c.scan_tmp, 4 * (size_t)(4096 + 1));
+        dev_alloc(c, c.nbr, 4 * (size_t)c.cap * (size_t)N);
+        dev_alloc(c, c.cnt, 4 * (size_t)N);
         c.capc = c.cap;
-        c.cand = (int *)dev_alloc(c, 4 * (size_t)c.capc * (size_t)N);
-        c.ccnt = (uint32_t *)dev_alloc(c, 4 * (size_t)N);
+        dev_alloc(c, c.cand, 4 * (size_t)c.capc * (size_t)N);
+        dev_alloc(c, c.ccnt, 4 * (size_t)N);
         // lanes per particle: enough threads for ~8 waves per SIMD on 256 CUs
         {
             int lpp = 1;
@@ -551,12 +606,12 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             }
         }
         const size_t max_tiles = (size_t)(Nf + n_sims + 8);
-        c.tiles = (int2 *)dev_alloc(c, sizeof(int2) * max_tiles);
-        c.partials = (double4 *)dev_alloc(c, sizeof(double4) * max_tiles);
-        c.partials2 = (double2 *)dev_alloc(c, sizeof(double2) * max_tiles);
-        c.flags = (int *)dev_alloc(c, sizeof(int) * (F_COUNT + n_sims));
+        dev_alloc(c, c.tiles, sizeof(int2) * max_tiles);
+        dev_alloc(c, c.partials, sizeof(double4) * max_tiles);
+        dev_alloc(c, c.partials2, sizeof(double2) * max_tiles);
+        dev_alloc(c, c.flags, sizeof(int) * (F_COUNT + n_sims));
         c.done_dev = c.flags + F_COUNT;
-        c.init_slot = (int *)dev_alloc(c, sizeof(int) * 2 * (size_t)N);
+        dev_alloc(c, c.init_slot, sizeof(int) * 2 * (size_t)N);
         {
             const size_t fb_bytes = (sizeof(int) * (F_COUNT + n_sims) + 15) / 16 * 16;
             const size_t pb_bytes = 8 * (size_t)n_sims;
@@ -983,6 +1038,39 @@ int dtsph_get_info(const dtsph_ctx *ctx, dtsph_info *out)
     out->reserved = 0;
     out->device_bytes = c.device_bytes;
     return DTSPH_OK;
+}
+
+int dtsph_workspace_bytes(const dtsph_ctx *ctx, size_t *bytes)
+{
+    if (!ctx || !bytes) return DTSPH_EINVAL;
+    *bytes = workspace_need(ctx->c);
+    return DTSPH_OK;
+}
+
+int dtsph_set_workspace(dtsph_ctx *ctx, void *dev, size_t bytes)
+{
+    return guarded(ctx, [&](Ctx &c) {
+        char *base = (char *)dev;
+        if (base == c.workspace && (base == nullptr || bytes == c.workspace_size)) return DTSPH_OK;
+        if (base) {
+            const size_t need = workspace_need(c);
+            if ((uintptr_t)base % kWsAlign)
+                throw ApiError(DTSPH_EINVAL, "workspace must be 256-byte aligned");
+            if (bytes < need)
+                throw ApiError(DTSPH_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes is smaller than the " +
+                                                 std::to_string(need) + " bytes needed");
+            if (c.workspace && base < c.workspace + c.workspace_size && c.workspace < base + need)
+                throw ApiError(DTSPH_EINVAL, "the new workspace overlaps the current one");
+            hipPointerAttribute_t attr{};
+            if (hipPointerGetAttributes(&attr, dev) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+                attr.device != c.device) {
+                (void)hipGetLastError();
+                throw ApiError(DTSPH_EINVAL, "workspace is not device memory of the context's device");
+            }
+        }
+        relocate(c, base, bytes);
+        return DTSPH_OK;
+    });
 }
 
 }  // extern "C"

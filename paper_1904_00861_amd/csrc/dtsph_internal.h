@@ -111,8 +111,17 @@ struct Ctx {
     int cur = 0;             // which vp buffer is current
     int last_iters = 4;      // adaptive chunking
 
-    // device memory
-    std::vector<void *> allocs;
+    // device memory: every device array of the context is registered with the
+    // address of the field that points to it, so that the whole set can move into
+    // (or out of) a caller-supplied workspace.
+    struct DevArray {
+        void **slot;
+        size_t bytes;
+    };
+    std::vector<DevArray> arrays;
+    std::vector<void *> owned;            // library allocations (empty while a workspace is set)
+    char *workspace = nullptr;            // caller-owned, or nullptr
+    size_t workspace_size = 0;
     int64_t device_bytes = 0;
     SimDev *sims = nullptr;
     SimIter *iters = nullptr;
@@ -144,8 +153,6 @@ struct Ctx {
     int capc = 0;
     int2 *tiles = nullptr;
     int n_tiles = 0;
-    int2 *wtiles = nullptr;
-    int n_wtiles = 0;
     double4 *partials = nullptr;
     double2 *partials2 = nullptr;         // per tile: max |V^{k+1} - V^(0)|^2, pairs
     int *flags = nullptr;

@@ -28,7 +28,7 @@ EXPORTS = [
     "dtsph_create", "dtsph_destroy", "dtsph_last_error", "dtsph_set_state", "dtsph_get_state",
     "dtsph_build_cells", "dtsph_predict", "dtsph_pseudo_iterate", "dtsph_correct", "dtsph_step",
     "dtsph_neighbor_list", "dtsph_cell_layout", "dtsph_set_option", "dtsph_get_timing",
-    "dtsph_get_info", "dtsph_autotune",
+    "dtsph_get_info", "dtsph_autotune", "dtsph_workspace_bytes", "dtsph_set_workspace",
 ]
 
 
@@ -143,6 +143,8 @@ def lib() -> C.CDLL:
         L.dtsph_get_timing.argtypes = [vp, P(Timing)]
         L.dtsph_get_info.argtypes = [vp, P(Info)]
         L.dtsph_autotune.argtypes = [vp, C.c_int32, P(TuneReport)]
+        L.dtsph_workspace_bytes.argtypes = [vp, P(C.c_size_t)]
+        L.dtsph_set_workspace.argtypes = [vp, vp, C.c_size_t]
         for name in EXPORTS:
             if name not in ("dtsph_destroy", "dtsph_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -278,6 +280,16 @@ def dtsph_get_info(ctx) -> dict:
     return i.as_dict()
 
 
+def dtsph_workspace_bytes(ctx) -> int:
+    b = C.c_size_t(0)
+    _check(ctx, lib().dtsph_workspace_bytes(ctx, C.byref(b)))
+    return int(b.value)
+
+
+def dtsph_set_workspace(ctx, dev_ptr: int, nbytes: int) -> int:
+    return _check(ctx, lib().dtsph_set_workspace(ctx, C.c_void_p(dev_ptr or None), int(nbytes)))
+
+
 # ---- convenience wrapper over torch device tensors --------------------------------
 
 class Sim:
@@ -379,6 +391,16 @@ class Sim:
         rep = dtsph_autotune(self.ctx, repeats)
         self.info = dtsph_get_info(self.ctx)
         return rep
+
+    def use_workspace(self, tensor=None):
+        """Move the context's device arrays into ``tensor`` (a torch uint8 device
+        tensor of at least ``dtsph_workspace_bytes`` bytes, kept alive by this
+        object), or back into library allocations with None."""
+        if tensor is None:
+            dtsph_set_workspace(self.ctx, 0, 0)
+        else:
+            dtsph_set_workspace(self.ctx, tensor.data_ptr(), tensor.numel() * tensor.element_size())
+        self.workspace = tensor
 
     def sim_slices(self) -> List[slice]:
         out, o = [], 0
