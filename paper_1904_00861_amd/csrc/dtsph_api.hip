@@ -277,14 +277,22 @@ SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
 void setup_tiles(Ctx &c)
 {
     std::vector<int2> tiles;
+    std::vector<int4> segs;
     for (int s = 0; s < c.n_sims; ++s) {
-        c.sims_h[s].tile_begin = (int)tiles.size();
+        SimDev &S = c.sims_h[s];
+        S.tile_begin = (int)tiles.size();
         const int per = c.block / c.lpp;  // particles per tile
         for (int off = 0; off < (int)c.nf[s]; off += per) tiles.push_back(make_int2(s, c.fluid_begin[s] + off));
-        c.sims_h[s].tile_end = (int)tiles.size();
+        S.tile_end = (int)tiles.size();
+        S.seg_begin = (int)segs.size();
+        for (int t = S.tile_begin, k = 0; t < S.tile_end; t += kSegTiles, ++k)
+            segs.push_back(make_int4(s, t, std::min(t + kSegTiles, S.tile_end), k));
+        S.seg_count = (int)segs.size() - S.seg_begin;
     }
     c.n_tiles = (int)tiles.size();
+    c.n_segs = (int)segs.size();
     DTSPH_HIP_CHECK(hipMemcpy(c.tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice));
+    DTSPH_HIP_CHECK(hipMemcpy(c.segs, segs.data(), sizeof(int4) * segs.size(), hipMemcpyHostToDevice));
     DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
 }
 
@@ -371,17 +379,54 @@ template <typename T> void ensure_cells(Ctx &c)
     }
 }
 
+// Rate pass at r^n and predictor. When the candidate lists of the last build
+// still cover every neighbour at r^n, the pass runs over them directly: a
+// candidate beyond the support adds exactly zero (every clipped kernel term is
+// zero there), so no filtered list is needed for this one pass.
 template <typename T> void do_predict(Ctx &c)
 {
     if (c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_predict: already inside a step (call dtsph_correct)");
-    ensure_cells<T>(c);
-    launch_pre_records<T>(c);
-    launch_wall<T>(c, MODE_PRE);
-    launch_pass<T>(c, MODE_PRE);
+    bool use_cand = false;
+    if (!c.cells_valid) {
+        if (c.cand_ok) use_cand = true;
+        else ensure_cells<T>(c);
+    }
+    if (!c.records_fresh) launch_pre_records<T>(c);
+    launch_wall<T>(c, MODE_PRE, use_cand);
+    launch_pass<T>(c, MODE_PRE, use_cand);
     c.xb ^= 1;
     c.in_loop = true;
     c.cells_valid = false;
     c.cand_ok = false;
+    c.records_fresh = false;
+    c.p_half = false;
+}
+
+// Tile ranges of the sims whose loop is still running (from the stop flags in
+// mapped memory); every tile when all run or the ranges do not fit.
+void set_active_ranges(Ctx &c, bool all)
+{
+    c.n_ranges = 0;
+    c.n_act_tiles = c.n_tiles;
+    if (all) return;
+    int n = 0, at = 0;
+    int2 r[kMaxRanges];
+    for (int s = 0; s < c.n_sims; ++s) {
+        if (c.flags_host[F_COUNT + s]) continue;
+        const int tb = c.sims_h[s].tile_begin, te = c.sims_h[s].tile_end;
+        if (te <= tb) continue;
+        if (n > 0 && r[n - 1].x + (at - r[n - 1].y) == tb) {
+            at += te - tb;
+            continue;
+        }
+        if (n == kMaxRanges) return;  // too fragmented: launch every tile
+        r[n++] = make_int2(tb, at);
+        at += te - tb;
+    }
+    if (at == c.n_tiles) return;
+    c.n_ranges = n;
+    c.n_act_tiles = at;
+    for (int q = 0; q < n; ++q) c.ranges[q] = r[q];
 }
 
 template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
@@ -390,6 +435,7 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
     if (fixed < 0) throw ApiError(DTSPH_EINVAL, "fixed_iters must be >= 0");
     ensure_cells<T>(c);
     launch_loop_begin<T>(c, fixed);
+    set_active_ranges(c, true);
     int max_it = fixed;
     if (fixed == 0)
         for (auto &d : c.desc) max_it = std::max(max_it, (int)d.max_iter);
@@ -410,8 +456,10 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
         for (int s = 0; s < c.n_sims; ++s) all = all && c.flags_host[F_COUNT + s];
         if (all || launched >= max_it) break;
         chunk = c.chunk > 0 ? c.chunk : 2;
+        set_active_ranges(c, false);
     }
-    launch_loop_end<T>(c);
+    set_active_ranges(c, true);
+    c.p_half = true;  // p^K = p^{K+1/2} - dtau/2 (dp/dtau)^K is applied lazily
     int status = DTSPH_OK, most = 1;
     bool cand = true;
     for (int s = 0; s < c.n_sims; ++s) {
@@ -448,6 +496,8 @@ template <typename T> void do_correct(Ctx &c)
     c.in_loop = false;
     c.cells_valid = false;
     c.cand_ok = c.cand_next;
+    c.p_half = false;
+    c.records_fresh = true;
 }
 
 template <typename T> int do_step(Ctx &c, int n_steps, dtsph_iter_report *reps)
@@ -608,6 +658,11 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         const size_t max_tiles = (size_t)(Nf + n_sims + 8);
         dev_alloc(c, c.tiles, sizeof(int2) * max_tiles);
         dev_alloc(c, c.partials, sizeof(double4) * max_tiles);
+        const size_t max_segs = max_tiles / kSegTiles + (size_t)n_sims + 1;
+        dev_alloc(c, c.segs, sizeof(int4) * max_segs);
+        dev_alloc(c, c.seg_p, sizeof(double4) * max_segs);
+        dev_alloc(c, c.seg_p2, sizeof(double2) * max_segs);
+        dev_alloc(c, c.tickets, sizeof(uint32_t) * n_sims);
         dev_alloc(c, c.partials2, sizeof(double2) * max_tiles);
         dev_alloc(c, c.flags, sizeof(int) * (F_COUNT + n_sims));
         c.done_dev = c.flags + F_COUNT;
@@ -630,6 +685,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         }
         DTSPH_HIP_CHECK(hipMemcpy(c.init_slot, init_slot.data(), sizeof(int) * 2 * N, hipMemcpyHostToDevice));
         DTSPH_HIP_CHECK(hipMemset(c.flags, 0, sizeof(int) * (F_COUNT + n_sims)));
+        DTSPH_HIP_CHECK(hipMemset(c.tickets, 0, sizeof(uint32_t) * n_sims));
         DTSPH_HIP_CHECK(hipMemset(c.cell_start, 0, 4 * (size_t)(2 * c.C_max + 1)));
         DTSPH_HIP_CHECK(hipMemset(c.count, 0, 4 * (size_t)(2 * c.C_max)));
         DTSPH_HIP_CHECK(hipMemset(c.cnt, 0, 4 * (size_t)N));
@@ -684,6 +740,8 @@ int dtsph_set_state(dtsph_ctx *ctx, const dtsph_state_view *s)
         c.cand_ok = false;
         c.cand_next = false;
         c.cur = 0;
+        c.p_half = false;
+        c.records_fresh = false;
         DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
         return DTSPH_OK;
     });

@@ -94,13 +94,17 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds_waves,
     return before + inc - v;
 }
 
-__global__ void k_scan_reduce(const uint32_t *__restrict__ in, int n, uint32_t *__restrict__ sums)
+// Per-block totals of the counts; reads are coalesced (the order of an integer
+// sum does not matter).
+__global__ void __launch_bounds__(kThreads) k_scan_reduce(const uint32_t *__restrict__ in, int n,
+                                                          uint32_t *__restrict__ sums)
 {
     __shared__ uint32_t lds[kThreads / 64];
-    int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    const int base = blockIdx.x * kScanTile + threadIdx.x;
     uint32_t s = 0;
+#pragma unroll
     for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) s += in[base + k];
+        if (base + k * kThreads < n) s += in[base + k * kThreads];
     uint32_t tot;
     block_exclusive_scan(s, lds, tot);
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
@@ -108,33 +112,53 @@ __global__ void k_scan_reduce(const uint32_t *__restrict__ in, int n, uint32_t *
 
 // Block b adds the sums of blocks 0..b-1 (read directly: there are at most a few
 // hundred), scans its own tile, writes the cell-start table, and leaves the
-// counts zeroed for the next build.
+// counts zeroed for the next build. The tile passes through LDS so that global
+// reads and writes are coalesced while each thread scans 16 consecutive counts
+// (row padding of one word per 16 keeps the LDS accesses conflict-free).
 __global__ void __launch_bounds__(kThreads) k_scan_down(uint32_t *__restrict__ in, int n,
                                                         const uint32_t *__restrict__ sums,
                                                         uint32_t *__restrict__ out)
 {
     __shared__ uint32_t lds[kThreads / 64];
+    __shared__ uint32_t tile[kScanTile + kScanTile / kScanItems];
+    const int t = threadIdx.x;
+    const int base = blockIdx.x * kScanTile;
+    auto pad = [](int j) { return j + j / kScanItems; };
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int j = k * kThreads + t;
+        uint32_t v = 0u;
+        if (base + j < n) {
+            v = in[base + j];
+            in[base + j] = 0u;
+        }
+        tile[pad(j)] = v;
+    }
     uint32_t before = 0;
-    for (int q = threadIdx.x; q < (int)blockIdx.x; q += blockDim.x) before += sums[q];
+    for (int q = t; q < (int)blockIdx.x; q += blockDim.x) before += sums[q];
     uint32_t block_off;
     block_exclusive_scan(before, lds, block_off);  // block total = sum of preceding blocks
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint32_t s = 0;
+#pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < n ? in[base + k] : 0u;
+        v[k] = tile[pad(t * kScanItems + k)];
         s += v[k];
     }
     uint32_t tot;
     uint32_t run = block_exclusive_scan(s, lds, tot) + block_off;
+#pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) {
-            out[base + k] = run;
-            in[base + k] = 0u;
-        }
+        tile[pad(t * kScanItems + k)] = run;
         run += v[k];
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) out[n] = run;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int j = k * kThreads + t;
+        if (base + j < n) out[base + j] = tile[pad(j)];
+    }
+    if (blockIdx.x == gridDim.x - 1 && t == blockDim.x - 1) out[n] = run;
 }
 
 __global__ void k_scatter(int N, const uint32_t *__restrict__ key, const uint32_t *__restrict__ rank,
@@ -283,27 +307,6 @@ struct NbrArgs {
     int *flags;
 };
 
-template <typename T>
-__device__ inline void write_record(const SimDev &S, void *prec, int i, const double xi[3]);
-
-template <>
-__device__ inline void write_record<float>(const SimDev &S, void *prec, int i, const double xi[3])
-{
-    uint32_t q[4] = {0u, 0u, 0u, 0u};
-    for (int a = 0; a < S.dim; ++a) {
-        double v = floor((xi[a] - S.lo[a]) * S.q_inv[a]);
-        q[a] = (uint32_t)(unsigned long long)(long long)v;
-    }
-    ((uint4 *)prec)[i] = make_uint4(q[0], q[1], q[2], 0u);
-}
-
-template <>
-__device__ inline void write_record<double>(const SimDev &S, void *prec, int i, const double xi[3])
-{
-    (void)S;
-    ((double4 *)prec)[i] = make_double4(xi[0], xi[1], xi[2], 0.0);
-}
-
 // G consecutive lanes share one particle and test its candidates G at a time;
 // a wave ballot gives each lane the number of accepted candidates before it in
 // the group, so the list keeps the sequential scan order.
@@ -370,7 +373,7 @@ __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
         int *__restrict__ cand = A.cand;
         if (grp.sub == 0) {
             const double pos3[3] = {P.xi, P.yi, P.zi};
-            write_record<T>(S, A.prec, i, pos3);
+            write_pos_record<T>(S, A.prec, i, pos3);
         }
         const int cx = cell_coord(P.xi, S.lo[0], S.inv_cs[0], nx);
         const int cy = cell_coord(P.yi, S.lo[1], S.inv_cs[1], ny);
@@ -470,7 +473,6 @@ __global__ void __launch_bounds__(kThreads) k_filter(NbrArgs<T> A)
     const bool active = i < A.N;
     const int N = A.N;
     const int s = active ? A.simid[i] : -1;
-    const bool fluid = i < A.Nf;
     int cf = 0, cw = 0;
     if (active) {
         const SimDev &S = A.sims[s];
@@ -481,7 +483,7 @@ __global__ void __launch_bounds__(kThreads) k_filter(NbrArgs<T> A)
         int *__restrict__ nbr = A.nbr + i;
         if (grp.sub == 0) {
             const double pos3[3] = {P.xi, P.yi, P.zi};
-            write_record<T>(S, A.prec, i, pos3);
+            write_pos_record<T>(S, A.prec, i, pos3);
         }
         const uint32_t cc = A.ccnt[i];
         const int ncf = (int)(cc & 0xffffu), nct = ncf + (int)(cc >> 16);
@@ -582,6 +584,7 @@ void build_cells(Ctx &c)
     hipLaunchKernelGGL(k_rank_gather<T>, dim3(grid_for(N)), dim3(kThreads), 0, st, g);
     c.buf = o;
     c.xb ^= 1;
+    c.records_fresh = false;  // the slots moved
     launch_nbr_lists<T>(c, false);
     timer_end(c, t0, 2);
 }

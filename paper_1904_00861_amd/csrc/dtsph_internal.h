@@ -29,6 +29,8 @@ namespace dtsph {
 constexpr int kHist = 8;             // residual history ring (stall window <= 8)
 constexpr int kMaxCellOccupancy = 4096;
 constexpr int kMaxBlock = 256;
+constexpr int kMaxRanges = 32;       // active tile ranges passed to the pair pass
+constexpr int kSegTiles = 256;       // tiles per residual segment (one finalize workgroup)
 
 enum PassMode { MODE_PRE = 0, MODE_PSEUDO = 1 };
 
@@ -42,6 +44,7 @@ struct SimDev {
     int fluid_begin;     // first fluid slot
     int key_base;        // first fluid key; wall keys add the total cell count
     int tile_begin, tile_end;  // fluid tiles of this sim (residual partials)
+    int seg_begin, seg_count;  // residual segments (runs of up to kSegTiles tiles)
     int ncell[3];
     int cell_div;        // cells of side >= (kappa h + skin) / cell_div; blocks of +-cell_div cells
     int periodic[3];
@@ -108,8 +111,18 @@ struct Ctx {
     bool cells_valid = false;  // exact lists match the current positions
     bool cand_ok = false;      // candidate lists cover the current positions
     bool cand_next = false;    // ... will cover r^{n+1} (decided by the loop)
-    int cur = 0;             // which vp buffer is current
+    int cur = 0;             // vp buffer read by the rate pass and the first
+                             // iteration; sim s then alternates by its own
+                             // iteration count (buffer (cur + iters_s) & 1)
+    bool p_half = false;     // pm holds p^{K+1/2} (the half step back to p^K
+                             // is applied by the corrector / state readout)
+    bool records_fresh = false;  // vp[cur] and the position records hold the
+                                 // state at the current positions (corrector)
     int last_iters = 4;      // adaptive chunking
+    // pair-pass launches inside a loop cover only sims still iterating: tile
+    // ranges (first tile, index within the launch); n_ranges == 0: every tile
+    int n_ranges = 0, n_act_tiles = 0;
+    int2 ranges[kMaxRanges];
 
     // device memory: every device array of the context is registered with the
     // address of the field that points to it, so that the whole set can move into
@@ -153,6 +166,11 @@ struct Ctx {
     int capc = 0;
     int2 *tiles = nullptr;
     int n_tiles = 0;
+    int4 *segs = nullptr;                 // per segment: sim, first tile, end tile, index in sim
+    int n_segs = 0;
+    double4 *seg_p = nullptr;             // per segment: partial sums of the residual terms
+    double2 *seg_p2 = nullptr;
+    uint32_t *tickets = nullptr;          // per sim: segments of the running finalize done
     double4 *partials = nullptr;
     double2 *partials2 = nullptr;         // per tile: max |V^{k+1} - V^(0)|^2, pairs
     int *flags = nullptr;
@@ -183,12 +201,11 @@ template <typename T> void build_cells(Ctx &c);        // dtsph_cells.hip
 template <typename T> void filter_lists(Ctx &c);
 template <typename T> void launch_nbr_lists(Ctx &c, bool filter);
 template <typename T> void launch_pre_records(Ctx &c);
-template <typename T> void launch_wall(Ctx &c, int mode);
-template <typename T> void launch_pass(Ctx &c, int mode);
+template <typename T> void launch_wall(Ctx &c, int mode, bool cand_lists = false);
+template <typename T> void launch_pass(Ctx &c, int mode, bool cand_lists = false);
 void launch_finalize(Ctx &c);
 void launch_publish(Ctx &c);
 template <typename T> void launch_loop_begin(Ctx &c, int fixed_iters);
-template <typename T> void launch_loop_end(Ctx &c);
 template <typename T> void launch_correct(Ctx &c);
 template <typename T> void launch_set_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
 template <typename T> void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
@@ -218,5 +235,29 @@ struct ApiError {
 };
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Position record of slot i read by the pair passes: FP32 path 32-bit fixed
+// point per axis, x_q = floor((x - lo) * q_inv) mod 2^32 (exact wrap on periodic
+// axes, whose q_len divides the period); FP64 path the float64 coordinates.
+template <typename T>
+__device__ inline void write_pos_record(const SimDev &S, void *prec, int i, const double xi[3]);
+
+template <>
+__device__ inline void write_pos_record<float>(const SimDev &S, void *prec, int i, const double xi[3])
+{
+    uint32_t q[4] = {0u, 0u, 0u, 0u};
+    for (int a = 0; a < S.dim; ++a) {
+        double v = floor((xi[a] - S.lo[a]) * S.q_inv[a]);
+        q[a] = (uint32_t)(unsigned long long)(long long)v;
+    }
+    ((uint4 *)prec)[i] = make_uint4(q[0], q[1], q[2], 0u);
+}
+
+template <>
+__device__ inline void write_pos_record<double>(const SimDev &S, void *prec, int i, const double xi[3])
+{
+    (void)S;
+    ((double4 *)prec)[i] = make_double4(xi[0], xi[1], xi[2], 0.0);
+}
 
 }  // namespace dtsph

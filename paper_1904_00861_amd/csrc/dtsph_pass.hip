@@ -166,15 +166,18 @@ __device__ inline int tile_of_block(int n_tiles, int remap)
 
 template <typename T> struct PassArgs {
     using Q = typename V4<T>::type;
-    int N, Nf, Nw, n_tiles, remap;
+    int N, Nf, Nw, n_tiles, remap;  // n_tiles: tiles this launch covers
+    int cur, n_ranges;
+    // when n_ranges > 0 the launch covers only these tile ranges (sims whose loop
+    // is still running): (first tile, index of that tile within the launch)
+    int2 ranges[kMaxRanges];
     const int2 *tiles;
     const SimDev *sims;
     const SimIter *iters;
     const int *nbr;
     const uint32_t *cnt;
     const void *prec;
-    const Q *vin;
-    Q *vout;
+    Q *vp0, *vp1;   // {V, p} records, ping-ponged per sim
     const T *vwall;
     const T *vn, *dv;
     T *w, *w0, *dp;
@@ -185,6 +188,19 @@ template <typename T> struct PassArgs {
     double2 *partials2;   // per tile: {max |V^{k+1} - V^(0)|^2, neighbour pairs}
 };
 
+template <typename T> __device__ inline int launch_tile(const PassArgs<T> &A, int v)
+{
+    if (A.n_ranges == 0) return v;
+    int first = A.ranges[0].x, at = A.ranges[0].y;
+#pragma unroll
+    for (int q = 1; q < kMaxRanges; ++q) {  // static indices: kernel-argument loads
+        const bool take = q < A.n_ranges && A.ranges[q].y <= v;
+        first = take ? A.ranges[q].x : first;
+        at = take ? A.ranges[q].y : at;
+    }
+    return first + (v - at);
+}
+
 template <typename T> __device__ inline void lane_sum(T &v, int lpp)
 {
     for (int o = lpp >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -193,14 +209,22 @@ template <typename T> __device__ inline void lane_sum(T &v, int lpp)
 // LPP lanes share one particle: lane `sub` takes neighbour entries sub, sub+LPP,
 // ... and the partial sums are combined with butterfly shuffles, so that small
 // problems still put enough waves on every SIMD to hide the gather latency.
+// Occupancy target (waves per SIMD) of the pair pass: the gathers are latency
+// bound, so the register budget is capped where that costs no spills.
+template <typename T, int DIM, bool HEAVY> struct PassWaves {
+    static constexpr int value = sizeof(T) == 4 ? (DIM == 2 ? 6 : 4) : (DIM == 2 && !HEAVY ? 5 : 4);
+};
+
 template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP>
-__global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(PassWaves<T, DIM, WALLS && AV && SEPDEN>::value)))
+k_pass(PassArgs<T> A)
 {
     using Q = typename V4<T>::type;
     using PosT = Pos<T, DIM>;
     using Rec = typename PosT::Rec;
-    const int t = tile_of_block(A.n_tiles, A.remap);
-    if (t < 0) return;
+    const int v = tile_of_block(A.n_tiles, A.remap);
+    if (v < 0) return;
+    const int t = launch_tile(A, v);
     const int2 tl = A.tiles[t];
     const int s = tl.x;
     const SimDev &S = A.sims[s];
@@ -210,16 +234,21 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
     const bool owner = active && sub == 0;
     const int N = A.N, Nf = A.Nf;
 
-    if (MODE == MODE_PSEUDO && A.iters[s].done) {  // uniform per block
-        if (owner) A.vout[i] = A.vin[i];
-        if (threadIdx.x == 0) { A.partials[t] = make_double4(0.0, 0.0, 0.0, 0.0); A.partials2[t] = make_double2(0.0, 0.0); }
-        return;
+    // Record buffers: the rate pass reads buffer `cur`; iteration k of sim s reads
+    // buffer (cur + k) & 1 and writes the other, so a sim whose loop has stopped
+    // simply drops out (uniform per block).
+    int par = A.cur;
+    if (MODE == MODE_PSEUDO) {
+        const SimIter &It = A.iters[s];
+        if (It.done) return;
+        par = (A.cur + It.iters) & 1;
     }
+    const Q *__restrict__ vin = par ? A.vp1 : A.vp0;
+    Q *__restrict__ vout = par ? A.vp0 : A.vp1;
 
     const PassConst<T> K(S);
     const PosT pos(S);
     const Rec *__restrict__ prec = (const Rec *)A.prec;
-    const Q *__restrict__ vin = A.vin;
 
     Acc<T> acc;
     T pi = 0, vi[3] = {0, 0, 0};
@@ -319,7 +348,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassArgs<T> A)
             const double pm = A.pm[i] + S.dtau * (double)Dv;
             A.pm[i] = pm;
             A.dp[i] = Dv;
-            A.vout[i] = make_rec<T, DIM>(vnew, (T)pm);
+            vout[i] = make_rec<T, DIM>(vnew, (T)pm);
         } else {
             const double dt = S.dt, hdt2 = 0.5 * S.dt * S.dt;
             for (int d = 0; d < DIM; ++d) {
@@ -389,7 +418,8 @@ template <typename T> struct WallArgs {
     const int *nbr;
     const uint32_t *cnt;
     const void *prec;
-    Q *vin;          // reads fluid records, writes wall records
+    Q *vp0, *vp1;    // reads fluid records, writes wall records (same buffer)
+    int cur;
     const T *vwall;
     T *pwall;
     const double *x;
@@ -408,11 +438,15 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
     const int N = A.N;
     const int s = A.simid[i];
     const SimDev &S = A.sims[s];
+    int par = A.cur;
     if (A.mode == MODE_PRE) {
         for (int d = 0; d < 3; ++d) A.x_alt[d * N + i] = A.x[d * N + i];
-    } else if (A.iters[s].done) {
-        return;
+    } else {
+        const SimIter &It = A.iters[s];
+        if (It.done) return;
+        par = (A.cur + It.iters) & 1;
     }
+    Q *__restrict__ vin = par ? A.vp1 : A.vp0;
     const PosT pos(S);
     const Rec *__restrict__ prec = (const Rec *)A.prec;
     const Rec ri = prec[i];
@@ -424,7 +458,7 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
     for (int k = 0; k < nfl; ++k) {
         const int j = nb[(size_t)k * N];
         const Rec rj = prec[j];
-        const Q vj = A.vin[j];
+        const Q vj = vin[j];
         T r[3];
         pos.delta(ri, rj, r);
         T r2 = r[0] * r[0] + r[1] * r[1];
@@ -455,75 +489,122 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
     } else {
         for (int d = 0; d < DIM; ++d) ghost[d] = vw[d];
     }
-    A.vin[i] = make_rec<T, DIM>(ghost, pw);
+    vin[i] = make_rec<T, DIM>(ghost, pw);
     A.pwall[iw] = pw;
 }
 
 // ---- residual reduction and stop test (section 3.4) --------------------------
-// Also writes each sim's report and stop flag into mapped host memory (and
-// moves any build flag there), so the host only needs a stream sync.
-__global__ void __launch_bounds__(256) k_finalize(const SimDev *__restrict__ sims, SimIter *__restrict__ iters,
-                                                  const double4 *__restrict__ partials,
-                                                  const double2 *__restrict__ partials2, int *__restrict__ done_out,
-                                                  int *__restrict__ flags, int n_sims, int *__restrict__ h_flags,
-                                                  MirrorRep *__restrict__ h_reps,
-                                                  unsigned long long *__restrict__ h_pairs)
+// Two levels in one launch: workgroup g reduces the partials of segment g (up to
+// kSegTiles tiles of one sim, fixed order); the last segment of a sim to arrive
+// (per-sim ticket) reduces that sim's segment sums in segment order, applies the
+// stop test and writes the sim's report and stop flag into mapped host memory
+// (moving any build flag there too), so the host only needs a stream sync.
+// Which workgroup arrives last does not change any sum.
+struct FinArgs {
+    const SimDev *sims;
+    SimIter *iters;
+    const double4 *partials;
+    const double2 *partials2;
+    const int4 *segs;
+    double4 *seg_p;
+    double2 *seg_p2;
+    uint32_t *tickets;
+    int *done_out, *flags;
+    int n_sims;
+    int *h_flags;
+    MirrorRep *h_reps;
+    unsigned long long *h_pairs;
+};
+
+constexpr int kFinThreads = kSegTiles;
+
+// Fixed-order workgroup reduction of {sum, sum, max, max, max, sum}; result in
+// thread 0.
+__device__ inline void fin_block_reduce(double v[6])
 {
-    __shared__ double lds[4][6];
-    const int s = blockIdx.x;
+    __shared__ double lds[kFinThreads / 64][6];
+    for (int o = 32; o > 0; o >>= 1) {
+        v[0] += __shfl_xor(v[0], o, 64);
+        v[1] += __shfl_xor(v[1], o, 64);
+        v[5] += __shfl_xor(v[5], o, 64);
+        v[2] = fmax(v[2], __shfl_xor(v[2], o, 64));
+        v[3] = fmax(v[3], __shfl_xor(v[3], o, 64));
+        v[4] = fmax(v[4], __shfl_xor(v[4], o, 64));
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    SimIter &It = iters[s];
-    if (s == 0 && threadIdx.x < F_COUNT) {
-        const int f = flags[threadIdx.x];
-        if (f) {
-            h_flags[threadIdx.x] = f;
-            flags[threadIdx.x] = 0;
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) lds[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kFinThreads / 64; ++w) {
+            v[0] += lds[w][0];
+            v[1] += lds[w][1];
+            v[2] = fmax(v[2], lds[w][2]);
+            v[3] = fmax(v[3], lds[w][3]);
+            v[4] = fmax(v[4], lds[w][4]);
+            v[5] += lds[w][5];
         }
     }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
+{
+    __shared__ int last;
+    const int g = blockIdx.x;
+    const int4 sg = A.segs[g];
+    const int s = sg.x;
+    if (g == 0 && threadIdx.x < F_COUNT) {
+        const int f = A.flags[threadIdx.x];
+        if (f) {
+            A.h_flags[threadIdx.x] = f;
+            A.flags[threadIdx.x] = 0;
+        }
+    }
+    SimIter &It = A.iters[s];
     if (It.done) {
-        if (threadIdx.x == 0) {
-            done_out[s] = 1;
-            h_flags[F_COUNT + s] = 1;
+        if (sg.w == 0 && threadIdx.x == 0) {
+            A.done_out[s] = 1;
+            A.h_flags[F_COUNT + s] = 1;
         }
         return;
     }
-    const SimDev &S = sims[s];
-    double sd = 0, sv = 0, md = 0, mv = 0, mw = 0, np = 0;
-    const int tb = S.tile_begin, te = S.tile_end;
-#pragma unroll 4
-    for (int t = tb + (int)threadIdx.x; t < te; t += 256) {
-        const double4 p = partials[t];
-        const double2 p2 = partials2[t];
-        sd += p.x;
-        sv += p.y;
-        md = fmax(md, p.z);
-        mv = fmax(mv, p.w);
-        mw = fmax(mw, p2.x);
-        np += p2.y;
+    const SimDev &S = A.sims[s];
+    double red[6] = {0, 0, 0, 0, 0, 0};
+    const int t = sg.y + (int)threadIdx.x;
+    if (t < sg.z) {
+        const double4 p = A.partials[t];
+        const double2 p2 = A.partials2[t];
+        red[0] = p.x; red[1] = p.y; red[2] = p.z; red[3] = p.w; red[4] = p2.x; red[5] = p2.y;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        sd += __shfl_xor(sd, o, 64);
-        sv += __shfl_xor(sv, o, 64);
-        np += __shfl_xor(np, o, 64);
-        md = fmax(md, __shfl_xor(md, o, 64));
-        mv = fmax(mv, __shfl_xor(mv, o, 64));
-        mw = fmax(mw, __shfl_xor(mw, o, 64));
-    }
-    if (lane == 0) {
-        lds[wave][0] = sd; lds[wave][1] = sv; lds[wave][2] = md; lds[wave][3] = mv; lds[wave][4] = mw;
-        lds[wave][5] = np;
+    fin_block_reduce(red);
+    if (threadIdx.x == 0) {
+        A.seg_p[g] = make_double4(red[0], red[1], red[2], red[3]);
+        A.seg_p2[g] = make_double2(red[4], red[5]);
+        __threadfence();  // segment sums visible before the arrival is counted
+        last = atomicAdd(&A.tickets[s], 1u) == (uint32_t)(S.seg_count - 1);
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    sd = lds[0][0]; sv = lds[0][1]; md = lds[0][2]; mv = lds[0][3]; mw = lds[0][4]; np = lds[0][5];
-    for (int w = 1; w < 4; ++w) {
-        sd += lds[w][0];
-        sv += lds[w][1];
-        md = fmax(md, lds[w][2]);
-        mv = fmax(mv, lds[w][3]);
-        mw = fmax(mw, lds[w][4]);
-        np += lds[w][5];
+    if (!last) return;
+    __threadfence();
+    for (int k = 0; k < 6; ++k) red[k] = 0.0;
+    for (int q = (int)threadIdx.x; q < S.seg_count; q += kFinThreads) {
+        const double4 p = A.seg_p[S.seg_begin + q];
+        const double2 p2 = A.seg_p2[S.seg_begin + q];
+        if (q == (int)threadIdx.x) {
+            red[0] = p.x; red[1] = p.y; red[2] = p.z; red[3] = p.w; red[4] = p2.x; red[5] = p2.y;
+        } else {
+            red[0] += p.x; red[1] += p.y; red[2] = fmax(red[2], p.z); red[3] = fmax(red[3], p.w);
+            red[4] = fmax(red[4], p2.x); red[5] += p2.y;
+        }
     }
+    fin_block_reduce(red);
+    if (threadIdx.x != 0) return;
+    A.tickets[s] = 0u;
+    const double sd = red[0], sv = red[1], md = red[2], mv = red[3], mw = red[4], np = red[5];
+    int *done_out = A.done_out, *h_flags = A.h_flags;
+    MirrorRep *h_reps = A.h_reps;
+    unsigned long long *h_pairs = A.h_pairs;
     It.disp = 0.5 * S.dt * sqrt(mw);
     It.pairs = (long long)np;
     const double pscale = S.dt / (S.rho0 * S.c * S.c);
@@ -612,16 +693,17 @@ __global__ void k_publish(int n_sims, int *__restrict__ flags, const SimIter *__
 
 // ---- per-particle kernels -------------------------------------------------------
 
-// {V, p} records of the fluid; at the start of a loop (half_step) also the
-// stage-1 half step of p and the reset of every sim's loop state.
+// {V, p} records of the fluid; at the start of a loop (reset) also the reset of
+// every sim's loop state and, unless the pressure master already holds it
+// (add_half = 0), the stage-1 half step of p.
 template <typename T, int DIM>
 __global__ void k_records(int Nf, const int *__restrict__ simid, const SimDev *__restrict__ sims,
                           const T *__restrict__ vn, const T *__restrict__ w, double *__restrict__ pm,
-                          const T *__restrict__ dp, typename V4<T>::type *__restrict__ vout, int half_step,
-                          SimIter *__restrict__ iters, int n_sims, int fixed)
+                          const T *__restrict__ dp, typename V4<T>::type *__restrict__ vout, int reset,
+                          int add_half, SimIter *__restrict__ iters, int n_sims, int fixed)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (half_step && i < n_sims) {
+    if (reset && i < n_sims) {
         SimIter z{};
         z.fixed = fixed;
         for (int k = 0; k < kHist; ++k) { z.hp[k] = 0.0; z.hv[k] = 0.0; }
@@ -629,7 +711,7 @@ __global__ void k_records(int Nf, const int *__restrict__ simid, const SimDev *_
     }
     if (i >= Nf) return;
     double p = pm[i];
-    if (half_step) {  // p^{k+1/2} = p^k + dtau/2 (dp/dtau)^k
+    if (add_half) {  // p^{k+1/2} = p^k + dtau/2 (dp/dtau)^k
         p += 0.5 * sims[simid[i]].dtau * (double)dp[i];
         pm[i] = p;
     }
@@ -638,27 +720,31 @@ __global__ void k_records(int Nf, const int *__restrict__ simid, const SimDev *_
     vout[i] = make_rec<T, DIM>(v, (T)p);
 }
 
-template <typename T>
-__global__ void k_loop_end(int Nf, const int *__restrict__ simid, const SimDev *__restrict__ sims,
-                           double *__restrict__ pm, const T *__restrict__ dp)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Nf) return;
-    pm[i] -= 0.5 * sims[simid[i]].dtau * (double)dp[i];
-}
-
+// Corrector (eq. r-update) fused with the end of the loop and the set-up of the
+// next rate pass: p^K = p^{K+1/2} - dtau/2 (dp/dtau)^K (when pending), positions
+// r^{n+1} = r^n + dt/2 (V^n + V^{n+1}) with periodic wrap, history rotation,
+// position records and the {V^{n+1}, p^{n+1}} records of buffer `vrec`.
 template <typename T>
 __global__ void k_correct(int N, int Nf, const int *__restrict__ simid, const SimDev *__restrict__ sims,
                           double *__restrict__ x, const double *__restrict__ xn, T *__restrict__ vn,
-                          T *__restrict__ dv, T *__restrict__ w, void *__restrict__ xr)
+                          T *__restrict__ dv, T *__restrict__ w, void *__restrict__ xr, double *__restrict__ pm,
+                          const T *__restrict__ dp, int half, void *__restrict__ prec,
+                          typename V4<T>::type *__restrict__ vrec)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Nf) return;
     const SimDev &S = sims[simid[i]];
+    double p = pm[i];
+    if (half) {
+        p -= 0.5 * S.dtau * (double)dp[i];
+        pm[i] = p;
+    }
     double xo[3] = {0.0, 0.0, 0.0};
+    T vr[3] = {T(0), T(0), T(0)};
     for (int d = 0; d < S.dim; ++d) {
         const T v0 = vn[d * Nf + i];
         const T v1 = v0 + w[d * Nf + i];
+        vr[d] = v1;
         double xv = xn[d * N + i] + 0.5 * S.dt * ((double)v0 + (double)v1);
         if (S.periodic[d]) {
             if (xv >= S.hi[d]) xv -= S.L[d];
@@ -672,11 +758,14 @@ __global__ void k_correct(int N, int Nf, const int *__restrict__ simid, const Si
     }
     if (S.dim == 2) ((double2 *)xr)[i] = make_double2(xo[0], xo[1]);
     else ((double4 *)xr)[i] = make_double4(xo[0], xo[1], xo[2], 0.0);
+    write_pos_record<T>(S, prec, i, xo);
+    vrec[i] = S.dim == 2 ? make_rec<T, 2>(vr, (T)p) : make_rec<T, 3>(vr, (T)p);
 }
 
 template <typename T>
 struct StateArgs {
-    int N, Nf, Nw, in_loop;
+    int N, Nf, Nw, in_loop, p_half;
+    const SimDev *sims;
     const int *init_slot, *init_sim;
     int *orig, *simid;
     double *x, *xn;
@@ -737,7 +826,7 @@ __global__ void k_get_state(StateArgs<T> A)
             if (A.cvi) A.cvi[3 * c + d] = (double)(vn + A.w[d * Nf + i]);
         }
         if (A.cp) A.cp[c] = lp ? A.pn[i] : A.pm[i];
-        if (A.cpi) A.cpi[c] = A.pm[i];
+        if (A.cpi) A.cpi[c] = A.p_half ? A.pm[i] - 0.5 * A.sims[A.simid[i]].dtau * (double)A.dp[i] : A.pm[i];
         if (A.cdp) A.cdp[c] = (double)A.dp[i];
     } else {
         const int iw = i - Nf;
@@ -755,15 +844,26 @@ __global__ void k_get_state(StateArgs<T> A)
 
 inline int grid_for(int n, int b = 256) { return n > 0 ? ceil_div(n, b) : 1; }
 
-template <typename T> PassArgs<T> pass_args(Ctx &c)
+template <typename T> PassArgs<T> pass_args(Ctx &c, int mode, bool cand_lists)
 {
     using Q = typename V4<T>::type;
     const int b = c.buf;
     PassArgs<T> a;
-    a.N = c.N; a.Nf = c.Nf; a.Nw = c.Nw; a.n_tiles = c.n_tiles; a.remap = c.xcd_remap;
-    a.tiles = c.tiles; a.sims = c.sims; a.iters = c.iters; a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec;
-    a.vin = (const Q *)c.vp[c.cur];
-    a.vout = (Q *)c.vp[c.cur ^ 1];
+    a.N = c.N; a.Nf = c.Nf; a.Nw = c.Nw; a.remap = c.xcd_remap;
+    a.n_tiles = c.n_tiles;
+    a.n_ranges = 0;
+    if (mode == MODE_PSEUDO && c.n_ranges > 0) {
+        a.n_tiles = c.n_act_tiles;
+        a.n_ranges = c.n_ranges;
+        for (int q = 0; q < c.n_ranges; ++q) a.ranges[q] = c.ranges[q];
+    }
+    for (int q = a.n_ranges; q < kMaxRanges; ++q) a.ranges[q] = make_int2(0, 0);
+    a.cur = c.cur;
+    a.tiles = c.tiles; a.sims = c.sims; a.iters = c.iters; a.prec = c.prec;
+    a.nbr = cand_lists ? c.cand : c.nbr;
+    a.cnt = cand_lists ? c.ccnt : c.cnt;
+    a.vp0 = (Q *)c.vp[0];
+    a.vp1 = (Q *)c.vp[1];
     a.vwall = (const T *)c.vw[b];
     a.vn = (const T *)c.vn[b]; a.dv = (const T *)c.dv[b];
     a.w = (T *)c.w[b]; a.w0 = (T *)c.w0[b]; a.dp = (T *)c.dp[b];
@@ -819,30 +919,32 @@ void dispatch_walls(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
 }  // namespace
 
 template <typename T>
-void launch_pass(Ctx &c, int mode)
+void launch_pass(Ctx &c, int mode, bool cand_lists)
 {
-    PassArgs<T> a = pass_args<T>(c);
-    const int grid = c.xcd_remap ? 8 * ((c.n_tiles + 7) / 8) : c.n_tiles;
+    PassArgs<T> a = pass_args<T>(c, mode, cand_lists);
+    if (a.n_tiles == 0) return;
+    const int grid = c.xcd_remap ? 8 * ((a.n_tiles + 7) / 8) : a.n_tiles;
     int t0 = mode == MODE_PSEUDO ? timer_begin(c) : -1;
     if (c.max_dim == 2) dispatch_walls<T, 2>(c, mode, a, dim3(grid));
     else dispatch_walls<T, 3>(c, mode, a, dim3(grid));
     DTSPH_HIP_CHECK(hipGetLastError());
-    if (mode == MODE_PSEUDO) {
-        timer_end(c, t0, 0);
-        c.cur ^= 1;
-    }
+    if (mode == MODE_PSEUDO) timer_end(c, t0, 0);
 }
 
 template <typename T>
-void launch_wall(Ctx &c, int mode)
+void launch_wall(Ctx &c, int mode, bool cand_lists)
 {
     if (c.Nw == 0) return;
     using Q = typename V4<T>::type;
     const int b = c.buf;
     WallArgs<T> a;
     a.N = c.N; a.Nf = c.Nf; a.Nw = c.Nw; a.mode = mode;
-    a.simid = c.simid[b]; a.sims = c.sims; a.iters = c.iters; a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec;
-    a.vin = (Q *)c.vp[c.cur];
+    a.simid = c.simid[b]; a.sims = c.sims; a.iters = c.iters; a.prec = c.prec;
+    a.nbr = cand_lists ? c.cand : c.nbr;
+    a.cnt = cand_lists ? c.ccnt : c.cnt;
+    a.vp0 = (Q *)c.vp[0];
+    a.vp1 = (Q *)c.vp[1];
+    a.cur = c.cur;
     a.vwall = (const T *)c.vw[b];
     a.pwall = (T *)c.pw[b];
     a.x = c.x[c.xb]; a.x_alt = c.x[c.xb ^ 1];
@@ -863,8 +965,12 @@ void launch_publish(Ctx &c)
 
 void launch_finalize(Ctx &c)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(c.n_sims), dim3(256), 0, c.stream, c.sims, c.iters, c.partials, c.partials2,
-                       c.done_dev, c.flags, c.n_sims, c.m_flags_d, c.m_reps_d, c.m_pairs_d);
+    FinArgs a;
+    a.sims = c.sims; a.iters = c.iters; a.partials = c.partials; a.partials2 = c.partials2;
+    a.segs = c.segs; a.seg_p = c.seg_p; a.seg_p2 = c.seg_p2; a.tickets = c.tickets;
+    a.done_out = c.done_dev; a.flags = c.flags; a.n_sims = c.n_sims;
+    a.h_flags = c.m_flags_d; a.h_reps = c.m_reps_d; a.h_pairs = c.m_pairs_d;
+    hipLaunchKernelGGL(k_finalize, dim3(c.n_segs), dim3(kFinThreads), 0, c.stream, a);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -876,11 +982,11 @@ void launch_pre_records(Ctx &c)
     if (c.max_dim == 2)
         hipLaunchKernelGGL((k_records<T, 2>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
                            (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0,
-                           c.iters, c.n_sims, 0);
+                           0, c.iters, c.n_sims, 0);
     else
         hipLaunchKernelGGL((k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
                            (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0,
-                           c.iters, c.n_sims, 0);
+                           0, c.iters, c.n_sims, 0);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -892,20 +998,11 @@ void launch_loop_begin(Ctx &c, int fixed_iters)
     if (c.max_dim == 2)
         hipLaunchKernelGGL((k_records<T, 2>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
                            (const T *)c.vn[b], (const T *)c.w[b], c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 1,
-                           c.iters, c.n_sims, fixed_iters);
+                           c.p_half ? 0 : 1, c.iters, c.n_sims, fixed_iters);
     else
         hipLaunchKernelGGL((k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
                            (const T *)c.vn[b], (const T *)c.w[b], c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 1,
-                           c.iters, c.n_sims, fixed_iters);
-    DTSPH_HIP_CHECK(hipGetLastError());
-}
-
-template <typename T>
-void launch_loop_end(Ctx &c)
-{
-    const int b = c.buf;
-    hipLaunchKernelGGL(k_loop_end<T>, dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims, c.pm[b],
-                       (const T *)c.dp[b]);
+                           c.p_half ? 0 : 1, c.iters, c.n_sims, fixed_iters);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -913,8 +1010,10 @@ template <typename T>
 void launch_correct(Ctx &c)
 {
     const int b = c.buf;
+    using Q = typename V4<T>::type;
     hipLaunchKernelGGL(k_correct<T>, dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.N, c.Nf, c.simid[b], c.sims,
-                       c.x[c.xb], c.xn[b], (T *)c.vn[b], (T *)c.dv[b], (T *)c.w[b], c.xr);
+                       c.x[c.xb], c.xn[b], (T *)c.vn[b], (T *)c.dv[b], (T *)c.w[b], c.xr, c.pm[b],
+                       (const T *)c.dp[b], c.p_half ? 1 : 0, c.prec, (Q *)c.vp[c.cur]);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -924,6 +1023,8 @@ static StateArgs<T> state_args(Ctx &c, const dtsph_state_view &s, bool in_loop)
     const int b = c.buf;
     StateArgs<T> a;
     a.N = c.N; a.Nf = c.Nf; a.Nw = c.Nw; a.in_loop = in_loop ? 1 : 0;
+    a.p_half = in_loop && c.p_half ? 1 : 0;
+    a.sims = c.sims;
     a.init_slot = c.init_slot; a.init_sim = c.init_slot + c.N;
     a.orig = c.orig[b]; a.simid = c.simid[b];
     a.x = c.x[c.xb]; a.xn = c.xn[b];
@@ -952,11 +1053,10 @@ void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop)
 }
 
 #define DTSPH_INSTANTIATE(T)                                                   \
-    template void launch_pass<T>(Ctx &, int);                                  \
-    template void launch_wall<T>(Ctx &, int);                                  \
+    template void launch_pass<T>(Ctx &, int, bool);                            \
+    template void launch_wall<T>(Ctx &, int, bool);                            \
     template void launch_pre_records<T>(Ctx &);                                \
     template void launch_loop_begin<T>(Ctx &, int);                            \
-    template void launch_loop_end<T>(Ctx &);                                   \
     template void launch_correct<T>(Ctx &);                                    \
     template void launch_set_state<T>(Ctx &, const dtsph_state_view &, bool);  \
     template void launch_get_state<T>(Ctx &, const dtsph_state_view &, bool);
