@@ -84,8 +84,8 @@ extern "C" {
  * Physical inputs of one sim. Uniform density rho0 (the density is held fixed,
  * section 3), mass and smoothing length for all its particles.
  *   dim            2 or 3
- *   max_neighbors  capacity of each particle's neighbour list; 0 = estimate
- *                  1.5 x the lattice count of the support + 8
+ *   max_neighbors  capacity of each particle's neighbour list, at most 8000;
+ *                  0 = estimate 1.5 x the lattice count of the support + 8
  *   h, kappa       smoothing length and support radius kappa*h (quintic: 3)
  *   rho0, mass     density and particle mass
  *   vref, beta     reference speed and beta = c / vref (section 3.4)
@@ -206,8 +206,11 @@ void dtsph_destroy(dtsph_ctx *ctx);
 const char *dtsph_last_error(const dtsph_ctx *ctx);
 
 /* Load / read the particle state (see dtsph_state_view). set_state
- * invalidates the cell lists. Errors: EINVAL (NULL required pointer, wrong
- * phase for in-loop fields), EHIP.                                          */
+ * invalidates the cell lists. On a periodic axis every position (x, and
+ * x_iter when given) must lie in [lo, hi), the interval the step keeps them in.
+ * Errors: EINVAL (NULL required pointer, wrong phase for in-loop fields, a
+ * periodic coordinate outside [lo, hi): the state is then not usable and must
+ * be set again), EHIP.                                                      */
 int dtsph_set_state(dtsph_ctx *ctx, const dtsph_state_view *state);
 int dtsph_get_state(dtsph_ctx *ctx, const dtsph_state_view *state);
 

@@ -9,6 +9,7 @@
 #include <mutex>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 
 #include "dtsph_internal.h"
 
@@ -150,7 +151,7 @@ void check_desc(const dtsph_sim_desc &d, int s, int64_t nf, int64_t nw)
     if (d.max_iter < 1) bad("max_iter must be >= 1");
     if (d.stall_window < 0 || d.stall_window > kHist) bad("stall_window must be in [0, 8]");
     if (d.conv_norm != 0 && d.conv_norm != 1) bad("conv_norm must be 0 or 1");
-    if (d.max_neighbors < 0 || d.max_neighbors > 65535) bad("max_neighbors must be in [0, 65535]");
+    if (d.max_neighbors < 0 || d.max_neighbors > 8000) bad("max_neighbors must be in [0, 8000]");
     for (int a = 0; a < d.dim; ++a) {
         if (!(d.hi[a] > d.lo[a])) bad("hi must exceed lo on every axis");
         if (d.periodic[a] && !(d.kappa * d.h < 0.5 * (d.hi[a] - d.lo[a])))
@@ -334,6 +335,7 @@ void resolve_timers(Ctx &c)
 {
     for (auto &pr : c.ev_pending) {
         float ms = 0.f;
+        DTSPH_HIP_CHECK(hipEventSynchronize(c.ev_pool[pr.first + 1]));
         DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, c.ev_pool[pr.first], c.ev_pool[pr.first + 1]));
         if (pr.second == 0) { c.tstats.pass_launches++; c.tstats.pass_ms += ms; }
         else if (pr.second == 1) { c.tstats.wall_launches++; c.tstats.wall_ms += ms; }
@@ -350,14 +352,43 @@ void check_host_flags(Ctx &c)
 {
     if (c.timing) resolve_timers(c);
     const int over = c.flags_host[F_NBR_OVERFLOW], need = c.flags_host[F_NBR_NEEDED];
-    const int cell = c.flags_host[F_CELL_OVERFLOW];
+    const int cell = c.flags_host[F_CELL_OVERFLOW], outside = c.flags_host[F_OUTSIDE];
     for (int k = 0; k < F_COUNT; ++k) c.flags_host[k] = 0;
+    if (outside)
+        throw ApiError(DTSPH_EINVAL, "a position on a periodic axis lies outside [lo, hi); the state was not "
+                                     "accepted (set it again)");
     if (over)
         throw ApiError(DTSPH_EOVERFLOW, "neighbour list capacity " + std::to_string(c.cap) + " exceeded; needs " +
                                             std::to_string(need) + " (set max_neighbors); particle state is undefined");
     if (cell)
         throw ApiError(DTSPH_EOVERFLOW, "a cell holds more than 4096 particles (particles far outside the grid "
                                         "box or clumped); particle state is undefined");
+}
+
+// Wait until the last finalize has published every sim's report: spin on the
+// per-sim sequence words in mapped memory (each written after its report, behind
+// a system-scope fence), asking the stream for errors now and then.
+void wait_reports(Ctx &c)
+{
+    const volatile int *seq = c.seq_host;
+    auto seen = [&]() {
+        for (int s = 0; s < c.n_sims; ++s)
+            if (seq[s] != c.seq) return false;
+        return true;
+    };
+    for (long spins = 1;; ++spins) {
+        if (seen()) break;
+        __builtin_ia32_pause();
+        if ((spins & 1023) == 0) {
+            const hipError_t e = hipStreamQuery(c.stream);
+            if (e == hipSuccess) {
+                if (seen()) break;
+                throw ApiError(DTSPH_EHIP, "finalize completed without publishing its reports");
+            }
+            if (e != hipErrorNotReady) throw HipError(e, "hipStreamQuery", __FILE__, __LINE__);
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
 }
 
 void readback_flags(Ctx &c)
@@ -450,7 +481,7 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
             launch_finalize(c);
         }
         launched += n;
-        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));  // k_finalize wrote the mapped reports
+        wait_reports(c);  // k_finalize wrote the mapped reports
         check_host_flags(c);
         bool all = true;
         for (int s = 0; s < c.n_sims; ++s) all = all && c.flags_host[F_COUNT + s];
@@ -622,7 +653,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         }
         c.C_max = (int)C;
         setup_keys(c, 2);
-        c.cap = std::min(65535, ((int)std::ceil(cap_est) + 3) / 4 * 4);
+        c.cap = std::min(8000, ((int)std::ceil(cap_est) + 3) / 4 * 4);
 
         // device memory
         dev_alloc(c, c.sims, sizeof(SimDev) * n_sims);
@@ -670,7 +701,8 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         {
             const size_t fb_bytes = (sizeof(int) * (F_COUNT + n_sims) + 15) / 16 * 16;
             const size_t pb_bytes = 8 * (size_t)n_sims;
-            const size_t bytes = fb_bytes + pb_bytes + sizeof(MirrorRep) * n_sims;
+            const size_t rb_bytes = (sizeof(MirrorRep) * n_sims + 15) / 16 * 16;
+            const size_t bytes = fb_bytes + pb_bytes + rb_bytes + sizeof(int) * n_sims;
             DTSPH_HIP_CHECK(hipHostMalloc(&c.mirror_h, bytes, hipHostMallocMapped));
             std::memset(c.mirror_h, 0, bytes);
             void *md = nullptr;
@@ -682,6 +714,8 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             c.m_flags_d = (int *)db;
             c.m_pairs_d = (unsigned long long *)(db + fb_bytes);
             c.m_reps_d = (MirrorRep *)(db + fb_bytes + pb_bytes);
+            c.seq_host = (int *)(hb + fb_bytes + pb_bytes + rb_bytes);
+            c.m_seq_d = (int *)(db + fb_bytes + pb_bytes + rb_bytes);
         }
         DTSPH_HIP_CHECK(hipMemcpy(c.init_slot, init_slot.data(), sizeof(int) * 2 * N, hipMemcpyHostToDevice));
         DTSPH_HIP_CHECK(hipMemset(c.flags, 0, sizeof(int) * (F_COUNT + n_sims)));
@@ -742,7 +776,7 @@ int dtsph_set_state(dtsph_ctx *ctx, const dtsph_state_view *s)
         c.cur = 0;
         c.p_half = false;
         c.records_fresh = false;
-        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+        readback_flags(c);
         return DTSPH_OK;
     });
 }

@@ -287,6 +287,14 @@ struct AxisRange {
         if (per) v = v < 0 ? v + n : (v >= n ? v - n : v);
         return v;
     }
+    // Periodic image of cell k of the block: a particle there, seen from the
+    // block's centre cell, is shifted by +L (wrapped from below) or -L.
+    __device__ double shift(int k, double L) const
+    {
+        if (!per) return 0.0;
+        const int v = first + k;
+        return v < 0 ? L : (v >= n ? -L : 0.0);
+    }
 };
 
 template <typename T>
@@ -330,12 +338,23 @@ template <int DIM> struct Probe {
     double xi, yi, zi, kh2;
     int px, py, pz;
     double Lx, Ly, Lz, hx, hy, hz;
+    // squared separation with the minimum image decided per candidate
     __device__ double r2(const typename XR<DIM>::type &q) const
     {
 #pragma clang fp contract(off)
         const double dx = min_image(xi - q.x, px, Lx, hx);
         const double dy = min_image(yi - q.y, py, Ly, hy);
         const double dz = DIM == 3 ? min_image(zi - XR<DIM>::z(q), pz, Lz, hz) : 0.0;
+        return (dx * dx + dy * dy) + dz * dz;
+    }
+    // squared separation with the periodic shift of the candidate's cell run
+    // (the same roundings: s - L is s + (-L))
+    __device__ double r2s(const typename XR<DIM>::type &q, double sx, double sy, double sz) const
+    {
+#pragma clang fp contract(off)
+        const double dx = (xi - q.x) + sx;
+        const double dy = (yi - q.y) + sy;
+        const double dz = DIM == 3 ? (zi - XR<DIM>::z(q)) + sz : 0.0;
         return (dx * dx + dy * dy) + dz * dz;
     }
 };
@@ -350,115 +369,163 @@ template <int DIM> __device__ inline Probe<DIM> make_probe(const SimDev &S, doub
     return P;
 }
 
+// Running state of one particle's list build.
+struct ListCursor {
+    int total = 0, ctotal = 0;   // entries found so far (exact, candidate)
+};
+
+// Tests the candidates in slots [jb, je) (one run of consecutive cells), G
+// lanes at a time with kBatch positions per lane in flight, and appends the
+// hits to the exact and candidate lists in scan order. GENERAL: minimum image
+// per candidate (needed when a periodic axis has fewer than 2m+3 cells);
+// otherwise the run's periodic shift (sx, sy, sz) applies to all of it.
+template <int DIM, int G, bool GENERAL>
+__device__ __forceinline__ void scan_run(const typename XR<DIM>::type *__restrict__ xr, int jb, int je, int i,
+                                         const Probe<DIM> &P, double sx, double sy, double sz, double cr2,
+                                         int *__restrict__ nbr, int *__restrict__ cand, int N, int cap, int capc,
+                                         const Group<G> &grp, ListCursor &cur)
+{
+    using Q = typename XR<DIM>::type;
+    for (int j0 = jb; j0 < je; j0 += G * kBatch) {  // uniform in the group
+        Q q[kBatch];
+#pragma unroll
+        for (int m = 0; m < kBatch; ++m) {
+            const int j = j0 + m * G + grp.sub;
+            q[m] = xr[j < je ? j : jb];
+        }
+#pragma unroll
+        for (int m = 0; m < kBatch; ++m) {
+            const int j = j0 + m * G + grp.sub;
+            const double r2 = GENERAL ? P.r2(q[m]) : P.r2s(q[m], sx, sy, sz);
+            const bool ok = j < je && j != i;
+            const bool in_c = ok && r2 < cr2, in_x = ok && r2 < P.kh2;
+            if (G == 1) {
+                if (in_c && cur.ctotal < capc) cand[(size_t)cur.ctotal * N] = j;
+                if (in_x && cur.total < cap) nbr[(size_t)cur.total * N] = j;
+                cur.ctotal += in_c;
+                cur.total += in_x;
+            } else {
+                const unsigned bc = grp.bits(in_c), bx = grp.bits(in_x);
+                if (in_c) {
+                    const int qq = cur.ctotal + grp.before(bc);
+                    if (qq < capc) cand[(size_t)qq * N] = j;
+                }
+                if (in_x) {
+                    const int qq = cur.total + grp.before(bx);
+                    if (qq < cap) nbr[(size_t)qq * N] = j;
+                }
+                cur.ctotal += __popc(bc);
+                cur.total += __popc(bx);
+            }
+        }
+    }
+}
+
+// Cell rows of one particle's search block, visited in order (type, plane,
+// row); each row is at most two runs of consecutive cell keys along x. The
+// bounds of the next row are loaded while the current one is scanned.
+template <typename T, int DIM, int G, bool GENERAL>
+__device__ __forceinline__ void scan_block(const NbrArgs<T> &A, const SimDev &S, int i, const Probe<DIM> &P,
+                                           int cx, int cy, int cz, bool fluid, int &cf, int &cw, int &ccf,
+                                           int &ccw, ListCursor &cur, const Group<G> &grp)
+{
+    using Q = typename XR<DIM>::type;
+    const Q *__restrict__ xr = (const Q *)A.xr;
+    const uint32_t *__restrict__ cstart = A.cell_start;
+    const int N = A.N;
+    const int nx = S.ncell[0], ny = S.ncell[1], nz = DIM == 3 ? S.ncell[2] : 1;
+    const int md = S.cell_div;
+    // x cells cx-m .. cx+m as at most two contiguous runs of keys
+    int xa0, xb0, xa1 = 0, xb1 = -1;
+    double sx1 = 0.0;
+    if (P.px && nx < 2 * md + 1) { xa0 = 0; xb0 = nx - 1; }
+    else if (P.px && cx - md < 0) { xa0 = 0; xb0 = cx + md; xa1 = nx + cx - md; xb1 = nx - 1; sx1 = P.Lx; }
+    else if (P.px && cx + md > nx - 1) { xa0 = cx - md; xb0 = nx - 1; xa1 = 0; xb1 = cx + md - nx; sx1 = -P.Lx; }
+    else { xa0 = cx > md ? cx - md : 0; xb0 = cx < nx - 1 - md ? cx + md : nx - 1; }
+    const AxisRange ry(cy, ny, P.py, md), rz(cz, nz, P.pz, DIM == 3 ? md : 0);
+    const int ntp = (fluid && S.nw > 0) ? 2 : 1;  // wall cells only where walls exist
+    const int per_tp = rz.count * ry.count;
+    const int nrows = ntp * per_tp;
+    int *__restrict__ nbr = A.nbr + i;
+    int *__restrict__ cand = A.cand + i;
+    const double cr2 = S.cand_r2;
+    auto row_key = [&](int r, int &u, int &v, int &tp) {
+        tp = r >= per_tp;
+        const int rr = r - tp * per_tp;
+        u = rr / ry.count;
+        v = rr - u * ry.count;
+        return S.key_base + (tp ? A.C : 0) + (rz.at(u) * ny + ry.at(v)) * nx;
+    };
+    int u, v, tp;
+    int row = row_key(0, u, v, tp);
+    int b0 = (int)cstart[row + xa0], e0 = (int)cstart[row + xb0 + 1];
+    int b1 = 0, e1 = 0;
+    if (xb1 >= xa1) { b1 = (int)cstart[row + xa1]; e1 = (int)cstart[row + xb1 + 1]; }
+    cf = -1;
+    for (int r = 0; r < nrows; ++r) {
+        const int cu = u, cv = v, ctp = tp;
+        const int jb0 = b0, je0 = e0, jb1 = b1, je1 = e1;
+        if (r + 1 < nrows) {  // prefetch the next row's bounds
+            row = row_key(r + 1, u, v, tp);
+            b0 = (int)cstart[row + xa0];
+            e0 = (int)cstart[row + xb0 + 1];
+            if (xb1 >= xa1) { b1 = (int)cstart[row + xa1]; e1 = (int)cstart[row + xb1 + 1]; }
+        }
+        if (ctp == 1 && cf < 0) { cf = cur.total; ccf = cur.ctotal; }
+        const double sy = ry.shift(cv, P.Ly), sz = DIM == 3 ? rz.shift(cu, P.Lz) : 0.0;
+        const int nrun = jb1 < je1 ? 2 : 1;
+        for (int k = 0; k < nrun; ++k)  // one code copy for both runs
+            scan_run<DIM, G, GENERAL>(xr, k ? jb1 : jb0, k ? je1 : je0, i, P, k ? sx1 : 0.0, sy, sz, cr2, nbr,
+                                      cand, N, A.cap, A.capc, grp, cur);
+    }
+    if (cf < 0) { cf = cur.total; ccf = cur.ctotal; }
+    cw = cur.total - cf;
+    ccw = cur.ctotal - ccf;
+}
+
 template <typename T, int DIM, int G>
 __global__ void __launch_bounds__(kThreads) k_nbr(NbrArgs<T> A)
 {
     using Q = typename XR<DIM>::type;
     const Group<G> grp;
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) / G;
-    const bool active = i < A.N;
-    const int N = A.N;
-    const int s = active ? A.simid[i] : -1;
+    if (i >= A.N) return;  // whole groups leave together
+    const int s = A.simid[i];
     const bool fluid = i < A.Nf;
-    int cf = 0, cw = 0;
-    if (active) {
-        const SimDev &S = A.sims[s];
-        const Q *__restrict__ xr = (const Q *)A.xr;
-        const Q me = xr[i];
-        const Probe<DIM> P = make_probe<DIM>(S, me.x, me.y, XR<DIM>::z(me));
-        const double cr2 = S.cand_r2;
-        const int nx = S.ncell[0], ny = S.ncell[1], nz = DIM == 3 ? S.ncell[2] : 1;
-        const uint32_t *__restrict__ cstart = A.cell_start;
-        int *__restrict__ nbr = A.nbr;
-        int *__restrict__ cand = A.cand;
+    const SimDev &S = A.sims[s];
+    const Q me = ((const Q *)A.xr)[i];
+    const Probe<DIM> P = make_probe<DIM>(S, me.x, me.y, XR<DIM>::z(me));
+    if (grp.sub == 0) {
+        const double pos3[3] = {P.xi, P.yi, P.zi};
+        write_pos_record<T>(S, A.prec, i, pos3);
+    }
+    const int nx = S.ncell[0], ny = S.ncell[1], nz = DIM == 3 ? S.ncell[2] : 1;
+    const int cx = cell_coord(P.xi, S.lo[0], S.inv_cs[0], nx);
+    const int cy = cell_coord(P.yi, S.lo[1], S.inv_cs[1], ny);
+    const int cz = DIM == 3 ? cell_coord(P.zi, S.lo[2], S.inv_cs[2], nz) : 0;
+    // per-run shifts are exact when every periodic axis has at least 2m+3 cells
+    // (then a block's cells lie within half a period of its centre, by a margin
+    // of half a cell) and positions lie in [lo, hi)
+    const int m3 = 2 * S.cell_div + 3;
+    const bool general = (P.px && nx < m3) || (P.py && ny < m3) || (DIM == 3 && P.pz && nz < m3);
+    ListCursor cur;
+    int cf, cw, ccf, ccw;
+    if (general) scan_block<T, DIM, G, true>(A, S, i, P, cx, cy, cz, fluid, cf, cw, ccf, ccw, cur, grp);
+    else scan_block<T, DIM, G, false>(A, S, i, P, cx, cy, cz, fluid, cf, cw, ccf, ccw, cur, grp);
+    const int cap = A.cap, capc = A.capc;
+    if (cur.total > cap || cur.ctotal > capc) {
         if (grp.sub == 0) {
-            const double pos3[3] = {P.xi, P.yi, P.zi};
-            write_pos_record<T>(S, A.prec, i, pos3);
+            atomicOr(&A.flags[F_NBR_OVERFLOW], 1);
+            atomicMax(&A.flags[F_NBR_NEEDED], cur.total > cur.ctotal ? cur.total : cur.ctotal);
         }
-        const int cx = cell_coord(P.xi, S.lo[0], S.inv_cs[0], nx);
-        const int cy = cell_coord(P.yi, S.lo[1], S.inv_cs[1], ny);
-        const int cz = DIM == 3 ? cell_coord(P.zi, S.lo[2], S.inv_cs[2], nz) : 0;
-        // x cells cx-m .. cx+m as at most two contiguous runs of keys
-        const int md = S.cell_div;
-        int xa0, xb0, xa1 = 0, xb1 = -1;
-        if (P.px && nx < 2 * md + 1) { xa0 = 0; xb0 = nx - 1; }
-        else if (P.px && cx - md < 0) { xa0 = 0; xb0 = cx + md; xa1 = nx + cx - md; xb1 = nx - 1; }
-        else if (P.px && cx + md > nx - 1) { xa0 = cx - md; xb0 = nx - 1; xa1 = 0; xb1 = cx + md - nx; }
-        else { xa0 = cx > md ? cx - md : 0; xb0 = cx < nx - 1 - md ? cx + md : nx - 1; }
-        const AxisRange ry(cy, ny, P.py, md), rz(cz, nz, P.pz, DIM == 3 ? md : 0);
-        const int cap = A.cap, capc = A.capc;
-        int total = 0, ctotal = 0, ccf = 0, ccw = 0;
-        const int ntp = (fluid && S.nw > 0) ? 2 : 1;  // wall cells only where walls exist
-        for (int tp = 0; tp < ntp; ++tp) {
-            const int base = S.key_base + (tp ? A.C : 0);
-            int found = 0, cfound = 0;
-            for (int u = 0; u < rz.count; ++u) {
-                // bounds of every run of this plane, loaded before any is used
-                constexpr int kMaxRows = 7;
-                int rb[kMaxRows][2], re[kMaxRows][2];
-#pragma unroll
-                for (int v = 0; v < kMaxRows; ++v) {
-                    const int row = base + (rz.at(u) * ny + ry.at(v < ry.count ? v : 0)) * nx;
-#pragma unroll
-                    for (int run = 0; run < 2; ++run) {
-                        const int xa = run ? xa1 : xa0, xb = run ? xb1 : xb0;
-                        const bool use = v < ry.count && xb >= xa;
-                        rb[v][run] = use ? (int)cstart[row + xa] : 0;
-                        re[v][run] = use ? (int)cstart[row + xb + 1] : 0;
-                    }
-                }
-#pragma unroll
-                for (int v = 0; v < kMaxRows; ++v)
-#pragma unroll
-                    for (int run = 0; run < 2; ++run) {
-                        const int jb = rb[v][run], je = re[v][run];
-                        for (int j0 = jb; j0 < je; j0 += G * kBatch) {  // uniform in the group
-                            Q q[kBatch];
-#pragma unroll
-                            for (int m = 0; m < kBatch; ++m) {
-                                const int j = j0 + m * G + grp.sub;
-                                q[m] = xr[j < je ? j : jb];
-                            }
-#pragma unroll
-                            for (int m = 0; m < kBatch; ++m) {
-                                const int j = j0 + m * G + grp.sub;
-                                const double r2 = P.r2(q[m]);
-                                const bool ok = j < je && j != i;
-                                const bool in_c = ok && r2 < cr2, in_x = ok && r2 < P.kh2;
-                                const unsigned bc = grp.bits(in_c), bx = grp.bits(in_x);
-                                if (in_c) {
-                                    const int qq = ctotal + grp.before(bc);
-                                    if (qq < capc) cand[(size_t)qq * N + i] = j;
-                                }
-                                if (in_x) {
-                                    const int qq = total + grp.before(bx);
-                                    if (qq < cap) nbr[(size_t)qq * N + i] = j;
-                                }
-                                ctotal += __popc(bc);
-                                cfound += __popc(bc);
-                                total += __popc(bx);
-                                found += __popc(bx);
-                            }
-                        }
-                    }
-            }
-            if (tp) { cw = found; ccw = cfound; }
-            else { cf = found; ccf = cfound; }
-        }
-        if (total > cap || ctotal > capc) {
-            if (grp.sub == 0) {
-                atomicOr(&A.flags[F_NBR_OVERFLOW], 1);
-                atomicMax(&A.flags[F_NBR_NEEDED], total > ctotal ? total : ctotal);
-            }
-            cf = cf < cap ? cf : cap;
-            cw = cap - cf < cw ? cap - cf : cw;
-            ccf = ccf < capc ? ccf : capc;
-            ccw = capc - ccf < ccw ? capc - ccf : ccw;
-        }
-        if (grp.sub == 0) {
-            A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
-            A.ccnt[i] = (uint32_t)ccf | ((uint32_t)ccw << 16);
-        }
+        cf = cf < cap ? cf : cap;
+        cw = cap - cf < cw ? cap - cf : cw;
+        ccf = ccf < capc ? ccf : capc;
+        ccw = capc - ccf < ccw ? capc - ccf : ccw;
+    }
+    if (grp.sub == 0) {
+        A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
+        A.ccnt[i] = (uint32_t)ccf | ((uint32_t)ccw << 16);
     }
 }
 

@@ -35,7 +35,7 @@ constexpr int kSegTiles = 256;       // tiles per residual segment (one finalize
 enum PassMode { MODE_PRE = 0, MODE_PSEUDO = 1 };
 
 // Device flag words
-enum Flag { F_NBR_OVERFLOW = 0, F_NBR_NEEDED = 1, F_CELL_OVERFLOW = 2, F_COUNT = 4 };
+enum Flag { F_NBR_OVERFLOW = 0, F_NBR_NEEDED = 1, F_CELL_OVERFLOW = 2, F_OUTSIDE = 3, F_COUNT = 4 };
 
 // Per-sim constants (device). Everything the kernels need, precomputed on the
 // host in float64; FP32 kernels convert once per thread.
@@ -185,6 +185,9 @@ struct Ctx {
     int *m_flags_d = nullptr;
     MirrorRep *m_reps_d = nullptr;
     unsigned long long *m_pairs_d = nullptr;
+    int *seq_host = nullptr;              // per sim: sequence number of the last finalize
+    int *m_seq_d = nullptr;
+    int seq = 0;                          // last finalize launched
 
     // timing
     bool timing = false;

@@ -514,9 +514,24 @@ struct FinArgs {
     int *h_flags;
     MirrorRep *h_reps;
     unsigned long long *h_pairs;
+    int *h_seq;      // per sim: `seq` once its report of this launch is visible
+    int seq;
 };
 
 constexpr int kFinThreads = kSegTiles;
+
+// Build flags move to mapped memory with sim 0's report (same thread, before
+// its sequence word).
+__device__ inline void move_build_flags(const FinArgs &A)
+{
+    for (int k = 0; k < F_COUNT; ++k) {
+        const int f = A.flags[k];
+        if (f) {
+            A.h_flags[k] = f;
+            A.flags[k] = 0;
+        }
+    }
+}
 
 // Fixed-order workgroup reduction of {sum, sum, max, max, max, sum}; result in
 // thread 0.
@@ -554,18 +569,14 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
     const int g = blockIdx.x;
     const int4 sg = A.segs[g];
     const int s = sg.x;
-    if (g == 0 && threadIdx.x < F_COUNT) {
-        const int f = A.flags[threadIdx.x];
-        if (f) {
-            A.h_flags[threadIdx.x] = f;
-            A.flags[threadIdx.x] = 0;
-        }
-    }
     SimIter &It = A.iters[s];
     if (It.done) {
         if (sg.w == 0 && threadIdx.x == 0) {
+            if (s == 0) move_build_flags(A);
             A.done_out[s] = 1;
             A.h_flags[F_COUNT + s] = 1;
+            __threadfence_system();
+            A.h_seq[s] = A.seq;
         }
         return;
     }
@@ -661,6 +672,9 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
     r.disp = It.disp;
     h_reps[s] = r;
     h_pairs[s] = (unsigned long long)It.pairs;
+    if (s == 0) move_build_flags(A);
+    __threadfence_system();
+    A.h_seq[s] = A.seq;
 }
 
 // Copy the host-visible control words (build flags, stop flags, per-sim reports
@@ -766,6 +780,7 @@ template <typename T>
 struct StateArgs {
     int N, Nf, Nw, in_loop, p_half;
     const SimDev *sims;
+    int *flags;
     const int *init_slot, *init_sim;
     int *orig, *simid;
     double *x, *xn;
@@ -784,6 +799,14 @@ __global__ void k_set_state(StateArgs<T> A)
     A.orig[i] = c;
     A.simid[i] = A.init_sim[c];
     const bool lp = A.in_loop != 0;
+    const SimDev &S = A.sims[A.init_sim[c]];
+    bool outside = false;  // positions on periodic axes must lie in [lo, hi)
+    for (int d = 0; d < S.dim; ++d) {
+        if (!S.periodic[d]) continue;
+        const double a = A.cx[3 * c + d], b = lp ? A.cxi[3 * c + d] : a;
+        outside = outside || !(a >= S.lo[d] && a < S.hi[d]) || !(b >= S.lo[d] && b < S.hi[d]);
+    }
+    if (outside) atomicOr(&A.flags[F_OUTSIDE], 1);
     for (int d = 0; d < 3; ++d) {
         A.x[d * N + i] = lp ? A.cxi[3 * c + d] : A.cx[3 * c + d];
         A.xn[d * N + i] = A.cx[3 * c + d];
@@ -970,6 +993,8 @@ void launch_finalize(Ctx &c)
     a.segs = c.segs; a.seg_p = c.seg_p; a.seg_p2 = c.seg_p2; a.tickets = c.tickets;
     a.done_out = c.done_dev; a.flags = c.flags; a.n_sims = c.n_sims;
     a.h_flags = c.m_flags_d; a.h_reps = c.m_reps_d; a.h_pairs = c.m_pairs_d;
+    a.h_seq = c.m_seq_d;
+    a.seq = ++c.seq;
     hipLaunchKernelGGL(k_finalize, dim3(c.n_segs), dim3(kFinThreads), 0, c.stream, a);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
@@ -1025,6 +1050,7 @@ static StateArgs<T> state_args(Ctx &c, const dtsph_state_view &s, bool in_loop)
     a.N = c.N; a.Nf = c.Nf; a.Nw = c.Nw; a.in_loop = in_loop ? 1 : 0;
     a.p_half = in_loop && c.p_half ? 1 : 0;
     a.sims = c.sims;
+    a.flags = c.flags;
     a.init_slot = c.init_slot; a.init_sim = c.init_slot + c.N;
     a.orig = c.orig[b]; a.simid = c.simid[b];
     a.x = c.x[c.xb]; a.xn = c.xn[b];

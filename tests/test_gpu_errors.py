@@ -145,3 +145,17 @@ def test_autotune_keeps_state_and_results():
     ref.close()
     nf = prob.n_fluid
     assert np.linalg.norm(tuned["v"][:nf] - plain["v"][:nf]) <= 1e-5 * np.linalg.norm(plain["v"][:nf])
+
+
+def test_periodic_position_outside_box_is_rejected():
+    banner("periodic position outside [lo, hi)")
+    prob = I.tgv2d(16, seed=1)
+    prob.x[3, 0] = prob.params["hi"][0]  # == hi lies outside [lo, hi)
+    with pytest.raises(D.DtsphError) as e:
+        D.Sim(prob, precision=D.FP32)
+    assert e.value.status == D.EINVAL
+    prob.x[3, 0] = prob.params["lo"][0]  # == lo is inside
+    sim = D.Sim(prob, precision=D.FP32)
+    st, _ = sim.step(1)
+    sim.close()
+    assert st >= 0
