@@ -164,7 +164,8 @@ typedef struct dtsph_iter_report {
 
 /* ---- timing of the pair pass (host memory; dtsph_set_option TIMING) ----- */
 typedef struct dtsph_timing {
-    int64_t pass_launches;  /* pseudo-iteration pair-pass launches timed     */
+    int64_t pass_launches;  /* pseudo-iteration pair-pass launches timed (every
+                               n-th, see DTSPH_OPT_TIMING)                   */
     double pass_ms;         /* summed duration (HIP events on the ctx stream) */
     int64_t pass_pairs;     /* neighbour pairs those launches evaluated       */
     int64_t pass_particles; /* fluid particles those launches updated         */
@@ -273,7 +274,8 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int64_t *offsets, int32_t *nbrs, int64_t
 int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int64_t *cell_start);
 
 /* Options (value semantics per option). Errors: EINVAL.                    */
-#define DTSPH_OPT_TIMING 1     /* 1: time pair passes with HIP events; 0: off */
+#define DTSPH_OPT_TIMING 1     /* n >= 1: time every n-th pair-pass, wall-pass
+                                  and build launch with HIP events; 0: off  */
 #define DTSPH_OPT_RESET_TIMING 2
 #define DTSPH_OPT_CHUNK 3      /* iterations launched between stop checks (>=1) */
 #define DTSPH_OPT_BLOCK 4      /* pair-pass workgroup size: 64, 128 or 256    */
@@ -286,6 +288,8 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
 #define DTSPH_OPT_CELL_DIV 8   /* cell side >= (kappa h + skin) / value, value
                                   in {1, 2, 3} (default 2); the search visits
                                   +-value cells per axis                      */
+#define DTSPH_OPT_NBR_LANES 9  /* lanes per particle of the neighbour-list
+                                  build: 1, 2, 4, 8 (0: automatic)           */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the pair pass's launch shape. Between steps only (EINVAL in

@@ -335,10 +335,11 @@ void resolve_timers(Ctx &c)
 {
     for (auto &pr : c.ev_pending) {
         float ms = 0.f;
-        DTSPH_HIP_CHECK(hipEventSynchronize(c.ev_pool[pr.first + 1]));
-        DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, c.ev_pool[pr.first], c.ev_pool[pr.first + 1]));
-        if (pr.second == 0) { c.tstats.pass_launches++; c.tstats.pass_ms += ms; }
-        else if (pr.second == 1) { c.tstats.wall_launches++; c.tstats.wall_ms += ms; }
+        DTSPH_HIP_CHECK(hipEventSynchronize(c.ev_pool[pr[0] + 1]));
+        DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, c.ev_pool[pr[0]], c.ev_pool[pr[0] + 1]));
+        // pair passes are booked at the end of their loop, with their pairs
+        if (pr[1] == 0) c.pass_times.emplace_back(pr[2], (double)ms);
+        else if (pr[1] == 1) { c.tstats.wall_launches++; c.tstats.wall_ms += ms; }
         else { c.tstats.build_launches++; c.tstats.build_ms += ms; }
     }
     c.ev_pending.clear();
@@ -467,6 +468,7 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
     ensure_cells<T>(c);
     launch_loop_begin<T>(c, fixed);
     set_active_ranges(c, true);
+    c.pass_times.clear();
     int max_it = fixed;
     if (fixed == 0)
         for (auto &d : c.desc) max_it = std::max(max_it, (int)d.max_iter);
@@ -476,9 +478,10 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
     for (;;) {
         const int n = std::min(chunk, max_it - launched);
         for (int k = 0; k < n; ++k) {
+            c.pass_index = launched + k;
             launch_wall<T>(c, MODE_PSEUDO);
             launch_pass<T>(c, MODE_PSEUDO);
-            launch_finalize(c);
+            launch_finalize(c, k == n - 1);  // the chunk's last one publishes the reports
         }
         launched += n;
         wait_reports(c);  // k_finalize wrote the mapped reports
@@ -500,8 +503,6 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
         cand = cand && c.sims_h[s].skin > 0 && it.disp < 0.4 * c.sims_h[s].skin;
         const int64_t pairs = (int64_t)c.pairs_host[s];
         most = std::max(most, it.iters);
-        c.tstats.pass_pairs += pairs * it.iters;
-        c.tstats.pass_particles += c.nf[s] * it.iters;
         if (rep) {
             rep[s].iters = it.iters;
             rep[s].reason = it.reason;
@@ -515,6 +516,20 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
         else if (it.reason == DTSPH_MAXITER && status == DTSPH_OK) status = DTSPH_WARN_MAXITER;
     }
     c.last_iters = most;
+    for (const auto &pt : c.pass_times) {  // timed launches with the sims that took part
+        int64_t pairs = 0, parts = 0;
+        for (int s = 0; s < c.n_sims; ++s)
+            if (pt.first < c.reps_host[s].iters) {
+                pairs += (int64_t)c.pairs_host[s];
+                parts += c.nf[s];
+            }
+        if (pairs == 0) continue;  // a launch after every sim had stopped
+        c.tstats.pass_launches++;
+        c.tstats.pass_ms += pt.second;
+        c.tstats.pass_pairs += pairs;
+        c.tstats.pass_particles += parts;
+    }
+    c.pass_times.clear();
     c.cand_next = cand;
     if (status == DTSPH_ENONFINITE) c.err = "non-finite residual in the pseudo-time loop";
     return status;
@@ -556,9 +571,10 @@ template <typename F> auto by_precision(Ctx &c, F &&f)
 
 namespace dtsph {
 
-int timer_begin(Ctx &c)
+int timer_begin(Ctx &c, int kind)
 {
     if (!c.timing) return -1;
+    if (c.timer_count[kind]++ % c.timing_every != 0) return -1;
     size_t k = c.ev_used;
     c.ev_used += 2;
     DTSPH_HIP_CHECK(hipEventRecord(pool_event(c, k), c.stream));
@@ -566,11 +582,27 @@ int timer_begin(Ctx &c)
     return (int)k;
 }
 
+int timer_slot(Ctx &c, int kind)
+{
+    if (!c.timing) return -1;
+    if (c.timer_count[kind]++ % c.timing_every != 0) return -1;
+    size_t k = c.ev_used;
+    c.ev_used += 2;
+    pool_event(c, k + 1);
+    return (int)k;
+}
+
+void timer_book(Ctx &c, int slot, int kind)
+{
+    if (slot < 0) return;
+    c.ev_pending.push_back({slot, kind, kind == 0 ? c.pass_index : -1});
+}
+
 void timer_end(Ctx &c, int slot, int kind)
 {
     if (slot < 0) return;
     DTSPH_HIP_CHECK(hipEventRecord(c.ev_pool[slot + 1], c.stream));
-    c.ev_pending.emplace_back(slot, kind);
+    c.ev_pending.push_back({slot, kind, kind == 0 ? c.pass_index : -1});
 }
 
 }  // namespace dtsph
@@ -925,7 +957,10 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
     return guarded(ctx, [&](Ctx &c) {
         switch (option) {
         case DTSPH_OPT_TIMING:
+            if (value < 0) throw ApiError(DTSPH_EINVAL, "timing sample interval must be >= 0");
             c.timing = value != 0;
+            c.timing_every = value > 0 ? (int)std::min<int64_t>(value, 1 << 20) : 1;
+            c.timer_count[0] = c.timer_count[1] = c.timer_count[2] = 0;
             break;
         case DTSPH_OPT_RESET_TIMING:
             DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
@@ -966,6 +1001,11 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
             DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
             c.cells_valid = false;
             c.cand_ok = c.cand_next = false;
+            break;
+        case DTSPH_OPT_NBR_LANES:
+            if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+                throw ApiError(DTSPH_EINVAL, "neighbour-build lanes must be 0, 1, 2, 4 or 8");
+            c.g_nbr = (int)value;
             break;
         case DTSPH_OPT_LANES:
             if (value != 1 && value != 2 && value != 4 && value != 8)

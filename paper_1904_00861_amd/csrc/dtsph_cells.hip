@@ -386,15 +386,28 @@ __device__ __forceinline__ void scan_run(const typename XR<DIM>::type *__restric
                                          const Group<G> &grp, ListCursor &cur)
 {
     using Q = typename XR<DIM>::type;
-    for (int j0 = jb; j0 < je; j0 += G * kBatch) {  // uniform in the group
-        Q q[kBatch];
+    constexpr int kB = DIM == 2 ? kBatch : kBatch / 2;  // 3D records are twice as wide
+    if (jb >= je) return;
+    // software pipeline: the next batch's positions are in flight while the
+    // current batch is tested
+    Q q[kB];
 #pragma unroll
-        for (int m = 0; m < kBatch; ++m) {
-            const int j = j0 + m * G + grp.sub;
-            q[m] = xr[j < je ? j : jb];
+    for (int m = 0; m < kB; ++m) {
+        const int j = jb + m * G + grp.sub;
+        q[m] = xr[j < je ? j : jb];
+    }
+    for (int j0 = jb; j0 < je; j0 += G * kB) {  // uniform in the group
+        Q qn[kB];
+        const int jn = j0 + G * kB;
+        if (jn < je) {
+#pragma unroll
+            for (int m = 0; m < kB; ++m) {
+                const int j = jn + m * G + grp.sub;
+                qn[m] = xr[j < je ? j : jb];
+            }
         }
 #pragma unroll
-        for (int m = 0; m < kBatch; ++m) {
+        for (int m = 0; m < kB; ++m) {
             const int j = j0 + m * G + grp.sub;
             const double r2 = GENERAL ? P.r2(q[m]) : P.r2s(q[m], sx, sy, sz);
             const bool ok = j < je && j != i;
@@ -417,6 +430,10 @@ __device__ __forceinline__ void scan_run(const typename XR<DIM>::type *__restric
                 cur.ctotal += __popc(bc);
                 cur.total += __popc(bx);
             }
+        }
+        if (jn < je) {
+#pragma unroll
+            for (int m = 0; m < kB; ++m) q[m] = qn[m];
         }
     }
 }
@@ -620,7 +637,7 @@ void build_cells(Ctx &c)
     hipStream_t st = c.stream;
     const int N = c.N, nkeys = 2 * c.C;
     const int b = c.buf, o = c.buf ^ 1;
-    int t0 = timer_begin(c);
+    int t0 = timer_begin(c, 2);
     hipLaunchKernelGGL(k_keys, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.Nf, c.C, c.x[c.xb], c.simid[b],
                        c.sims, c.key, c.rank, c.count);
     const int nblk = ceil_div(nkeys, kScanTile);
@@ -660,7 +677,7 @@ void build_cells(Ctx &c)
 template <typename T>
 void filter_lists(Ctx &c)
 {
-    int t0 = timer_begin(c);
+    int t0 = timer_begin(c, 2);
     launch_nbr_lists<T>(c, true);
     timer_end(c, t0, 2);
 }

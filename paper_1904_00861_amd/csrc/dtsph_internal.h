@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
 #include <string>
 #include <vector>
 
@@ -191,9 +192,14 @@ struct Ctx {
 
     // timing
     bool timing = false;
+    int timing_every = 1;                 // time every n-th launch of each kind
+    long long timer_count[3] = {0, 0, 0};
+    int pass_index = 0;                   // launch index of the next pair pass in the loop
+    hipEvent_t ext_start = nullptr, ext_stop = nullptr;  // events of a timed pass launch
+    std::vector<std::pair<int, double>> pass_times;  // this loop's timed pair passes (index, ms)
     dtsph_timing tstats{};
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, int>> ev_pending;  // (start event, kind)
+    std::vector<std::array<int, 3>> ev_pending;  // (start event, kind, pass index)
     size_t ev_used = 0;
 
     std::string err;
@@ -206,15 +212,18 @@ template <typename T> void launch_nbr_lists(Ctx &c, bool filter);
 template <typename T> void launch_pre_records(Ctx &c);
 template <typename T> void launch_wall(Ctx &c, int mode, bool cand_lists = false);
 template <typename T> void launch_pass(Ctx &c, int mode, bool cand_lists = false);
-void launch_finalize(Ctx &c);
+void launch_finalize(Ctx &c, bool publish);
 void launch_publish(Ctx &c);
 template <typename T> void launch_loop_begin(Ctx &c, int fixed_iters);
 template <typename T> void launch_correct(Ctx &c);
 template <typename T> void launch_set_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
 template <typename T> void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
 
-// timing helpers (dtsph_api.hip)
-int timer_begin(Ctx &c);
+// timing helpers (dtsph_api.hip); timer_slot reserves the two events of a
+// launch timed by the runtime itself (hipExtLaunchKernel), timer_book queues them
+int timer_begin(Ctx &c, int kind);
+int timer_slot(Ctx &c, int kind);
+void timer_book(Ctx &c, int slot, int kind);
 void timer_end(Ctx &c, int slot, int kind);
 
 #define DTSPH_HIP_CHECK(expr)                                                              \

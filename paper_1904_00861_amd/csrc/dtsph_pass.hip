@@ -25,6 +25,8 @@
 // sim's residual is a fixed-order sum of its own partials and a batch member
 // computes bit-for-bit what it computes alone). Consecutive tiles are mapped to
 // the same XCD so that neighbouring tiles share that XCD's L2.
+#include <hip/hip_ext.h>
+
 #include "dtsph_internal.h"
 
 namespace dtsph {
@@ -516,6 +518,7 @@ struct FinArgs {
     unsigned long long *h_pairs;
     int *h_seq;      // per sim: `seq` once its report of this launch is visible
     int seq;
+    int publish;     // 0: device state only (not the last iteration of a chunk)
 };
 
 constexpr int kFinThreads = kSegTiles;
@@ -563,6 +566,26 @@ __device__ inline void fin_block_reduce(double v[6])
     __syncthreads();
 }
 
+// Sim s's report and stop flag (and, with sim 0, the build flags) into mapped
+// memory, then its sequence word behind a system-scope fence.
+__device__ inline void publish_report(const FinArgs &A, int s, const SimIter &It)
+{
+    A.h_flags[F_COUNT + s] = It.done;
+    MirrorRep r;
+    r.iters = It.iters;
+    r.reason = It.reason;
+    r.rp_mean = It.rp_mean;
+    r.rv_mean = It.rv_mean;
+    r.rp_max = It.rp_max;
+    r.rv_max = It.rv_max;
+    r.disp = It.disp;
+    A.h_reps[s] = r;
+    A.h_pairs[s] = (unsigned long long)It.pairs;
+    if (s == 0) move_build_flags(A);
+    __threadfence_system();
+    A.h_seq[s] = A.seq;
+}
+
 __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
 {
     __shared__ int last;
@@ -572,11 +595,8 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
     SimIter &It = A.iters[s];
     if (It.done) {
         if (sg.w == 0 && threadIdx.x == 0) {
-            if (s == 0) move_build_flags(A);
             A.done_out[s] = 1;
-            A.h_flags[F_COUNT + s] = 1;
-            __threadfence_system();
-            A.h_seq[s] = A.seq;
+            if (A.publish) publish_report(A, s, It);
         }
         return;
     }
@@ -613,9 +633,7 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
     if (threadIdx.x != 0) return;
     A.tickets[s] = 0u;
     const double sd = red[0], sv = red[1], md = red[2], mv = red[3], mw = red[4], np = red[5];
-    int *done_out = A.done_out, *h_flags = A.h_flags;
-    MirrorRep *h_reps = A.h_reps;
-    unsigned long long *h_pairs = A.h_pairs;
+    int *done_out = A.done_out;
     It.disp = 0.5 * S.dt * sqrt(mw);
     It.pairs = (long long)np;
     const double pscale = S.dt / (S.rho0 * S.c * S.c);
@@ -661,20 +679,7 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
         It.reason = reason;
     }
     done_out[s] = It.done;
-    h_flags[F_COUNT + s] = It.done;
-    MirrorRep r;
-    r.iters = It.iters;
-    r.reason = It.reason;
-    r.rp_mean = It.rp_mean;
-    r.rv_mean = It.rv_mean;
-    r.rp_max = It.rp_max;
-    r.rv_max = It.rv_max;
-    r.disp = It.disp;
-    h_reps[s] = r;
-    h_pairs[s] = (unsigned long long)It.pairs;
-    if (s == 0) move_build_flags(A);
-    __threadfence_system();
-    A.h_seq[s] = A.seq;
+    if (A.publish) publish_report(A, s, It);
 }
 
 // Copy the host-visible control words (build flags, stop flags, per-sim reports
@@ -897,11 +902,16 @@ template <typename T> PassArgs<T> pass_args(Ctx &c, int mode, bool cand_lists)
     return a;
 }
 
+// A timed pair pass goes through hipExtLaunchKernelGGL, whose events take the
+// kernel's own start and end timestamps (no queue gaps in the interval).
 template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int LPP>
 void dispatch_mode(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
 {
     if (mode == MODE_PRE)
         hipLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PRE, LPP>), grid, dim3(c.block), 0, c.stream, a);
+    else if (c.ext_start)
+        hipExtLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP>), grid, dim3(c.block), 0,
+                              c.stream, c.ext_start, c.ext_stop, 0, a);
     else
         hipLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP>), grid, dim3(c.block), 0, c.stream,
                            a);
@@ -947,11 +957,16 @@ void launch_pass(Ctx &c, int mode, bool cand_lists)
     PassArgs<T> a = pass_args<T>(c, mode, cand_lists);
     if (a.n_tiles == 0) return;
     const int grid = c.xcd_remap ? 8 * ((a.n_tiles + 7) / 8) : a.n_tiles;
-    int t0 = mode == MODE_PSEUDO ? timer_begin(c) : -1;
+    const int t0 = mode == MODE_PSEUDO ? timer_slot(c, 0) : -1;
+    if (t0 >= 0) {
+        c.ext_start = c.ev_pool[t0];
+        c.ext_stop = c.ev_pool[t0 + 1];
+    }
     if (c.max_dim == 2) dispatch_walls<T, 2>(c, mode, a, dim3(grid));
     else dispatch_walls<T, 3>(c, mode, a, dim3(grid));
+    c.ext_start = c.ext_stop = nullptr;
     DTSPH_HIP_CHECK(hipGetLastError());
-    if (mode == MODE_PSEUDO) timer_end(c, t0, 0);
+    timer_book(c, t0, 0);
 }
 
 template <typename T>
@@ -971,7 +986,7 @@ void launch_wall(Ctx &c, int mode, bool cand_lists)
     a.vwall = (const T *)c.vw[b];
     a.pwall = (T *)c.pw[b];
     a.x = c.x[c.xb]; a.x_alt = c.x[c.xb ^ 1];
-    int t0 = mode == MODE_PSEUDO ? timer_begin(c) : -1;
+    int t0 = mode == MODE_PSEUDO ? timer_begin(c, 1) : -1;
     if (c.max_dim == 2) hipLaunchKernelGGL((k_wall<T, 2>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
     else hipLaunchKernelGGL((k_wall<T, 3>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
     DTSPH_HIP_CHECK(hipGetLastError());
@@ -986,7 +1001,7 @@ void launch_publish(Ctx &c)
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
-void launch_finalize(Ctx &c)
+void launch_finalize(Ctx &c, bool publish)
 {
     FinArgs a;
     a.sims = c.sims; a.iters = c.iters; a.partials = c.partials; a.partials2 = c.partials2;
@@ -994,7 +1009,8 @@ void launch_finalize(Ctx &c)
     a.done_out = c.done_dev; a.flags = c.flags; a.n_sims = c.n_sims;
     a.h_flags = c.m_flags_d; a.h_reps = c.m_reps_d; a.h_pairs = c.m_pairs_d;
     a.h_seq = c.m_seq_d;
-    a.seq = ++c.seq;
+    a.publish = publish ? 1 : 0;
+    a.seq = publish ? ++c.seq : c.seq;
     hipLaunchKernelGGL(k_finalize, dim3(c.n_segs), dim3(kFinThreads), 0, c.stream, a);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
