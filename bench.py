@@ -52,13 +52,24 @@ def pair_evals(reports):
     return sum(r["pairs"] * r["iters"] for step in reports for r in step)
 
 
-def run_leg(problems, precision, steps, warmup, timing_every):
+def run_leg(problems, precision, steps, warmup, timing_every, shape=None):
     import torch
     from paper_1904_00861_amd import dtsph as D
 
     sim = D.Sim(problems, precision=precision)
-    tune = sim.autotune()
-    log(f"autotune: pass lanes {tune['lanes']} block {tune['block']} ({tune['us']:.2f} us); " +
+    if shape:  # fixed launch configuration instead of the autotuner
+        lanes, block, nbr_lanes, cell_div = shape
+        sim.set_option(D.OPT_LANES, lanes)
+        sim.set_option(D.OPT_BLOCK, block)
+        sim.set_option(D.OPT_NBR_LANES, nbr_lanes)
+        sim.set_option(D.OPT_CELL_DIV, cell_div)
+        tune = dict(lanes=lanes, block=block, nbr_lanes=nbr_lanes, cell_div=cell_div, fixed=True)
+        log(f"fixed launch shape: pass lanes {lanes} block {block}, neighbour-build lanes {nbr_lanes}, "
+            f"cell subdivision {cell_div}")
+    else:
+        tune = sim.autotune()
+    if not shape:
+        log(f"autotune: pass lanes {tune['lanes']} block {tune['block']} ({tune['us']:.2f} us); " +
         " ".join(f"{e['lanes']}x{e['block']}:{e['us']:.1f}" for e in tune["entries"]) +
         f"; cell subdivision {tune['cell_div']} (full build {tune['build_us']:.1f} us)"
         f"; neighbour build lanes {tune['nbr_lanes']} ({tune['nbr_us']:.1f} us), "
@@ -78,17 +89,21 @@ def run_leg(problems, precision, steps, warmup, timing_every):
     return dict(seconds=t1 - t0, reports=reps, timing=tm, status=st, info=info, tune=tune)
 
 
-def traffic_from_profile(kernel_src):
+def traffic_from_profile(kernel_src, shape):
     """HBM bytes per pair-pass launch from the committed counter summary, or None
-    if the summary is missing or the pass kernel changed since it was taken."""
+    if the summary is missing, was taken for another launch shape (lanes, block)
+    or the pass kernel changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "k_pass_C1_fp32_traffic.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_hash = re.search(r"source sha256: ([0-9a-f]{64})", txt)
     m_bytes = re.search(r"HBM bytes per launch: ([0-9.eE+]+)", txt)
-    if not m_hash or not m_bytes:
+    m_shape = re.search(r"launch shape: lanes (\d+) block (\d+)", txt)
+    if not m_hash or not m_bytes or not m_shape:
         return None
+    if (int(m_shape.group(1)), int(m_shape.group(2))) != shape:
+        return None  # counters were taken for another variant of the kernel
     digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
     return float(m_bytes.group(1)) if digest == m_hash.group(1) else None
 
@@ -119,6 +134,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and batched legs")
     ap.add_argument("--no-timing", action="store_true", help="no HIP events in the timed region")
+    ap.add_argument("--shape", default=None, metavar="L,B,G,M",
+                    help="fixed launch shape instead of the autotuner: pair-pass lanes per particle, "
+                         "workgroup size, neighbour-build lanes, cell subdivision (for profiling runs)")
     ap.add_argument("--timing-every", type=int, default=4, metavar="N",
                     help="HIP events around every N-th pair-pass launch in the timed region (each "
                          "event record costs host time; sampling keeps it off the step time)")
@@ -158,7 +176,8 @@ def main():
 
     log(f"main leg {args.config} {args.precision}: {n_particles} particles, "
         f"{args.warmup} warmup + {args.steps} timed steps")
-    main_leg = run_leg(problems, prec, args.steps, args.warmup, 0 if args.no_timing else args.timing_every)
+    shape = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
+    main_leg = run_leg(problems, prec, args.steps, args.warmup, 0 if args.no_timing else args.timing_every, shape)
     evals = pair_evals(main_leg["reports"])
     secs = main_leg["seconds"]
     value = evals / secs
@@ -174,7 +193,8 @@ def main():
         achieved = flop / (tm["pass_ms"] * 1e-3) / 1e12
         peak = PEAK_TFLOPS[dtype]
         src = os.path.join(ROOT, "paper_1904_00861_amd", "csrc", "dtsph_pass.hip")
-        tr = traffic_from_profile(src) if (args.config == "C1" and dtype == "f32") else None
+        tr = traffic_from_profile(src, (main_leg["tune"]["lanes"], main_leg["tune"]["block"])) \
+            if (args.config == "C1" and dtype == "f32") else None
         roofline = dict(bound="alu", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                         frac=round(achieved / peak, 4), traffic=tr,
                         kernel="k_pass (pseudo-time pair pass)",
@@ -184,7 +204,10 @@ def main():
                         pairs_per_launch=round(tm["pass_pairs"] / tm["pass_launches"], 1),
                         flop_per_pair=FLOP_PER_PAIR[dim],
                         launch_shape=dict(lanes_per_particle=main_leg["tune"]["lanes"],
-                                          block=main_leg["tune"]["block"]),
+                                          block=main_leg["tune"]["block"],
+                                          nbr_lanes=main_leg["tune"]["nbr_lanes"],
+                                          cell_div=main_leg["tune"]["cell_div"],
+                                          autotuned=not shape),
                         frac_of_packed_peak=round(achieved / PEAK_PACKED_F32, 4) if dtype == "f32" else None)
 
     extras = {}
