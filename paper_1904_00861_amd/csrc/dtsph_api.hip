@@ -465,8 +465,14 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
 {
     if (!c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_pseudo_iterate: not inside a step (call dtsph_predict)");
     if (fixed < 0) throw ApiError(DTSPH_EINVAL, "fixed_iters must be >= 0");
-    ensure_cells<T>(c);
-    launch_loop_begin<T>(c, fixed);
+    if (!c.cells_valid && !c.cand_ok) {
+        // full build at the frozen positions, with the loop set-up in its gather
+        build_cells<T>(c, fixed);
+        c.cells_valid = true;
+    } else {
+        ensure_cells<T>(c);
+        launch_loop_begin<T>(c, fixed);
+    }
     set_active_ranges(c, true);
     c.pass_times.clear();
     int max_it = fixed;

@@ -189,7 +189,18 @@ struct GatherArgs {
     double *pm_out, *pn_out;
     const T *vw_in, *pw_in;
     T *vw_out, *pw_out;
+    // loop set-up fused into the gather (loop >= 0): reset of every sim's loop
+    // state (fixed iterations = loop), stage-1 half step of p unless pending,
+    // and the {V^k, p^{k+1/2}} records of buffer `rec`
+    int loop, add_half, n_sims;
+    const SimDev *sims;
+    SimIter *iters;
+    void *rec;
 };
+
+template <typename T> struct RecT;
+template <> struct RecT<float> { using type = float4; };
+template <> struct RecT<double> { using type = double4; };
 
 // Final slot = cell start + number of the cell's particles with a smaller caller
 // index (ties in caller order, independent of atomic arrival order); every
@@ -198,6 +209,12 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (A.loop >= 0 && m < A.n_sims) {
+        SimIter z{};
+        z.fixed = A.loop;
+        for (int k = 0; k < kHist; ++k) { z.hp[k] = 0.0; z.hv[k] = 0.0; }
+        A.iters[m] = z;
+    }
     if (m >= A.N) return;
     const int N = A.N, Nf = A.Nf, Nw = A.Nw;
     const int s = (int)A.perm[m];
@@ -227,15 +244,30 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
     if (A.dim == 2) ((double2 *)A.xr)[d] = make_double2(A.x_in[s], A.x_in[N + s]);
     else ((double4 *)A.xr)[d] = make_double4(A.x_in[s], A.x_in[N + s], A.x_in[2 * N + s], 0.0);
     if (d < Nf) {
+        T v[3];
         for (int a = 0; a < 3; ++a) {
-            A.vn_out[a * Nf + d] = A.vn_in[a * Nf + s];
+            const T vn = A.vn_in[a * Nf + s], w = A.w_in[a * Nf + s];
+            A.vn_out[a * Nf + d] = vn;
             A.dv_out[a * Nf + d] = A.dv_in[a * Nf + s];
-            A.w_out[a * Nf + d] = A.w_in[a * Nf + s];
+            A.w_out[a * Nf + d] = w;
             A.w0_out[a * Nf + d] = A.w0_in[a * Nf + s];
+            v[a] = vn + w;
         }
-        A.pm_out[d] = A.pm_in[s];
+        const T dp = A.dp_in[s];
+        double p = A.pm_in[s];
+        if (A.loop >= 0 && A.add_half) p += 0.5 * A.sims[A.simid_in[s]].dtau * (double)dp;
+        A.pm_out[d] = p;
         A.pn_out[d] = A.pn_in[s];
-        A.dp_out[d] = A.dp_in[s];
+        A.dp_out[d] = dp;
+        if (A.loop >= 0) {
+            using Q = typename RecT<T>::type;
+            Q r;
+            r.x = v[0];
+            r.y = v[1];
+            if (A.dim == 2) { r.z = (T)p; r.w = T(0); }
+            else { r.z = v[2]; r.w = (T)p; }
+            ((Q *)A.rec)[d] = r;
+        }
     } else {
         const int dw = d - Nf, sw = s - Nf;
         for (int a = 0; a < 3; ++a) A.vw_out[a * Nw + dw] = A.vw_in[a * Nw + sw];
@@ -632,7 +664,7 @@ template <typename T> void launch_grouped(Ctx &c, const NbrArgs<T> &a, bool filt
 }  // namespace
 
 template <typename T>
-void build_cells(Ctx &c)
+void build_cells(Ctx &c, int loop_fixed)
 {
     hipStream_t st = c.stream;
     const int N = c.N, nkeys = 2 * c.C;
@@ -665,6 +697,12 @@ void build_cells(Ctx &c)
     g.pn_in = c.pn[b]; g.pn_out = c.pn[o];
     g.vw_in = (const T *)c.vw[b]; g.vw_out = (T *)c.vw[o];
     g.pw_in = (const T *)c.pw[b]; g.pw_out = (T *)c.pw[o];
+    g.loop = loop_fixed;
+    g.add_half = c.p_half ? 0 : 1;
+    g.n_sims = c.n_sims;
+    g.sims = c.sims;
+    g.iters = c.iters;
+    g.rec = c.vp[c.cur];
     hipLaunchKernelGGL(k_rank_gather<T>, dim3(grid_for(N)), dim3(kThreads), 0, st, g);
     c.buf = o;
     c.xb ^= 1;
@@ -700,7 +738,7 @@ template void filter_lists<float>(Ctx &);
 template void filter_lists<double>(Ctx &);
 template void launch_nbr_lists<float>(Ctx &, bool);
 template void launch_nbr_lists<double>(Ctx &, bool);
-template void build_cells<float>(Ctx &);
-template void build_cells<double>(Ctx &);
+template void build_cells<float>(Ctx &, int);
+template void build_cells<double>(Ctx &, int);
 
 }  // namespace dtsph

@@ -206,7 +206,9 @@ struct Ctx {
 };
 
 // ---- launchers (defined in the .hip files) ---------------------------------
-template <typename T> void build_cells(Ctx &c);        // dtsph_cells.hip
+// build_cells(c, loop_fixed): with loop_fixed >= 0 the gather also performs the
+// set-up of a pseudo-time loop (what launch_loop_begin does) for fixed = loop_fixed
+template <typename T> void build_cells(Ctx &c, int loop_fixed = -1);  // dtsph_cells.hip
 template <typename T> void filter_lists(Ctx &c);
 template <typename T> void launch_nbr_lists(Ctx &c, bool filter);
 template <typename T> void launch_pre_records(Ctx &c);
