@@ -106,7 +106,12 @@ extern "C" {
  *   lo, hi         domain box. Periodic axes: the period [lo, hi); needs
  *                  kappa*h < (hi-lo)/2. Other axes: the cell grid's extent;
  *                  particles outside it are clamped into edge cells.
- *   periodic       per axis 0/1                                            */
+ *   periodic       per axis 0/1
+ *   shift          1: particle shifting with Taylor correction after the
+ *                  corrector (section 3.5, eqs. shift, shift-deltar,
+ *                  shift-correct; free-surface particles are not shifted)
+ *   shift_r, shift_n  shifting coefficient 1 + shift_r (W_ij / W(h))^shift_n;
+ *                  the printed form is shift_r = 1, shift_n = 1 (n in 1..8)  */
 typedef struct dtsph_sim_desc {
     int32_t dim;
     int32_t max_neighbors;
@@ -124,6 +129,8 @@ typedef struct dtsph_sim_desc {
     int32_t edac_rho_literal, reserved0;
     double lo[3], hi[3];
     int32_t periodic[3], reserved1;
+    int32_t shift, shift_n;
+    double shift_r;
 } dtsph_sim_desc;
 
 /* ---- state views (device pointers, caller order, n = all particles) -----
@@ -290,6 +297,12 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
                                   +-value cells per axis                      */
 #define DTSPH_OPT_NBR_LANES 9  /* lanes per particle of the neighbour-list
                                   build: 1, 2, 4, 8 (0: automatic)           */
+#define DTSPH_OPT_GRAPHS 10    /* 1 (default): dtsph_step records the segment
+                                  from the rate pass to the first chunk of
+                                  pseudo-iterations as a HIP graph (one per
+                                  launch configuration, kept by the context)
+                                  and replays it; 0: plain launches. Steps
+                                  with a timed pair-pass launch run plainly.  */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the pair pass's launch shape. Between steps only (EINVAL in

@@ -46,6 +46,8 @@ class Params(C.Structure):
         ("periodic", C.c_int32 * 3),
         ("edac_reg_literal", C.c_int32), ("edac_rho_literal", C.c_int32),
         ("pad2", C.c_int32),
+        ("shift", C.c_int32), ("shift_n", C.c_int32),
+        ("shift_r", C.c_double),
     ]
 
 
@@ -105,6 +107,8 @@ def lib():
         L.or_rows.restype = None
         L.or_rows.argtypes = [P(Params), C.c_int, C.c_int, C.c_int, d, d, d, d, d, d, C.c_int,
                               P(C.c_int32), d, d, d]
+        L.or_shift.restype = None
+        L.or_shift.argtypes = [P(Params), C.c_int, C.c_int, d, d, d, d, P(C.c_int32)]
         L.or_num_threads.restype = C.c_int
         L.or_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -122,7 +126,7 @@ def params(p: dict) -> Params:
         elif name == "periodic":
             getattr(s, name)[:] = [int(t) for t in val]
         elif name in ("dim", "max_iter", "stall_window", "conv_norm", "edac_reg_literal",
-                      "edac_rho_literal"):
+                      "edac_rho_literal", "shift", "shift_n"):
             setattr(s, name, int(val))
         else:
             setattr(s, name, float(val))
@@ -222,7 +226,8 @@ def correct(prm: dict, nf: int, nw: int, x, v, v_prev, p, v_iter, p_iter):
 
 
 def step(prm: dict, nf: int, nw: int, x, v, v_prev, p, n_steps: int = 1, fixed_iters: int = 0):
-    """Advance n_steps real steps (Algorithm 2 without shifting). Returns
+    """Advance n_steps real steps (Algorithm 2; particle shifting after each
+    corrector when prm["shift"] is 1). Returns
     (x, v, v_prev, p, reports, status)."""
     n = nf + nw
     x, v = _f64(x, (n, 3)).copy(), _f64(v, (n, 3)).copy()
@@ -232,6 +237,20 @@ def step(prm: dict, nf: int, nw: int, x, v, v_prev, p, n_steps: int = 1, fixed_i
     st = lib().or_step(C.byref(P), nf, nw, _d(x), _d(v), _d(vp), _d(p), int(n_steps),
                        int(fixed_iters), reps)
     return x, v, vp, p, [reps[s].as_dict() for s in range(n_steps)], st
+
+
+def shift(prm: dict, nf: int, nw: int, x, v, p):
+    """Particle shifting with Taylor correction (section 3.5). Returns new
+    (x, v, p), the shift vectors of the fluid (nf, 3) and the free-surface flags."""
+    n = nf + nw
+    x = _f64(x, (n, 3)).copy()
+    v = _f64(v, (n, 3)).copy()
+    p = _f64(p, (n,)).copy()
+    dr = np.zeros((max(nf, 1), 3))
+    fs = np.zeros(max(nf, 1), dtype=np.int32)
+    lib().or_shift(C.byref(params(prm)), nf, nw, _d(x), _d(v), _d(p), _d(dr),
+                   fs.ctypes.data_as(C.POINTER(C.c_int32)))
+    return x, v, p, dr[:nf], fs[:nf].astype(bool)
 
 
 def rows(prm: dict, nf: int, nw: int, mode: int, rows_idx, x, vk, pk, dk=None, vn=None,

@@ -35,6 +35,15 @@
  *            gives p_w to the pressure terms, its ghost velocity to the viscous
  *            and artificial-viscosity terms and its prescribed velocity to
  *            the divergence term.
+ *  R-shift   particle shifting (section 3.5) after the corrector, at
+ *            (r^{n+1}, V^{n+1}, p^{n+1}): the printed coefficient
+ *            1 + W_ij / W(dx) with dx = h (generalised to 1 + R (W_ij/W(dx))^n,
+ *            R = n = 1 as printed); sums over fluid and wall neighbours with
+ *            V_j = m / rho0; the free-surface test uses the SPH estimate
+ *            div r_i = -sum_j V_j r_ij . gradW_ij; the Taylor correction uses
+ *            (grad phi)_i = sum_j V_j (phi_j - phi_i) gradW_ij over fluid
+ *            neighbours and corrects V^{n+1} and p^{n+1} (the stored V^n of the
+ *            time history is left as it is); all sums see the unshifted state.
  */
 #include <math.h>
 #include <stdint.h>
@@ -63,6 +72,8 @@ typedef struct {
     int32_t periodic[3];
     int32_t edac_reg_literal, edac_rho_literal;
     int32_t pad2;
+    int32_t shift, shift_n; /* particle shifting on/off and the exponent n (R-shift) */
+    double shift_r;         /* R of the shifting coefficient (R-shift)              */
 } or_params;
 
 typedef struct {
@@ -618,7 +629,74 @@ void or_correct(const or_params *P, int nf, int nw, double *x, double *v, double
     for (int i = 0; i < n; ++i) p[i] = pk[i];
 }
 
-/* ---- one or more real steps (Algorithm 2 without shifting) ------------------- */
+/* ---- particle shifting (section 3.5: eq. shift, eq. shift-deltar, eq.
+ * shift-correct, free-surface test; R-shift) ---------------------------------
+ * For every fluid particle i, with neighbours at the current positions:
+ *   div_r = -sum_j V_j r_ij . gradW_ij                   (fluid and walls)
+ *   dr    = -(h^2/2) sum_j V_j (1 + R (W_ij/W(h))^n) gradW_ij   (fluid and walls)
+ *   dr    = 0 if div_r < dim - 1/2 (free surface)
+ *   grad p, grad V = sum_j V_j (phi_j - phi_i) gradW_ij  (fluid)
+ * then r_i += dr (wrapped), p_i += grad p . dr, V_i += grad V . dr. Outputs
+ * dr and the free-surface flag per fluid particle when the pointers are given. */
+void or_shift(const or_params *P, int nf, int nw, double *x, double *v, double *p, double *dr_out,
+              int32_t *fs_out)
+{
+    int n = nf + nw;
+    nlist L;
+    build_nlist(P, nf, nw, x, 1, &L);
+    const double vol = P->mass / P->rho0;
+    const double w0 = or_w(P->dim, P->h, P->h);
+    double *dr = (double *)calloc(3 * (size_t)nf + 3, sizeof(double));
+    double *dp = (double *)calloc((size_t)nf + 1, sizeof(double));
+    double *dv = (double *)calloc(3 * (size_t)nf + 3, sizeof(double));
+    int32_t *fs = (int32_t *)calloc((size_t)nf + 1, sizeof(int32_t));
+    (void)n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int i = 0; i < nf; ++i) {
+        double divr = 0.0, s[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, gv[3][3] = {{0}};
+        for (int64_t e = L.off[i]; e < L.off[i + 1]; ++e) {
+            const int j = L.idx[e];
+            double d[3];
+            separation(P, x + 3 * i, x + 3 * j, d);
+            const double r = sqrt(norm2(d));
+            if (r <= 0.0) continue;
+            const double f = or_dwdr(P->dim, P->h, r) / r; /* gradW = f d */
+            divr -= vol * f * ((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+            double ratio = or_w(P->dim, P->h, r) / w0, pw = 1.0;
+            for (int k = 0; k < P->shift_n; ++k) pw *= ratio;
+            const double c = vol * (1.0 + P->shift_r * pw) * f;
+            for (int a = 0; a < 3; ++a) s[a] += c * d[a];
+            if (j < nf) {
+                const double cp = vol * (p[j] - p[i]) * f;
+                for (int a = 0; a < 3; ++a) gp[a] += cp * d[a];
+                for (int b = 0; b < 3; ++b) {
+                    const double cv = vol * (v[3 * j + b] - v[3 * i + b]) * f;
+                    for (int a = 0; a < 3; ++a) gv[b][a] += cv * d[a];
+                }
+            }
+        }
+        fs[i] = divr < P->dim - 0.5;
+        double del[3] = {0, 0, 0};
+        if (!fs[i])
+            for (int a = 0; a < P->dim; ++a) del[a] = -0.5 * P->h * P->h * s[a];
+        for (int a = 0; a < 3; ++a) dr[3 * i + a] = del[a];
+        dp[i] = (gp[0] * del[0] + gp[1] * del[1]) + gp[2] * del[2];
+        for (int b = 0; b < 3; ++b) dv[3 * i + b] = (gv[b][0] * del[0] + gv[b][1] * del[1]) + gv[b][2] * del[2];
+    }
+    for (int i = 0; i < nf; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            x[3 * i + a] = wrap(P, a, x[3 * i + a] + dr[3 * i + a]);
+            v[3 * i + a] += dv[3 * i + a];
+            if (dr_out) dr_out[3 * i + a] = dr[3 * i + a];
+        }
+        p[i] += dp[i];
+        if (fs_out) fs_out[i] = fs[i];
+    }
+    free(dr); free(dp); free(dv); free(fs);
+    nlist_free(&L);
+}
+
+/* ---- one or more real steps (Algorithm 2; shifting when P->shift) ------------- */
 int or_step(const or_params *P, int nf, int nw, double *x, double *v, double *v_prev,
             double *p, int n_steps, int fixed_iters, or_report *reps)
 {
@@ -633,6 +711,7 @@ int or_step(const or_params *P, int nf, int nw, double *x, double *v, double *v_
         if (st < 0) { status = st; break; }
         if (st > 0) status = st;
         or_correct(P, nf, nw, x, v, v_prev, p, v0, p0);
+        if (P->shift) or_shift(P, nf, nw, x, v, p, NULL, NULL);
     }
     free(x0); free(v0); free(p0); free(d0);
     return status;

@@ -91,8 +91,15 @@ size_t workspace_need(const Ctx &c)
 // Move every device array to `base` (a caller workspace of workspace_need(c)
 // bytes) or, with base == nullptr, to fresh library allocations; contents are
 // copied on the context's stream, old library allocations freed.
+void clear_graphs(Ctx &c)
+{
+    for (auto &kv : c.graph_cache) (void)hipGraphExecDestroy(kv.second);
+    c.graph_cache.clear();
+}
+
 void relocate(Ctx &c, char *base, size_t size)
 {
+    clear_graphs(c);  // they hold the old addresses
     std::vector<void *> fresh(c.arrays.size(), nullptr);
     std::vector<void *> fresh_owned;
     try {
@@ -125,6 +132,9 @@ void relocate(Ctx &c, char *base, size_t size)
 
 void free_all(Ctx &c)
 {
+    clear_graphs(c);
+    if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
+    c.cap_stream = nullptr;
     for (void *p : c.owned) (void)hipFree(p);
     c.owned.clear();
     c.arrays.clear();
@@ -152,6 +162,9 @@ void check_desc(const dtsph_sim_desc &d, int s, int64_t nf, int64_t nw)
     if (d.stall_window < 0 || d.stall_window > kHist) bad("stall_window must be in [0, 8]");
     if (d.conv_norm != 0 && d.conv_norm != 1) bad("conv_norm must be 0 or 1");
     if (d.max_neighbors < 0 || d.max_neighbors > 8000) bad("max_neighbors must be in [0, 8000]");
+    if (d.shift != 0 && d.shift != 1) bad("shift must be 0 or 1");
+    if (d.shift && (d.shift_n < 1 || d.shift_n > 8)) bad("shift_n must be in [1, 8]");
+    if (d.shift && !(d.shift_r >= 0 && std::isfinite(d.shift_r))) bad("shift_r must be finite and >= 0");
     for (int a = 0; a < d.dim; ++a) {
         if (!(d.hi[a] > d.lo[a])) bad("hi must exceed lo on every axis");
         if (d.periodic[a] && !(d.kappa * d.h < 0.5 * (d.hi[a] - d.lo[a])))
@@ -272,6 +285,10 @@ SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
     S.tiny_r2 = 1e-12 * d.h * d.h;
     S.res_p = S.dt / (rho * S.c * S.c) / (double)nf;
     S.res_v = 1.0 / (d.vref * (double)nf);
+    S.shift = d.shift ? 1 : 0;
+    S.shift_n = d.shift_n;
+    S.shift_r = d.shift_r;
+    S.vol = m / rho;
     return S;
 }
 
@@ -461,7 +478,13 @@ void set_active_ranges(Ctx &c, bool all)
     for (int q = 0; q < n; ++q) c.ranges[q] = r[q];
 }
 
-template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
+// A pseudo-time loop: set-up, chunks of iterations with a stop check after each,
+// and the bookkeeping at its end.
+struct LoopRun {
+    int fixed = 0, max_it = 0, launched = 0, chunk = 1;
+};
+
+template <typename T> void loop_prologue(Ctx &c, int fixed, LoopRun &L)
 {
     if (!c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_pseudo_iterate: not inside a step (call dtsph_predict)");
     if (fixed < 0) throw ApiError(DTSPH_EINVAL, "fixed_iters must be >= 0");
@@ -475,28 +498,41 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
     }
     set_active_ranges(c, true);
     c.pass_times.clear();
-    int max_it = fixed;
+    L.fixed = fixed;
+    L.max_it = fixed;
     if (fixed == 0)
-        for (auto &d : c.desc) max_it = std::max(max_it, (int)d.max_iter);
-    int launched = 0;
-    int chunk = c.chunk > 0 ? c.chunk : std::max(1, std::min(c.last_iters, 64));
-    if (fixed > 0) chunk = std::min(chunk, fixed);
+        for (auto &d : c.desc) L.max_it = std::max(L.max_it, (int)d.max_iter);
+    L.launched = 0;
+    L.chunk = c.chunk > 0 ? c.chunk : std::max(1, std::min(c.last_iters, 64));
+    if (fixed > 0) L.chunk = std::min(L.chunk, fixed);
+}
+
+// The next chunk of iterations (its size: L.chunk, capped by the iteration limit).
+template <typename T> void launch_chunk(Ctx &c, LoopRun &L)
+{
+    const int n = std::min(L.chunk, L.max_it - L.launched);
+    for (int k = 0; k < n; ++k) {
+        c.pass_index = L.launched + k;
+        launch_wall<T>(c, MODE_PSEUDO);
+        launch_pass<T>(c, MODE_PSEUDO);
+        launch_finalize(c, k == n - 1);  // the chunk's last one publishes the reports
+    }
+    L.launched += n;
+}
+
+// Waits for the chunk in flight, launches more until every sim has stopped, and
+// books the loop's reports.
+template <typename T> int loop_finish(Ctx &c, LoopRun &L, dtsph_iter_report *rep)
+{
     for (;;) {
-        const int n = std::min(chunk, max_it - launched);
-        for (int k = 0; k < n; ++k) {
-            c.pass_index = launched + k;
-            launch_wall<T>(c, MODE_PSEUDO);
-            launch_pass<T>(c, MODE_PSEUDO);
-            launch_finalize(c, k == n - 1);  // the chunk's last one publishes the reports
-        }
-        launched += n;
         wait_reports(c);  // k_finalize wrote the mapped reports
         check_host_flags(c);
         bool all = true;
         for (int s = 0; s < c.n_sims; ++s) all = all && c.flags_host[F_COUNT + s];
-        if (all || launched >= max_it) break;
-        chunk = c.chunk > 0 ? c.chunk : 2;
+        if (all || L.launched >= L.max_it) break;
+        L.chunk = c.chunk > 0 ? c.chunk : 2;
         set_active_ranges(c, false);
+        launch_chunk<T>(c, L);
     }
     set_active_ranges(c, true);
     c.p_half = true;  // p^K = p^{K+1/2} - dtau/2 (dp/dtau)^K is applied lazily
@@ -507,6 +543,7 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
         // r^{n+1} - r^(0) = dt/2 (V^{n+1} - V^(0)): within skin/2 (with margin) the
         // candidate lists built at r^(0) still hold every neighbour at r^{n+1}
         cand = cand && c.sims_h[s].skin > 0 && it.disp < 0.4 * c.sims_h[s].skin;
+        c.last_disp[s] = it.disp;
         const int64_t pairs = (int64_t)c.pairs_host[s];
         most = std::max(most, it.iters);
         if (rep) {
@@ -541,6 +578,39 @@ template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
     return status;
 }
 
+template <typename T> int do_loop(Ctx &c, int fixed, dtsph_iter_report *rep)
+{
+    LoopRun L;
+    loop_prologue<T>(c, fixed, L);
+    launch_chunk<T>(c, L);
+    return loop_finish<T>(c, L, rep);
+}
+
+// Particle shifting after the corrector (section 3.5) for the sims that ask
+// for it. The sums run over the candidate lists when they cover r^{n+1}, else
+// over lists of a fresh build there; the largest shift is read back to decide
+// whether the candidate lists still cover the shifted positions.
+template <typename T> void do_shift(Ctx &c)
+{
+    const bool use_cand = c.cand_ok;
+    if (!use_cand) {
+        build_cells<T>(c);
+        c.cells_valid = true;
+        launch_pre_records<T>(c);
+    }
+    launch_shift<T>(c, use_cand);
+    DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+    const double mx = *(volatile double *)c.sh_max_h;
+    bool ok = true;
+    for (int s = 0; s < c.n_sims; ++s) {
+        const double moved = (use_cand ? c.last_disp[s] : 0.0) + mx;
+        ok = ok && c.sims_h[s].skin > 0 && moved < 0.4 * c.sims_h[s].skin;
+    }
+    c.cand_ok = ok;
+    c.cells_valid = false;
+    c.records_fresh = true;  // k_shift_apply rewrote the records
+}
+
 template <typename T> void do_correct(Ctx &c)
 {
     if (!c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_correct: not inside a step (call dtsph_predict)");
@@ -550,6 +620,73 @@ template <typename T> void do_correct(Ctx &c)
     c.cand_ok = c.cand_next;
     c.p_half = false;
     c.records_fresh = true;
+    if (c.any_shift) do_shift<T>(c);
+}
+
+// Would the timer sample one of the next n pair-pass launches?
+bool pass_timer_fires(const Ctx &c, int n)
+{
+    if (!c.timing) return false;
+    for (int k = 0; k < n; ++k)
+        if ((c.timer_count[0] + k) % c.timing_every == 0) return true;
+    return false;
+}
+
+// The segment of a real step that runs without host decisions: rate pass and
+// predictor, the build at the frozen positions with the loop set-up, and the
+// first chunk of pseudo-iterations. With graphs on (and no timed launch in it)
+// it is captured once per key into a HIP graph and replayed afterwards; the
+// host logic still runs (launching nothing) to keep the context's bookkeeping.
+template <typename T> void step_segment(Ctx &c, LoopRun &L)
+{
+    auto body = [&]() {
+        do_predict<T>(c);
+        loop_prologue<T>(c, 0, L);
+        launch_chunk<T>(c, L);
+    };
+    int max_it = 0;
+    for (auto &d : c.desc) max_it = std::max(max_it, (int)d.max_iter);
+    const int n = std::min(c.chunk > 0 ? c.chunk : std::max(1, std::min(c.last_iters, 64)), max_it);
+    if (!c.graphs || pass_timer_fires(c, n)) {
+        body();
+        return;
+    }
+    const bool use_cand = !c.cells_valid && c.cand_ok;
+    const uint64_t key = (uint64_t)c.buf | (uint64_t)c.xb << 1 | (uint64_t)use_cand << 2 |
+                         (uint64_t)c.cells_valid << 3 | (uint64_t)c.records_fresh << 4 | (uint64_t)c.cur << 5 |
+                         (uint64_t)n << 8;
+    struct SegmentFlags {  // restores the mode flags however the body ends
+        Ctx &c;
+        hipStream_t stream;
+        ~SegmentFlags() { c.replay = false; c.in_segment = false; c.stream = stream; }
+    } guard{c, c.stream};
+    c.in_segment = true;
+    auto hit = c.graph_cache.find(key);
+    if (hit != c.graph_cache.end()) {
+        c.replay = true;
+        body();
+        c.replay = false;
+        DTSPH_HIP_CHECK(hipGraphLaunch(hit->second, guard.stream));
+        return;
+    }
+    DTSPH_HIP_CHECK(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeRelaxed));
+    c.stream = c.cap_stream;
+    hipGraph_t g = nullptr;
+    try {
+        body();
+    } catch (...) {
+        (void)hipStreamEndCapture(c.cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    c.stream = guard.stream;
+    DTSPH_HIP_CHECK(hipStreamEndCapture(c.cap_stream, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) throw HipError(e, "hipGraphInstantiate", __FILE__, __LINE__);
+    c.graph_cache[key] = ex;
+    DTSPH_HIP_CHECK(hipGraphLaunch(ex, c.stream));
 }
 
 template <typename T> int do_step(Ctx &c, int n_steps, dtsph_iter_report *reps)
@@ -558,8 +695,9 @@ template <typename T> int do_step(Ctx &c, int n_steps, dtsph_iter_report *reps)
     if (c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_step: inside a step (call dtsph_correct first)");
     int status = DTSPH_OK;
     for (int s = 0; s < n_steps; ++s) {
-        do_predict<T>(c);
-        int st = do_loop<T>(c, 0, reps ? reps + (size_t)s * c.n_sims : nullptr);
+        LoopRun L;
+        step_segment<T>(c, L);
+        int st = loop_finish<T>(c, L, reps ? reps + (size_t)s * c.n_sims : nullptr);
         do_correct<T>(c);
         if (st < 0) return st;
         if (st > 0) status = st;
@@ -580,6 +718,7 @@ namespace dtsph {
 int timer_begin(Ctx &c, int kind)
 {
     if (!c.timing) return -1;
+    if (c.in_segment && kind != 0) return -1;  // graph segments time pair passes only
     if (c.timer_count[kind]++ % c.timing_every != 0) return -1;
     size_t k = c.ev_used;
     c.ev_used += 2;
@@ -591,6 +730,7 @@ int timer_begin(Ctx &c, int kind)
 int timer_slot(Ctx &c, int kind)
 {
     if (!c.timing) return -1;
+    if (c.in_segment && kind != 0) return -1;
     if (c.timer_count[kind]++ % c.timing_every != 0) return -1;
     size_t k = c.ev_used;
     c.ev_used += 2;
@@ -639,6 +779,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         Ctx &c = ctx->c;
         DTSPH_HIP_CHECK(hipGetDevice(&c.device));
         c.stream = (hipStream_t)hip_stream;
+        DTSPH_HIP_CHECK(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
         c.precision = precision;
         c.n_sims = n_sims;
         c.N = (int)N;
@@ -677,6 +818,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             wb += n_wall[s];
             c.any_walls = c.any_walls || n_wall[s] > 0;
             c.any_av = c.any_av || d.alpha > 0;
+            c.any_shift = c.any_shift || d.shift;
             c.sep_den = c.sep_den || S.den_e != S.den_v || (d.alpha > 0 && S.den_a != S.den_v);
             double est;
             if (d.max_neighbors > 0) {
@@ -732,15 +874,24 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         dev_alloc(c, c.seg_p, sizeof(double4) * max_segs);
         dev_alloc(c, c.seg_p2, sizeof(double2) * max_segs);
         dev_alloc(c, c.tickets, sizeof(uint32_t) * n_sims);
+        dev_alloc(c, c.pubcount, sizeof(uint32_t) * n_sims);
         dev_alloc(c, c.partials2, sizeof(double2) * max_tiles);
         dev_alloc(c, c.flags, sizeof(int) * (F_COUNT + n_sims));
         c.done_dev = c.flags + F_COUNT;
         dev_alloc(c, c.init_slot, sizeof(int) * 2 * (size_t)N);
+        if (c.any_shift) {
+            dev_alloc(c, c.sh_dr, 8 * 3 * (size_t)Nf);
+            dev_alloc(c, c.sh_dp, 8 * (size_t)Nf);
+            dev_alloc(c, c.sh_dv, 8 * 3 * (size_t)Nf);
+            dev_alloc(c, c.sh_part, 8 * ((size_t)Nf / 256 + 2));
+        }
+        c.last_disp.assign(n_sims, 0.0);
         {
             const size_t fb_bytes = (sizeof(int) * (F_COUNT + n_sims) + 15) / 16 * 16;
             const size_t pb_bytes = 8 * (size_t)n_sims;
             const size_t rb_bytes = (sizeof(MirrorRep) * n_sims + 15) / 16 * 16;
-            const size_t bytes = fb_bytes + pb_bytes + rb_bytes + sizeof(int) * n_sims;
+            const size_t sq_bytes = (sizeof(int) * n_sims + 15) / 16 * 16;
+            const size_t bytes = fb_bytes + pb_bytes + rb_bytes + sq_bytes + 16;
             DTSPH_HIP_CHECK(hipHostMalloc(&c.mirror_h, bytes, hipHostMallocMapped));
             std::memset(c.mirror_h, 0, bytes);
             void *md = nullptr;
@@ -754,10 +905,13 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             c.m_reps_d = (MirrorRep *)(db + fb_bytes + pb_bytes);
             c.seq_host = (int *)(hb + fb_bytes + pb_bytes + rb_bytes);
             c.m_seq_d = (int *)(db + fb_bytes + pb_bytes + rb_bytes);
+            c.sh_max_h = (double *)(hb + fb_bytes + pb_bytes + rb_bytes + sq_bytes);
+            c.sh_max_d = (double *)(db + fb_bytes + pb_bytes + rb_bytes + sq_bytes);
         }
         DTSPH_HIP_CHECK(hipMemcpy(c.init_slot, init_slot.data(), sizeof(int) * 2 * N, hipMemcpyHostToDevice));
         DTSPH_HIP_CHECK(hipMemset(c.flags, 0, sizeof(int) * (F_COUNT + n_sims)));
         DTSPH_HIP_CHECK(hipMemset(c.tickets, 0, sizeof(uint32_t) * n_sims));
+        DTSPH_HIP_CHECK(hipMemset(c.pubcount, 0, sizeof(uint32_t) * n_sims));
         DTSPH_HIP_CHECK(hipMemset(c.cell_start, 0, 4 * (size_t)(2 * c.C_max + 1)));
         DTSPH_HIP_CHECK(hipMemset(c.count, 0, 4 * (size_t)(2 * c.C_max)));
         DTSPH_HIP_CHECK(hipMemset(c.cnt, 0, 4 * (size_t)N));
@@ -961,6 +1115,9 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
 {
     return guarded(ctx, [&](Ctx &c) {
+        // launch shapes, grids and lists change: recorded graphs are stale
+        if (option != DTSPH_OPT_TIMING && option != DTSPH_OPT_RESET_TIMING && option != DTSPH_OPT_CHUNK)
+            clear_graphs(c);
         switch (option) {
         case DTSPH_OPT_TIMING:
             if (value < 0) throw ApiError(DTSPH_EINVAL, "timing sample interval must be >= 0");
@@ -1008,6 +1165,11 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
             c.cells_valid = false;
             c.cand_ok = c.cand_next = false;
             break;
+        case DTSPH_OPT_GRAPHS:
+            if (value != 0 && value != 1) throw ApiError(DTSPH_EINVAL, "graphs must be 0 or 1");
+            clear_graphs(c);
+            c.graphs = value != 0;
+            break;
         case DTSPH_OPT_NBR_LANES:
             if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
                 throw ApiError(DTSPH_EINVAL, "neighbour-build lanes must be 0, 1, 2, 4 or 8");
@@ -1031,6 +1193,7 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
 {
     return guarded(ctx, [&](Ctx &c) {
         if (c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_autotune: only between steps");
+        clear_graphs(c);
         const int reps = repeats > 0 ? repeats : 5;
         const bool timing = c.timing;
         c.timing = false;

@@ -635,8 +635,8 @@ inline int grid_for(int n) { return n > 0 ? ceil_div(n, kThreads) : 1; }
 template <typename T, int DIM, int G> void launch_g(Ctx &c, const NbrArgs<T> &a, bool filter)
 {
     const dim3 grid(grid_for((int)std::min<int64_t>((int64_t)a.N * G, INT32_MAX)));
-    if (filter) hipLaunchKernelGGL((k_filter<T, DIM, G>), grid, dim3(kThreads), 0, c.stream, a);
-    else hipLaunchKernelGGL((k_nbr<T, DIM, G>), grid, dim3(kThreads), 0, c.stream, a);
+    if (filter) DTSPH_LAUNCH(c, (k_filter<T, DIM, G>), grid, dim3(kThreads), 0, c.stream, a);
+    else DTSPH_LAUNCH(c, (k_nbr<T, DIM, G>), grid, dim3(kThreads), 0, c.stream, a);
 }
 
 // lanes per particle in the neighbour kernels: the autotuner's choice, else
@@ -670,13 +670,13 @@ void build_cells(Ctx &c, int loop_fixed)
     const int N = c.N, nkeys = 2 * c.C;
     const int b = c.buf, o = c.buf ^ 1;
     int t0 = timer_begin(c, 2);
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.Nf, c.C, c.x[c.xb], c.simid[b],
+    DTSPH_LAUNCH(c, k_keys, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.Nf, c.C, c.x[c.xb], c.simid[b],
                        c.sims, c.key, c.rank, c.count);
     const int nblk = ceil_div(nkeys, kScanTile);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(kThreads), 0, st, c.count, nkeys, c.scan_tmp);
-    hipLaunchKernelGGL(k_scan_down, dim3(nblk), dim3(kThreads), 0, st, c.count, nkeys, c.scan_tmp,
+    DTSPH_LAUNCH(c, k_scan_reduce, dim3(nblk), dim3(kThreads), 0, st, c.count, nkeys, c.scan_tmp);
+    DTSPH_LAUNCH(c, k_scan_down, dim3(nblk), dim3(kThreads), 0, st, c.count, nkeys, c.scan_tmp,
                        c.cell_start);
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.key, c.rank, c.cell_start,
+    DTSPH_LAUNCH(c, k_scatter, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.key, c.rank, c.cell_start,
                        c.perm);
     GatherArgs<T> g;
     g.N = N; g.Nf = c.Nf; g.Nw = c.Nw;
@@ -703,7 +703,7 @@ void build_cells(Ctx &c, int loop_fixed)
     g.sims = c.sims;
     g.iters = c.iters;
     g.rec = c.vp[c.cur];
-    hipLaunchKernelGGL(k_rank_gather<T>, dim3(grid_for(N)), dim3(kThreads), 0, st, g);
+    DTSPH_LAUNCH(c, k_rank_gather<T>, dim3(grid_for(N)), dim3(kThreads), 0, st, g);
     c.buf = o;
     c.xb ^= 1;
     c.records_fresh = false;  // the slots moved

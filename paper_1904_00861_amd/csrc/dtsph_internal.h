@@ -20,6 +20,7 @@
 #include <stdint.h>
 
 #include <array>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,9 @@ struct SimDev {
     // 32-bit fixed-point frame of the FP32 pass: x_q = (x - lo) * q_inv mod 2^32
     double q_inv[3], q_len[3];
     double res_p, res_v;          // residual scales incl. 1/nf
+    // particle shifting (section 3.5): on/off, coefficient 1 + shift_r (W/W(h))^shift_n
+    int shift, shift_n;
+    double shift_r, vol;          // vol = m / rho0
 };
 
 // Per-sim pseudo-time loop state (device).
@@ -98,7 +102,7 @@ struct Ctx {
     int chunk = 0;           // 0 = adaptive
     int xcd_remap = 1;
     int max_dim = 2;
-    bool any_walls = false, any_av = false, sep_den = false;
+    bool any_walls = false, any_av = false, sep_den = false, any_shift = false;
     hipStream_t stream = nullptr;
     int device = 0;
 
@@ -202,8 +206,32 @@ struct Ctx {
     std::vector<std::array<int, 3>> ev_pending;  // (start event, kind, pass index)
     size_t ev_used = 0;
 
+    // HIP graphs of the step segment from the rate pass to the first chunk of
+    // pseudo-iterations, keyed by everything that changes its launches
+    bool graphs = true;
+    bool replay = false;       // host logic of a cached segment: launch nothing
+    bool in_segment = false;   // inside a captured or replayed segment
+    hipStream_t cap_stream = nullptr;
+    std::map<uint64_t, hipGraphExec_t> graph_cache;
+    uint32_t *pubcount = nullptr;  // per sim: reports published so far (device)
+
+    // particle shifting: per fluid particle shift and corrections, per-block
+    // maximum |shift|^2, and the last maximum read back by the host
+    double *sh_dr = nullptr, *sh_dp = nullptr;
+    void *sh_dv = nullptr;
+    double *sh_part = nullptr;
+    double *sh_max_h = nullptr, *sh_max_d = nullptr;  // mapped host memory
+    std::vector<double> last_disp;    // per sim: max |r^{n+1} - r^(0)| of the last loop
+
     std::string err;
 };
+
+// Every kernel launch of the library goes through this gate: while the host
+// logic of a cached graph segment runs (replay), it launches nothing.
+#define DTSPH_LAUNCH(ctx, ...)                                                             \
+    do {                                                                                   \
+        if (!(ctx).replay) hipLaunchKernelGGL(__VA_ARGS__);                                \
+    } while (0)
 
 // ---- launchers (defined in the .hip files) ---------------------------------
 // build_cells(c, loop_fixed): with loop_fixed >= 0 the gather also performs the
@@ -218,6 +246,7 @@ void launch_finalize(Ctx &c, bool publish);
 void launch_publish(Ctx &c);
 template <typename T> void launch_loop_begin(Ctx &c, int fixed_iters);
 template <typename T> void launch_correct(Ctx &c);
+template <typename T> void launch_shift(Ctx &c, bool cand_lists);  // sums, apply, max
 template <typename T> void launch_set_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
 template <typename T> void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
 

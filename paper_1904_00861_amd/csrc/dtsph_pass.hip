@@ -516,8 +516,8 @@ struct FinArgs {
     int *h_flags;
     MirrorRep *h_reps;
     unsigned long long *h_pairs;
-    int *h_seq;      // per sim: `seq` once its report of this launch is visible
-    int seq;
+    int *h_seq;      // per sim: its count of published reports, once this one is visible
+    uint32_t *pubcount;
     int publish;     // 0: device state only (not the last iteration of a chunk)
 };
 
@@ -582,8 +582,10 @@ __device__ inline void publish_report(const FinArgs &A, int s, const SimIter &It
     A.h_reps[s] = r;
     A.h_pairs[s] = (unsigned long long)It.pairs;
     if (s == 0) move_build_flags(A);
+    const uint32_t q = A.pubcount[s] + 1u;  // one publishing thread per sim and launch
+    A.pubcount[s] = q;
     __threadfence_system();
-    A.h_seq[s] = A.seq;
+    A.h_seq[s] = (int)q;
 }
 
 __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
@@ -781,6 +783,158 @@ __global__ void k_correct(int N, int Nf, const int *__restrict__ simid, const Si
     vrec[i] = S.dim == 2 ? make_rec<T, 2>(vr, (T)p) : make_rec<T, 3>(vr, (T)p);
 }
 
+// ---- particle shifting (section 3.5: eqs. shift, shift-deltar, shift-correct) ---
+// After the corrector, for fluid particles of sims with shifting on, over the
+// neighbour lists at the corrected positions (fluid and wall entries; a list
+// entry beyond the support adds nothing):
+//   div r = -sum_j V_j r_ij . gradW_ij; free surface if div r < dim - 1/2
+//   dr = -(h^2/2) sum_j V_j (1 + R (W_ij / W(h))^n) gradW_ij (0 on the free surface)
+//   grad phi = sum_j V_j (phi_j - phi_i) gradW_ij over fluid j, phi in {p, V}
+// k_shift_sums evaluates these from the unshifted records into scratch arrays;
+// k_shift_apply then moves the particles and adds the Taylor corrections
+// grad phi . dr to p^{n+1} and V^{n+1} (and to V^{n+1} - V^n).
+template <typename T> struct ShiftArgs {
+    using Q = typename V4<T>::type;
+    int N, Nf, Nw;
+    const int *simid;
+    const SimDev *sims;
+    const int *nbr;
+    const uint32_t *cnt;
+    void *prec;
+    Q *vrec;            // {V, p} records of buffer cur (read by the sums, rewritten by apply)
+    double *dr, *dp;    // per fluid particle: shift (3 x Nf), pressure correction
+    T *dv;              // velocity correction (3 x Nf)
+    double *part;       // per workgroup: max |dr|^2
+    double *x;          // active positions (3 x N)
+    void *xr;
+    T *vn, *vdiff;      // V^{n+1}; V^{n+1} - V^n
+    double *pm;
+};
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_shift_sums(ShiftArgs<T> A)
+{
+    using Q = typename V4<T>::type;
+    using PosT = Pos<T, DIM>;
+    using Rec = typename PosT::Rec;
+    __shared__ double lds[4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double m2 = 0.0;
+    if (i < A.Nf) {
+        const SimDev &S = A.sims[A.simid[i]];
+        double del[3] = {0.0, 0.0, 0.0}, dpi = 0.0;
+        T dvi[3] = {T(0), T(0), T(0)};
+        if (S.shift) {
+            const PosT pos(S);
+            const Rec *__restrict__ prec = (const Rec *)A.prec;
+            const Rec ri = prec[i];
+            const Q me = A.vrec[i];
+            const T pi = pres<DIM>(me);
+            const T vi[3] = {me.x, me.y, DIM == 3 ? me.z : T(0)};
+            const T inv_h = (T)S.inv_h, kg = (T)S.kg, vol = (T)S.vol, rco = (T)S.shift_r;
+            const int nexp = S.shift_n;
+            T divr = 0, sd[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, gv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            const uint32_t cn = A.cnt[i];
+            const int total = (int)(cn & 0xffffu) + (int)(cn >> 16);
+            const int *__restrict__ nb = A.nbr + i;
+            for (int k = 0; k < total; ++k) {
+                const int j = nb[(size_t)k * A.N];
+                T r[3];
+                pos.delta(ri, prec[j], r);
+                T r2 = r[0] * r[0] + r[1] * r[1];
+                if (DIM == 3) r2 += r[2] * r[2];
+                if (!(r2 > T(0))) continue;
+                const T rinv = rsq<T>(r2);
+                const T q = r2 * rinv * inv_h;
+                T t3 = T(3) - q, t2 = T(2) - q, t1 = T(1) - q;
+                t3 = t3 > T(0) ? t3 : T(0);
+                t2 = t2 > T(0) ? t2 : T(0);
+                t1 = t1 > T(0) ? t1 : T(0);
+                const T a4 = t3 * t3 * t3 * t3, b4 = t2 * t2 * t2 * t2, c4 = t1 * t1 * t1 * t1;
+                const T f = kg * (T(15) * c4 + (T(-6) * b4 + a4)) * rinv;  // dW/dr / r
+                const T w5 = T(15) * c4 * t1 + (T(-6) * b4 * t2 + a4 * t3);
+                divr -= vol * f * r2;
+                const T ratio = w5 * T(1.0 / 26.0);  // W / W(h): w(1) = 2^5 - 6 = 26
+                T pw = T(1);
+                for (int e = 0; e < nexp; ++e) pw *= ratio;
+                const T cf = vol * (T(1) + rco * pw) * f;
+                for (int a = 0; a < DIM; ++a) sd[a] += cf * r[a];
+                if (j < A.Nf) {
+                    const Q vj = A.vrec[j];
+                    const T cp = vol * (pres<DIM>(vj) - pi) * f;
+                    const T vjv[3] = {vj.x, vj.y, DIM == 3 ? vj.z : T(0)};
+                    for (int a = 0; a < DIM; ++a) gp[a] += cp * r[a];
+                    for (int b = 0; b < DIM; ++b) {
+                        const T cv = vol * (vjv[b] - vi[b]) * f;
+                        for (int a = 0; a < DIM; ++a) gv[b][a] += cv * r[a];
+                    }
+                }
+            }
+            if (!(divr < T(S.dim) - T(0.5)))  // not on the free surface
+                for (int a = 0; a < DIM; ++a) del[a] = -0.5 * S.h * S.h * (double)sd[a];
+            for (int a = 0; a < DIM; ++a) dpi += (double)gp[a] * del[a];
+            for (int b = 0; b < DIM; ++b) {
+                double acc = 0.0;
+                for (int a = 0; a < DIM; ++a) acc += (double)gv[b][a] * del[a];
+                dvi[b] = (T)acc;
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            A.dr[a * A.Nf + i] = del[a];
+            A.dv[a * A.Nf + i] = dvi[a];
+        }
+        A.dp[i] = dpi;
+        m2 = (del[0] * del[0] + del[1] * del[1]) + del[2] * del[2];
+    }
+    for (int o = 32; o > 0; o >>= 1) m2 = fmax(m2, __shfl_xor(m2, o, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m2;
+    __syncthreads();
+    if (threadIdx.x == 0) A.part[blockIdx.x] = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_shift_apply(ShiftArgs<T> A)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.Nf) return;
+    const SimDev &S = A.sims[A.simid[i]];
+    if (!S.shift) return;
+    const int N = A.N, Nf = A.Nf;
+    double xo[3] = {0.0, 0.0, 0.0};
+    T v[3] = {T(0), T(0), T(0)};
+    for (int a = 0; a < DIM; ++a) {
+        double xv = A.x[a * N + i] + A.dr[a * Nf + i];
+        if (S.periodic[a]) {
+            if (xv >= S.hi[a]) xv -= S.L[a];
+            else if (xv < S.lo[a]) xv += S.L[a];
+        }
+        A.x[a * N + i] = xv;
+        xo[a] = xv;
+        const T d = A.dv[a * Nf + i];
+        v[a] = A.vn[a * Nf + i] + d;
+        A.vn[a * Nf + i] = v[a];
+        A.vdiff[a * Nf + i] += d;
+    }
+    const double p = A.pm[i] + A.dp[i];
+    A.pm[i] = p;
+    if (DIM == 2) ((double2 *)A.xr)[i] = make_double2(xo[0], xo[1]);
+    else ((double4 *)A.xr)[i] = make_double4(xo[0], xo[1], xo[2], 0.0);
+    write_pos_record<T>(S, A.prec, i, xo);
+    A.vrec[i] = make_rec<T, DIM>(v, (T)p);
+}
+
+// Largest shift of the launch into mapped memory (one workgroup).
+__global__ void __launch_bounds__(256) k_shift_max(const double *__restrict__ part, int n, double *out)
+{
+    __shared__ double lds[4];
+    double m = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) m = fmax(m, part[k]);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = sqrt(fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3])));
+}
+
 template <typename T>
 struct StateArgs {
     int N, Nf, Nw, in_loop, p_half;
@@ -908,12 +1062,12 @@ template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int LPP>
 void dispatch_mode(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
 {
     if (mode == MODE_PRE)
-        hipLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PRE, LPP>), grid, dim3(c.block), 0, c.stream, a);
+        DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PRE, LPP>), grid, dim3(c.block), 0, c.stream, a);
     else if (c.ext_start)
         hipExtLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP>), grid, dim3(c.block), 0,
                               c.stream, c.ext_start, c.ext_stop, 0, a);
     else
-        hipLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP>), grid, dim3(c.block), 0, c.stream,
+        DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP>), grid, dim3(c.block), 0, c.stream,
                            a);
 }
 
@@ -987,8 +1141,8 @@ void launch_wall(Ctx &c, int mode, bool cand_lists)
     a.pwall = (T *)c.pw[b];
     a.x = c.x[c.xb]; a.x_alt = c.x[c.xb ^ 1];
     int t0 = mode == MODE_PSEUDO ? timer_begin(c, 1) : -1;
-    if (c.max_dim == 2) hipLaunchKernelGGL((k_wall<T, 2>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
-    else hipLaunchKernelGGL((k_wall<T, 3>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
+    if (c.max_dim == 2) DTSPH_LAUNCH(c, (k_wall<T, 2>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
+    else DTSPH_LAUNCH(c, (k_wall<T, 3>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
     DTSPH_HIP_CHECK(hipGetLastError());
     if (mode == MODE_PSEUDO) timer_end(c, t0, 1);
 }
@@ -996,7 +1150,7 @@ void launch_wall(Ctx &c, int mode, bool cand_lists)
 void launch_publish(Ctx &c)
 {
     const int n = F_COUNT + c.n_sims;
-    hipLaunchKernelGGL(k_publish, dim3(grid_for(n)), dim3(256), 0, c.stream, c.n_sims, c.flags, c.iters,
+    DTSPH_LAUNCH(c, k_publish, dim3(grid_for(n)), dim3(256), 0, c.stream, c.n_sims, c.flags, c.iters,
                        c.m_flags_d, c.m_reps_d, c.m_pairs_d);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
@@ -1009,9 +1163,10 @@ void launch_finalize(Ctx &c, bool publish)
     a.done_out = c.done_dev; a.flags = c.flags; a.n_sims = c.n_sims;
     a.h_flags = c.m_flags_d; a.h_reps = c.m_reps_d; a.h_pairs = c.m_pairs_d;
     a.h_seq = c.m_seq_d;
+    a.pubcount = c.pubcount;
     a.publish = publish ? 1 : 0;
-    a.seq = publish ? ++c.seq : c.seq;
-    hipLaunchKernelGGL(k_finalize, dim3(c.n_segs), dim3(kFinThreads), 0, c.stream, a);
+    if (publish) ++c.seq;  // every sim's count advances once per publishing launch
+    DTSPH_LAUNCH(c, k_finalize, dim3(c.n_segs), dim3(kFinThreads), 0, c.stream, a);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -1021,11 +1176,11 @@ void launch_pre_records(Ctx &c)
     using Q = typename V4<T>::type;
     const int b = c.buf;
     if (c.max_dim == 2)
-        hipLaunchKernelGGL((k_records<T, 2>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
+        DTSPH_LAUNCH(c, (k_records<T, 2>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
                            (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0,
                            0, c.iters, c.n_sims, 0);
     else
-        hipLaunchKernelGGL((k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
+        DTSPH_LAUNCH(c, (k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
                            (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0,
                            0, c.iters, c.n_sims, 0);
     DTSPH_HIP_CHECK(hipGetLastError());
@@ -1037,11 +1192,11 @@ void launch_loop_begin(Ctx &c, int fixed_iters)
     using Q = typename V4<T>::type;
     const int b = c.buf;
     if (c.max_dim == 2)
-        hipLaunchKernelGGL((k_records<T, 2>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
+        DTSPH_LAUNCH(c, (k_records<T, 2>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
                            (const T *)c.vn[b], (const T *)c.w[b], c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 1,
                            c.p_half ? 0 : 1, c.iters, c.n_sims, fixed_iters);
     else
-        hipLaunchKernelGGL((k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
+        DTSPH_LAUNCH(c, (k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
                            (const T *)c.vn[b], (const T *)c.w[b], c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 1,
                            c.p_half ? 0 : 1, c.iters, c.n_sims, fixed_iters);
     DTSPH_HIP_CHECK(hipGetLastError());
@@ -1052,9 +1207,36 @@ void launch_correct(Ctx &c)
 {
     const int b = c.buf;
     using Q = typename V4<T>::type;
-    hipLaunchKernelGGL(k_correct<T>, dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.N, c.Nf, c.simid[b], c.sims,
+    DTSPH_LAUNCH(c, k_correct<T>, dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.N, c.Nf, c.simid[b], c.sims,
                        c.x[c.xb], c.xn[b], (T *)c.vn[b], (T *)c.dv[b], (T *)c.w[b], c.xr, c.pm[b],
                        (const T *)c.dp[b], c.p_half ? 1 : 0, c.prec, (Q *)c.vp[c.cur]);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_shift(Ctx &c, bool cand_lists)
+{
+    using Q = typename V4<T>::type;
+    const int b = c.buf;
+    ShiftArgs<T> a;
+    a.N = c.N; a.Nf = c.Nf; a.Nw = c.Nw;
+    a.simid = c.simid[b]; a.sims = c.sims;
+    a.nbr = cand_lists ? c.cand : c.nbr;
+    a.cnt = cand_lists ? c.ccnt : c.cnt;
+    a.prec = c.prec;
+    a.vrec = (Q *)c.vp[c.cur];
+    a.dr = c.sh_dr; a.dp = c.sh_dp; a.dv = (T *)c.sh_dv; a.part = c.sh_part;
+    a.x = c.x[c.xb]; a.xr = c.xr;
+    a.vn = (T *)c.vn[b]; a.vdiff = (T *)c.dv[b]; a.pm = c.pm[b];
+    const int nblk = grid_for(c.Nf);
+    if (c.max_dim == 2) {
+        DTSPH_LAUNCH(c, (k_shift_sums<T, 2>), dim3(nblk), dim3(256), 0, c.stream, a);
+        DTSPH_LAUNCH(c, (k_shift_apply<T, 2>), dim3(nblk), dim3(256), 0, c.stream, a);
+    } else {
+        DTSPH_LAUNCH(c, (k_shift_sums<T, 3>), dim3(nblk), dim3(256), 0, c.stream, a);
+        DTSPH_LAUNCH(c, (k_shift_apply<T, 3>), dim3(nblk), dim3(256), 0, c.stream, a);
+    }
+    DTSPH_LAUNCH(c, k_shift_max, dim3(1), dim3(256), 0, c.stream, c.sh_part, nblk, c.sh_max_d);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -1082,7 +1264,7 @@ template <typename T>
 void launch_set_state(Ctx &c, const dtsph_state_view &s, bool in_loop)
 {
     StateArgs<T> a = state_args<T>(c, s, in_loop);
-    hipLaunchKernelGGL(k_set_state<T>, dim3(grid_for(c.N)), dim3(256), 0, c.stream, a);
+    DTSPH_LAUNCH(c, k_set_state<T>, dim3(grid_for(c.N)), dim3(256), 0, c.stream, a);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -1090,7 +1272,7 @@ template <typename T>
 void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop)
 {
     StateArgs<T> a = state_args<T>(c, s, in_loop);
-    hipLaunchKernelGGL(k_get_state<T>, dim3(grid_for(c.N)), dim3(256), 0, c.stream, a);
+    DTSPH_LAUNCH(c, k_get_state<T>, dim3(grid_for(c.N)), dim3(256), 0, c.stream, a);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -1100,6 +1282,7 @@ void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop)
     template void launch_pre_records<T>(Ctx &);                                \
     template void launch_loop_begin<T>(Ctx &, int);                            \
     template void launch_correct<T>(Ctx &);                                    \
+    template void launch_shift<T>(Ctx &, bool);                                \
     template void launch_set_state<T>(Ctx &, const dtsph_state_view &, bool);  \
     template void launch_get_state<T>(Ctx &, const dtsph_state_view &, bool);
 DTSPH_INSTANTIATE(float)

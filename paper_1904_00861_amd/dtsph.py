@@ -22,7 +22,7 @@ EINVAL, ENOMEM, EHIP, ENONFINITE, EOVERFLOW = -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 REASONS = {0: "running", 1: "converged", 2: "stalled", 3: "max_iter", 4: "nonfinite", 5: "fixed"}
 OPT_TIMING, OPT_RESET_TIMING, OPT_CHUNK, OPT_BLOCK, OPT_XCD_REMAP, OPT_LANES, OPT_SKIN = 1, 2, 3, 4, 5, 6, 7
-OPT_CELL_DIV, OPT_NBR_LANES = 8, 9
+OPT_CELL_DIV, OPT_NBR_LANES, OPT_GRAPHS = 8, 9, 10
 
 EXPORTS = [
     "dtsph_create", "dtsph_destroy", "dtsph_last_error", "dtsph_set_state", "dtsph_get_state",
@@ -55,6 +55,8 @@ class SimDesc(C.Structure):
         ("edac_rho_literal", C.c_int32), ("reserved0", C.c_int32),
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("periodic", C.c_int32 * 3), ("reserved1", C.c_int32),
+        ("shift", C.c_int32), ("shift_n", C.c_int32),
+        ("shift_r", C.c_double),
     ]
 
 
@@ -163,7 +165,7 @@ def desc_from_params(p: dict) -> SimDesc:
         elif name == "periodic":
             getattr(d, name)[:] = [int(t) for t in val]
         elif name in ("dim", "max_neighbors", "max_iter", "stall_window", "conv_norm",
-                      "edac_reg_literal", "edac_rho_literal"):
+                      "edac_reg_literal", "edac_rho_literal", "shift", "shift_n"):
             setattr(d, name, int(val))
         else:
             setattr(d, name, float(val))

@@ -59,6 +59,9 @@ BASE_PARAMS = dict(
     edac_reg_literal=0,
     edac_rho_literal=0,
     max_neighbors=0,    # 0 -> library estimate
+    shift=0,            # particle shifting after the corrector (section 3.5): 0 off, 1 on
+    shift_r=1.0,        # shifting coefficient 1 + shift_r * (W / W(dx))^shift_n,
+    shift_n=1,          # dx = h; the printed form is R = n = 1
 )
 
 CFL = 0.25  # dt * V_ref = C * h with C = 0.25
