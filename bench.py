@@ -227,6 +227,17 @@ def main():
             extras["batched_instance_steps_per_s"] = len(batch) * bsteps / bl["seconds"]
             extras["batched_pair_evals_per_s"] = pair_evals(bl["reports"]) / bl["seconds"]
             extras["batched_workload"] = WORKLOADS["C4"] + ", FP32 sums, 5 steps"
+        if not any(p.params.get("shift", 0) for p in problems):
+            # the same workload with the paper's particle shifting after each step
+            shifted = []
+            for p in problems:
+                q = p.copy()
+                q.params = dict(p.params, shift=1)
+                shifted.append(q)
+            log("leg with particle shifting")
+            sl = run_leg(shifted, prec, args.steps, args.warmup, 0)
+            extras["with_shifting_value"] = pair_evals(sl["reports"]) / sl["seconds"]
+            extras["with_shifting_ms_per_step"] = sl["seconds"] * 1e3 / args.steps
     extras["iterations_per_step_mean"] = sum(iters) / len(iters)
     if tm["pass_launches"]:
         launches_all = sum(max(r["iters"] for r in step) for step in main_leg["reports"])
@@ -251,6 +262,7 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "particles": n_particles,
+                   "particle_shifting": bool(any(p.params.get("shift", 0) for p in problems)),
                    "pair_sums": args.precision,
                    "positions_pressure_residuals": "f64"},
         "roofline": roofline,

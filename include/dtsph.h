@@ -297,12 +297,14 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
                                   +-value cells per axis                      */
 #define DTSPH_OPT_NBR_LANES 9  /* lanes per particle of the neighbour-list
                                   build: 1, 2, 4, 8 (0: automatic)           */
-#define DTSPH_OPT_GRAPHS 10    /* 1 (default): dtsph_step records the segment
-                                  from the rate pass to the first chunk of
-                                  pseudo-iterations as a HIP graph (one per
-                                  launch configuration, kept by the context)
-                                  and replays it; 0: plain launches. Steps
-                                  with a timed pair-pass launch run plainly.  */
+#define DTSPH_OPT_GRAPHS 10    /* 1: dtsph_step records the segment from the
+                                  rate pass to the first chunk of pseudo-
+                                  iterations as a HIP graph (one per launch
+                                  configuration, at most 16, kept by the
+                                  context) and replays it; 0 (default): plain
+                                  launches, which measured faster on MI355X
+                                  for every workload here. Steps with a timed
+                                  pair-pass launch run plainly.               */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the pair pass's launch shape. Between steps only (EINVAL in

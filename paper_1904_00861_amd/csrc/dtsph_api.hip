@@ -655,6 +655,11 @@ template <typename T> void step_segment(Ctx &c, LoopRun &L)
     const uint64_t key = (uint64_t)c.buf | (uint64_t)c.xb << 1 | (uint64_t)use_cand << 2 |
                          (uint64_t)c.cells_valid << 3 | (uint64_t)c.records_fresh << 4 | (uint64_t)c.cur << 5 |
                          (uint64_t)n << 8;
+    constexpr size_t kMaxGraphs = 16;  // recording is costly: past this many keys, launch plainly
+    if (c.graph_cache.size() >= kMaxGraphs && c.graph_cache.find(key) == c.graph_cache.end()) {
+        body();
+        return;
+    }
     struct SegmentFlags {  // restores the mode flags however the body ends
         Ctx &c;
         hipStream_t stream;

@@ -208,7 +208,7 @@ struct Ctx {
 
     // HIP graphs of the step segment from the rate pass to the first chunk of
     // pseudo-iterations, keyed by everything that changes its launches
-    bool graphs = true;
+    bool graphs = false;
     bool replay = false;       // host logic of a cached segment: launch nothing
     bool in_segment = false;   // inside a captured or replayed segment
     hipStream_t cap_stream = nullptr;

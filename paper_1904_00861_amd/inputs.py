@@ -279,15 +279,24 @@ def config(name: str):
     C0: 2D TGV 50^2, FP64, 10 steps      C1: 2D TGV 400^2, 200 steps
     C2: 3D TGV 64^3, 50 steps            C3: 2D dam break dx=0.002, 100 steps
     C4: batch of 64 TGV/cavity instances, 50 steps each
+
+    C2 and C3 switch on the paper's particle shifting (section 3.5, used there
+    for every test case): without it the 3D vortex turns unstable after about
+    30 steps and the dam break after about 58, the same in any implementation of
+    the step (the oracle and the library follow the same trajectory).
     """
     if name == "C0":
         return tgv2d(50, seed=1904)
     if name == "C1":
         return tgv2d(400, seed=1905)
     if name == "C2":
-        return tgv3d(64, seed=1906)
+        prob = tgv3d(64, seed=1906)
+        prob.params = dict(prob.params, shift=1)
+        return prob
     if name == "C3":
-        return dam_break(0.002)
+        prob = dam_break(0.002)
+        prob.params = dict(prob.params, shift=1)
+        return prob
     if name == "C4":
         return batch(64)
     raise KeyError(name)

@@ -31,6 +31,7 @@ def _pair(case, prec):
     eager = D.Sim(prob, precision=prec)
     eager.set_option(D.OPT_GRAPHS, 0)
     graph = D.Sim(prob, precision=prec)
+    graph.set_option(D.OPT_GRAPHS, 1)
     return eager, graph
 
 
