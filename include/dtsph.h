@@ -290,8 +290,9 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
 #define DTSPH_OPT_LANES 6      /* lanes per particle in the pair pass: 1, 2, 4, 8
                                   (default: smallest giving >= 512k threads)  */
 #define DTSPH_OPT_SKIN 7       /* candidate-list skin in thousandths of h, at
-                                  most the default 100 (0: rebuild the cell
-                                  lists at every position change)            */
+                                  most the default (100; 250 for sims with
+                                  shifting) (0: rebuild the cell lists at
+                                  every position change)                     */
 #define DTSPH_OPT_CELL_DIV 8   /* cell side >= (kappa h + skin) / value, value
                                   in {1, 2, 3} (default 2); the search visits
                                   +-value cells per axis                      */

@@ -214,9 +214,10 @@ SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
     S.nw = (int)nw;
     S.edac_reg_literal = d.edac_reg_literal;
     const double kh = d.kappa * d.h;
-    // candidate lists reach kappa h + skin: skin = 0.1 h, reduced so that the
-    // candidate radius stays below half of every period
-    double skin = 0.1 * d.h;
+    // candidate lists reach kappa h + skin: skin = 0.1 h (0.25 h with particle
+    // shifting, whose moves of a few hundredths of h add to the loop's), reduced
+    // so that the candidate radius stays below half of every period
+    double skin = (d.shift ? 0.25 : 0.1) * d.h;
     for (int a = 0; a < d.dim; ++a)
         if (d.periodic[a]) skin = std::min(skin, 0.5 * (0.5 * (d.hi[a] - d.lo[a]) - kh));
     S.skin = std::max(0.0, skin);
@@ -888,7 +889,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             dev_alloc(c, c.sh_dr, 8 * 3 * (size_t)Nf);
             dev_alloc(c, c.sh_dp, 8 * (size_t)Nf);
             dev_alloc(c, c.sh_dv, 8 * 3 * (size_t)Nf);
-            dev_alloc(c, c.sh_part, 8 * ((size_t)Nf / 256 + 2));
+            dev_alloc(c, c.sh_part, 8 * ((size_t)Nf * 4 / 256 + 2));  // per shift-sum workgroup
         }
         c.last_disp.assign(n_sims, 0.0);
         {

@@ -811,16 +811,19 @@ template <typename T> struct ShiftArgs {
     double *pm;
 };
 
-template <typename T, int DIM>
+// SL lanes share one particle (list entries sub, sub + SL, ...), combined by
+// butterfly shuffles.
+template <typename T, int DIM, int SL>
 __global__ void __launch_bounds__(256) k_shift_sums(ShiftArgs<T> A)
 {
     using Q = typename V4<T>::type;
     using PosT = Pos<T, DIM>;
     using Rec = typename PosT::Rec;
     __shared__ double lds[4];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = (int)threadIdx.x & (SL - 1);
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / SL;
     double m2 = 0.0;
-    if (i < A.Nf) {
+    if (i < A.Nf) {  // uniform in each group of SL lanes
         const SimDev &S = A.sims[A.simid[i]];
         double del[3] = {0.0, 0.0, 0.0}, dpi = 0.0;
         T dvi[3] = {T(0), T(0), T(0)};
@@ -837,7 +840,7 @@ __global__ void __launch_bounds__(256) k_shift_sums(ShiftArgs<T> A)
             const uint32_t cn = A.cnt[i];
             const int total = (int)(cn & 0xffffu) + (int)(cn >> 16);
             const int *__restrict__ nb = A.nbr + i;
-            for (int k = 0; k < total; ++k) {
+            for (int k = sub; k < total; k += SL) {
                 const int j = nb[(size_t)k * A.N];
                 T r[3];
                 pos.delta(ri, prec[j], r);
@@ -870,6 +873,14 @@ __global__ void __launch_bounds__(256) k_shift_sums(ShiftArgs<T> A)
                     }
                 }
             }
+            if (SL > 1) {
+                lane_sum(divr, SL);
+                for (int a = 0; a < DIM; ++a) {
+                    lane_sum(sd[a], SL);
+                    lane_sum(gp[a], SL);
+                    for (int b = 0; b < DIM; ++b) lane_sum(gv[b][a], SL);
+                }
+            }
             if (!(divr < T(S.dim) - T(0.5)))  // not on the free surface
                 for (int a = 0; a < DIM; ++a) del[a] = -0.5 * S.h * S.h * (double)sd[a];
             for (int a = 0; a < DIM; ++a) dpi += (double)gp[a] * del[a];
@@ -879,12 +890,14 @@ __global__ void __launch_bounds__(256) k_shift_sums(ShiftArgs<T> A)
                 dvi[b] = (T)acc;
             }
         }
-        for (int a = 0; a < 3; ++a) {
-            A.dr[a * A.Nf + i] = del[a];
-            A.dv[a * A.Nf + i] = dvi[a];
+        if (sub == 0) {
+            for (int a = 0; a < 3; ++a) {
+                A.dr[a * A.Nf + i] = del[a];
+                A.dv[a * A.Nf + i] = dvi[a];
+            }
+            A.dp[i] = dpi;
+            m2 = (del[0] * del[0] + del[1] * del[1]) + del[2] * del[2];
         }
-        A.dp[i] = dpi;
-        m2 = (del[0] * del[0] + del[1] * del[1]) + del[2] * del[2];
     }
     for (int o = 32; o > 0; o >>= 1) m2 = fmax(m2, __shfl_xor(m2, o, 64));
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m2;
@@ -1228,15 +1241,16 @@ void launch_shift(Ctx &c, bool cand_lists)
     a.dr = c.sh_dr; a.dp = c.sh_dp; a.dv = (T *)c.sh_dv; a.part = c.sh_part;
     a.x = c.x[c.xb]; a.xr = c.xr;
     a.vn = (T *)c.vn[b]; a.vdiff = (T *)c.dv[b]; a.pm = c.pm[b];
-    const int nblk = grid_for(c.Nf);
+    // lanes per particle: 4 for the ~110 neighbours of 3D, 2 for the ~26 of 2D
+    const int nblk = grid_for(c.Nf), nsum = grid_for(c.Nf * (c.max_dim == 2 ? 2 : 4));
     if (c.max_dim == 2) {
-        DTSPH_LAUNCH(c, (k_shift_sums<T, 2>), dim3(nblk), dim3(256), 0, c.stream, a);
+        DTSPH_LAUNCH(c, (k_shift_sums<T, 2, 2>), dim3(nsum), dim3(256), 0, c.stream, a);
         DTSPH_LAUNCH(c, (k_shift_apply<T, 2>), dim3(nblk), dim3(256), 0, c.stream, a);
     } else {
-        DTSPH_LAUNCH(c, (k_shift_sums<T, 3>), dim3(nblk), dim3(256), 0, c.stream, a);
+        DTSPH_LAUNCH(c, (k_shift_sums<T, 3, 4>), dim3(nsum), dim3(256), 0, c.stream, a);
         DTSPH_LAUNCH(c, (k_shift_apply<T, 3>), dim3(nblk), dim3(256), 0, c.stream, a);
     }
-    DTSPH_LAUNCH(c, k_shift_max, dim3(1), dim3(256), 0, c.stream, c.sh_part, nblk, c.sh_max_d);
+    DTSPH_LAUNCH(c, k_shift_max, dim3(1), dim3(256), 0, c.stream, c.sh_part, nsum, c.sh_max_d);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
