@@ -255,6 +255,19 @@ k_pass(PassArgs<T> A)
     Acc<T> acc;
     T pi = 0, vi[3] = {0, 0, 0};
     int npairs = 0;
+    // the owner's own state for the update, loaded before the neighbour loop so
+    // that its latency hides behind the gathers
+    T st_w[3] = {0, 0, 0}, st_dv[3] = {0, 0, 0}, st_w0[3] = {0, 0, 0}, st_vn[3] = {0, 0, 0};
+    double st_pm = 0.0;
+    if (MODE == MODE_PSEUDO && owner) {
+        for (int d = 0; d < DIM; ++d) {
+            st_w[d] = A.w[d * Nf + i];
+            st_dv[d] = A.dv[d * Nf + i];
+            st_w0[d] = A.w0[d * Nf + i];
+            st_vn[d] = A.vn[d * Nf + i];
+        }
+        st_pm = A.pm[i];
+    }
     if (active) {
         const Rec ri = prec[i];
         const Q me = vin[i];
@@ -336,18 +349,18 @@ k_pass(PassArgs<T> A)
             const T inv2dt = (T)S.inv2dt, gamma = (T)S.gamma, dtau = (T)S.dtau, dt = (T)S.dt;
             T vnew[3] = {0, 0, 0};
             for (int d = 0; d < DIM; ++d) {
-                const T wk = A.w[d * Nf + i];
-                const T bdf = (T(3) * wk - A.dv[d * Nf + i]) * inv2dt;
+                const T wk = st_w[d];
+                const T bdf = (T(3) * wk - st_dv[d]) * inv2dt;
                 const T dvdtau = (R[d] - bdf) * gamma;
                 const T wn = wk + dtau * dvdtau;
                 const T vt = dt * dvdtau;
                 vt2 += vt * vt;
-                const T dw = wn - A.w0[d * Nf + i];
+                const T dw = wn - st_w0[d];
                 dw2 += dw * dw;
                 A.w[d * Nf + i] = wn;
-                vnew[d] = A.vn[d * Nf + i] + wn;
+                vnew[d] = st_vn[d] + wn;
             }
-            const double pm = A.pm[i] + S.dtau * (double)Dv;
+            const double pm = st_pm + S.dtau * (double)Dv;
             A.pm[i] = pm;
             A.dp[i] = Dv;
             vout[i] = make_rec<T, DIM>(vnew, (T)pm);
