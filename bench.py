@@ -90,22 +90,39 @@ def run_leg(problems, precision, steps, warmup, timing_every, shape=None):
 
 
 def traffic_from_profile(kernel_src, shape):
-    """HBM bytes per pair-pass launch from the committed counter summary, or None
-    if the summary is missing, was taken for another launch shape (lanes, block)
-    or the pass kernel changed since it was taken."""
+    """HBM bytes per pair-pass launch from the committed counter summary for the
+    launch shape (lanes, block, cell subdivision), or None if the summary is
+    missing, has no row for that shape or the pass kernel changed since it was
+    taken."""
     path = os.path.join(ROOT, "profiles", "k_pass_C1_fp32_traffic.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_hash = re.search(r"source sha256: ([0-9a-f]{64})", txt)
-    m_bytes = re.search(r"HBM bytes per launch: ([0-9.eE+]+)", txt)
-    m_shape = re.search(r"launch shape: lanes (\d+) block (\d+)", txt)
-    if not m_hash or not m_bytes or not m_shape:
+    if not m_hash:
         return None
-    if (int(m_shape.group(1)), int(m_shape.group(2))) != shape:
-        return None  # counters were taken for another variant of the kernel
     digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    return float(m_bytes.group(1)) if digest == m_hash.group(1) else None
+    if digest != m_hash.group(1):
+        return None  # counters were taken for an older kernel
+    for m in re.finditer(r"traffic: lanes (\d+) block (\d+) cell_div (\d+) bytes ([0-9.eE+]+)", txt):
+        if tuple(int(m.group(k)) for k in (1, 2, 3)) == shape:
+            return float(m.group(4))
+    return None
+
+
+# launch shapes whose pass traffic the counter sweep measures: cell subdivision
+# outermost, then lanes, then workgroup size (the order the summary relies on)
+SWEEP_SHAPES = [(lanes, block, 2, cell_div) for cell_div in (1, 2, 3)
+                for lanes in (1, 2, 4) for block in (64, 128, 256)]
+
+
+def traffic_sweep(problems, prec):
+    """Run the workload briefly in every launch shape of SWEEP_SHAPES, one after
+    the other in one process, for a hardware-counter run of the profiler."""
+    for i, shape in enumerate(SWEEP_SHAPES):
+        log(f"sweep leg {i}: lanes {shape[0]} block {shape[1]} cell_div {shape[3]}")
+        run_leg(problems, prec, 10, 3, 0, shape)
+    print(json.dumps({"traffic_sweep": [dict(lanes=s[0], block=s[1], cell_div=s[3]) for s in SWEEP_SHAPES]}))
 
 
 def cpu_baseline(prob, budget_s=12.0, max_steps=400):
@@ -140,6 +157,9 @@ def main():
     ap.add_argument("--timing-every", type=int, default=4, metavar="N",
                     help="HIP events around every N-th pair-pass launch in the timed region (each "
                          "event record costs host time; sampling keeps it off the step time)")
+    ap.add_argument("--traffic-sweep", action="store_true",
+                    help="only run the workload for 3+10 steps in each launch shape of a fixed list, "
+                         "for the HBM byte counters of a profiler")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise copy of MIB MiB (float32) five times, for "
                          "scaling the HBM byte counters of a profiler; prints its bytes")
@@ -176,6 +196,9 @@ def main():
 
     log(f"main leg {args.config} {args.precision}: {n_particles} particles, "
         f"{args.warmup} warmup + {args.steps} timed steps")
+    if args.traffic_sweep:
+        traffic_sweep(problems, prec)
+        return
     shape = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
     main_leg = run_leg(problems, prec, args.steps, args.warmup, 0 if args.no_timing else args.timing_every, shape)
     evals = pair_evals(main_leg["reports"])
@@ -193,7 +216,8 @@ def main():
         achieved = flop / (tm["pass_ms"] * 1e-3) / 1e12
         peak = PEAK_TFLOPS[dtype]
         src = os.path.join(ROOT, "paper_1904_00861_amd", "csrc", "dtsph_pass.hip")
-        tr = traffic_from_profile(src, (main_leg["tune"]["lanes"], main_leg["tune"]["block"])) \
+        tr = traffic_from_profile(src, (main_leg["tune"]["lanes"], main_leg["tune"]["block"],
+                                        main_leg["tune"]["cell_div"])) \
             if (args.config == "C1" and dtype == "f32") else None
         roofline = dict(bound="alu", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                         frac=round(achieved / peak, 4), traffic=tr,
