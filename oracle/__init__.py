@@ -48,6 +48,7 @@ class Params(C.Structure):
         ("pad2", C.c_int32),
         ("shift", C.c_int32), ("shift_n", C.c_int32),
         ("shift_r", C.c_double),
+        ("steady", C.c_int32), ("pad3", C.c_int32),
     ]
 
 
@@ -126,7 +127,7 @@ def params(p: dict) -> Params:
         elif name == "periodic":
             getattr(s, name)[:] = [int(t) for t in val]
         elif name in ("dim", "max_iter", "stall_window", "conv_norm", "edac_reg_literal",
-                      "edac_rho_literal", "shift", "shift_n"):
+                      "edac_rho_literal", "shift", "shift_n", "steady"):
             setattr(s, name, int(val))
         else:
             setattr(s, name, float(val))
@@ -227,8 +228,9 @@ def correct(prm: dict, nf: int, nw: int, x, v, v_prev, p, v_iter, p_iter):
 
 def step(prm: dict, nf: int, nw: int, x, v, v_prev, p, n_steps: int = 1, fixed_iters: int = 0):
     """Advance n_steps real steps (Algorithm 2; particle shifting after each
-    corrector when prm["shift"] is 1). Returns
-    (x, v, v_prev, p, reports, status)."""
+    corrector when prm["shift"] is 1). With prm["steady"] = 1 each step is one
+    run of the steady-state pseudo-time loop from the current state (sections
+    2.3 and 3.3), particles fixed. Returns (x, v, v_prev, p, reports, status)."""
     n = nf + nw
     x, v = _f64(x, (n, 3)).copy(), _f64(v, (n, 3)).copy()
     vp, p = _f64(v_prev, (n, 3)).copy(), _f64(p, (n,)).copy()

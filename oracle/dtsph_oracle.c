@@ -44,6 +44,16 @@
  *            (grad phi)_i = sum_j V_j (phi_j - phi_i) gradW_ij over fluid
  *            neighbours and corrects V^{n+1} and p^{n+1} (the stored V^n of the
  *            time history is left as it is); all sums see the unshifted state.
+ *  R-steady  steady-state solve (sections 2.3 and 3.3): the pressure rate is
+ *            eq. dp-dtau-frozen (no EDAC term), the momentum rate eq.
+ *            mom-steady: no real-time term, plus minus the convective sum
+ *            sum_j (V_i . gradW_ij)(V_i m_i/rho_i + V_j m_j/rho_j) (a wall
+ *            gives its ghost velocity, as in the viscous term); the pseudo-time
+ *            integrator is the frozen one; particles never move. A real step
+ *            becomes one run of the pseudo-time loop from the current state,
+ *            started with the steady pressure rate there, whose result is
+ *            committed as the new state (V^{n-1} <- V^n, V^n <- V^K); eq. conv
+ *            is applied with the configured dt.
  */
 #include <math.h>
 #include <stdint.h>
@@ -74,6 +84,8 @@ typedef struct {
     int32_t pad2;
     int32_t shift, shift_n; /* particle shifting on/off and the exponent n (R-shift) */
     double shift_r;         /* R of the shifting coefficient (R-shift)              */
+    int32_t steady;         /* steady-state solve (R-steady)                        */
+    int32_t pad3;
 } or_params;
 
 typedef struct {
@@ -363,9 +375,11 @@ static void wall_pass(const or_params *P, int nf, int nw, const double *x, const
 }
 
 /* ---- rates of one fluid particle -----------------------------------------------
- * D_i: eq. dp-dtau-frozen-edac (EDAC pressure rate, R-edac).
+ * D_i: eq. dp-dtau-frozen-edac (EDAC pressure rate, R-edac); for a steady solve
+ *      eq. dp-dtau-frozen (R-steady).
  * R_i: right side of eq. mom-sph-frozen (pressure gradient with artificial
- *      viscosity eq. mom-av / eq. av-phiij, Morris viscous term, body force).
+ *      viscosity eq. mom-av / eq. av-phiij, Morris viscous term, body force);
+ *      for a steady solve also minus the convective sum of eq. mom-steady.
  * vdiv: velocity used in the divergence term; vvis: velocity in the viscous
  * and artificial-viscosity terms; pall: pressure of every particle.          */
 static void rates_one(const or_params *P, int i, const double *x, const double *vdiv,
@@ -390,10 +404,12 @@ static void rates_one(const or_params *P, int i, const double *x, const double *
         D += mj * rhoi / rhoj * c2 * (vd[0] * gw[0] + vd[1] * gw[1] + vd[2] * gw[2]);
 
         /* EDAC diffusion: 4 m_j/(rho_i+rho_j) nu_e p_ij grad W . r_ij / (r^2 + eta h^2) */
-        double dreg = P->edac_reg_literal ? r2 + h * h : r2 + P->eta * h * h;
-        double ecoef = 4.0 * mj / (rhoi + rhoj);
-        if (P->edac_rho_literal) ecoef /= rhoj;
-        D += ecoef * nue * (pall[i] - pall[j]) * gw_r / dreg;
+        if (!P->steady) {
+            double dreg = P->edac_reg_literal ? r2 + h * h : r2 + P->eta * h * h;
+            double ecoef = 4.0 * mj / (rhoi + rhoj);
+            if (P->edac_rho_literal) ecoef /= rhoj;
+            D += ecoef * nue * (pall[i] - pall[j]) * gw_r / dreg;
+        }
 
         /* momentum: -m_j (p_i/rho_i^2 + p_j/rho_j^2 + Pi_ij) grad W
          *           + m_j 4 nu (grad W . r_ij) / ((rho_i+rho_j)(r^2 + eta h^2)) V_ij */
@@ -408,6 +424,12 @@ static void rates_one(const or_params *P, int i, const double *x, const double *
         double pterm = pall[i] / (rhoi * rhoi) + pall[j] / (rhoj * rhoj) + Pi;
         double vcoef = mj * 4.0 * P->nu * gw_r / ((rhoi + rhoj) * (r2 + P->eta * h * h));
         for (int a = 0; a < 3; ++a) R[a] += -mj * pterm * gw[a] + vcoef * vv[a];
+        if (P->steady) {
+            /* eq. mom-steady: - (V_i . grad W_ij) (V_i m_i/rho_i + V_j m_j/rho_j) */
+            const double *Vi = vvis + 3 * i, *Vj = vvis + 3 * j;
+            double s = Vi[0] * gw[0] + Vi[1] * gw[1] + Vi[2] * gw[2];
+            for (int a = 0; a < 3; ++a) R[a] -= s * (Vi[a] * P->mass / rhoi + Vj[a] * mj / rhoj);
+        }
     }
     for (int a = 0; a < 3; ++a) Ri[a] = a < P->dim ? R[a] + P->g[a] : 0.0;
     *Di = D;
@@ -535,7 +557,8 @@ int or_pseudo_loop(const or_params *P, int nf, int nw, const double *x0, const d
     nlist L;
     build_nlist(P, nf, nw, x0, method, &L);
     const double dt = P->dt, dtau = pseudo_dt(P), c = sound(P);
-    const double gamma = 2.0 * dt / (2.0 * dt + 3.0 * dtau);
+    /* frozen eq. dv_dtau_exact; a steady solve has no real-time term (R-steady) */
+    const double gamma = P->steady ? 1.0 : 2.0 * dt / (2.0 * dt + 3.0 * dtau);
     int cap = fixed_iters > 0 ? fixed_iters : (P->max_iter > 0 ? P->max_iter : 1);
     double *hp = (double *)malloc(sizeof(double) * (size_t)cap);
     double *hv = (double *)malloc(sizeof(double) * (size_t)cap);
@@ -564,7 +587,8 @@ int or_pseudo_loop(const or_params *P, int nf, int nw, const double *x0, const d
         for (int i = 0; i < nf; ++i) {
             double nv = 0.0;
             for (int a = 0; a < 3; ++a) {
-                double bdf = (3.0 * vk[3 * i + a] - 4.0 * vn[3 * i + a] + vnm1[3 * i + a]) / (2.0 * dt);
+                double bdf = P->steady ? 0.0
+                                       : (3.0 * vk[3 * i + a] - 4.0 * vn[3 * i + a] + vnm1[3 * i + a]) / (2.0 * dt);
                 double dvdtau = (R[3 * i + a] - bdf) * gamma;
                 vk[3 * i + a] += dtau * dvdtau;
                 double t = dt * dvdtau; /* eq. vtilde */
@@ -696,7 +720,35 @@ void or_shift(const or_params *P, int nf, int nw, double *x, double *v, double *
     nlist_free(&L);
 }
 
-/* ---- one or more real steps (Algorithm 2; shifting when P->shift) ------------- */
+/* ---- steady-state segment (sections 2.3 and 3.3; R-steady) -------------------
+ * D^0 is the steady pressure rate at (x, V, p); the pseudo-time loop runs from
+ * there with the particles fixed; V^{n-1} <- V^n, V^n <- V^K, p <- p^K.       */
+int or_steady_segment(const or_params *P, int nf, int nw, const double *x, double *v, double *v_prev,
+                      double *p, int fixed_iters, or_report *rep)
+{
+    int n = nf + nw;
+    size_t b3 = sizeof(double) * (3 * (size_t)n + 3), b1 = sizeof(double) * ((size_t)n + 1);
+    double *vk = (double *)malloc(b3), *R = (double *)calloc(1, b3);
+    double *pk = (double *)malloc(b1), *dk = (double *)calloc(1, b1), *pw = (double *)calloc(1, b1);
+    or_rates(P, nf, nw, x, v, p, 1, dk, R, pw, NULL);
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) vk[3 * i + a] = v[3 * i + a];
+        pk[i] = i < nf ? p[i] : pw[i];
+        if (i >= nf) dk[i] = 0.0;
+    }
+    int st = or_pseudo_loop(P, nf, nw, x, v, v_prev, vk, pk, dk, fixed_iters, 1, rep);
+    for (int i = 0; i < nf; ++i)
+        for (int a = 0; a < 3; ++a) {
+            v_prev[3 * i + a] = v[3 * i + a];
+            v[3 * i + a] = vk[3 * i + a];
+        }
+    for (int i = 0; i < n; ++i) p[i] = pk[i];
+    free(vk); free(R); free(pk); free(dk); free(pw);
+    return st;
+}
+
+/* ---- one or more real steps (Algorithm 2; shifting when P->shift; a steady
+ *      solve when P->steady) --------------------------------------------------- */
 int or_step(const or_params *P, int nf, int nw, double *x, double *v, double *v_prev,
             double *p, int n_steps, int fixed_iters, or_report *reps)
 {
@@ -705,6 +757,12 @@ int or_step(const or_params *P, int nf, int nw, double *x, double *v, double *v_
     double *x0 = (double *)malloc(b3), *v0 = (double *)malloc(b3);
     double *p0 = (double *)malloc(b1), *d0 = (double *)malloc(b1);
     for (int s = 0; s < n_steps; ++s) {
+        if (P->steady) { /* R-steady: one loop from the current state, particles fixed */
+            int st = or_steady_segment(P, nf, nw, x, v, v_prev, p, fixed_iters, reps ? reps + s : NULL);
+            if (st < 0) { status = st; break; }
+            if (st > 0) status = st;
+            continue;
+        }
         or_predict(P, nf, nw, x, v, p, x0, v0, p0, d0, NULL);
         int st = or_pseudo_loop(P, nf, nw, x0, v, v_prev, v0, p0, d0, fixed_iters, 1,
                                 reps ? reps + s : NULL);
@@ -743,7 +801,7 @@ void or_rows(const or_params *P, int nf, int nw, int mode, const double *x, cons
 {
     int n = nf + nw;
     const double dt = P->dt, dtau = pseudo_dt(P);
-    const double gamma = 2.0 * dt / (2.0 * dt + 3.0 * dtau);
+    const double gamma = P->steady ? 1.0 : 2.0 * dt / (2.0 * dt + 3.0 * dtau);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int r = 0; r < nrows; ++r) {
         int i = rows[r];
@@ -801,7 +859,8 @@ void or_rows(const or_params *P, int nf, int nw, int mode, const double *x, cons
             if (mode == 0) {
                 v_out[3 * r + a] = vk[3 * i + a] + dt * R[a];
             } else {
-                double bdf = (3.0 * vk[3 * i + a] - 4.0 * vn[3 * i + a] + vnm1[3 * i + a]) / (2.0 * dt);
+                double bdf = P->steady ? 0.0
+                                       : (3.0 * vk[3 * i + a] - 4.0 * vn[3 * i + a] + vnm1[3 * i + a]) / (2.0 * dt);
                 v_out[3 * r + a] = vk[3 * i + a] + dtau * (R[a] - bdf) * gamma;
             }
         }

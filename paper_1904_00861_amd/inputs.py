@@ -62,6 +62,7 @@ BASE_PARAMS = dict(
     shift=0,            # particle shifting after the corrector (section 3.5): 0 off, 1 on
     shift_r=1.0,        # shifting coefficient 1 + shift_r * (W / W(dx))^shift_n,
     shift_n=1,          # dx = h; the printed form is R = n = 1
+    steady=0,           # 1: steady-state solve (sections 2.3, 3.3), particles never move
 )
 
 CFL = 0.25  # dt * V_ref = C * h with C = 0.25
@@ -174,10 +175,11 @@ def _wall_box(nx, ny, dx, layers, x_ext, y_ext, open_top):
 
 
 def cavity(n: int = 50, re: float = 100.0, lid: float = 1.0, beta: float = 10.0,
-           tol: float = 1e-4, layers: int = 3, name: str = None) -> Problem:
+           tol: float = 1e-4, layers: int = 3, name: str = None, steady: bool = False) -> Problem:
     """Lid-driven cavity: n x n fluid in the unit box, wall layers all around.
 
-    The top wall layers (full width, corners included) move at u = lid.
+    The top wall layers (full width, corners included) move at u = lid. With
+    steady=True the sim is solved for its steady state (particles fixed).
     """
     dx = 1.0 / n
     h = dx
@@ -194,8 +196,37 @@ def cavity(n: int = 50, re: float = 100.0, lid: float = 1.0, beta: float = 10.0,
     lo = (-layers * dx - kh, -layers * dx - kh, 0.0)
     hi = (1 + layers * dx + kh, 1 + layers * dx + kh, 1.0)
     prm = _params(dim=2, h=h, rho0=1.0, mass=dx * dx, vref=lid, beta=beta, nu=nu, dt=dt,
-                  tol=tol, lo=lo, hi=hi, periodic=(0, 0, 0))
-    return Problem(name or f"cavity_{n}", prm, x, v, np.zeros_like(x), p, nf, nw)
+                  tol=tol, lo=lo, hi=hi, periodic=(0, 0, 0), steady=1 if steady else 0)
+    return Problem(name or f"cavity{'_steady' if steady else ''}_{n}", prm, x, v, np.zeros_like(x), p, nf, nw)
+
+
+def poiseuille(ny: int = 20, nx: int = 8, nu: float = 1.0, g: float = 1.0, beta: float = 10.0,
+               layers: int = 3, steady: bool = True, dtau: float = None, name: str = None) -> Problem:
+    """Plane channel of height 1 between two walls (y < 0 and y > 1), periodic in
+    x over nx columns, driven by a body force g along x, fluid at rest. Its
+    steady state is u(y) = g y (1 - y) / (2 nu). The pseudo step defaults to a
+    tenth of the viscous limit h^2 / nu."""
+    dx = 1.0 / ny
+    h = dx
+    xs = (np.arange(nx) + 0.5) * dx
+    ys = (np.arange(-layers, ny + layers) + 0.5) * dx
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    pts = np.zeros((X.size, 3))
+    pts[:, 0], pts[:, 1] = X.ravel(), Y.ravel()
+    is_fluid = (pts[:, 1] > 0.0) & (pts[:, 1] < 1.0)
+    fluid, walls = pts[is_fluid], pts[~is_fluid]
+    x = np.concatenate([fluid, walls])
+    nf, nw = fluid.shape[0], walls.shape[0]
+    vref = g / (8.0 * nu) if g > 0 else 1.0  # centre-line speed
+    dt = CFL * h / vref
+    kh = 3.0 * h
+    lo = (0.0, -layers * dx - kh, 0.0)
+    hi = (nx * dx, 1.0 + layers * dx + kh, 1.0)
+    prm = _params(dim=2, h=h, rho0=1.0, mass=dx * dx, vref=vref, beta=beta, nu=nu, dt=dt,
+                  dtau=dtau if dtau is not None else 0.1 * h * h / nu, g=(g, 0.0, 0.0),
+                  tol=1e-8, lo=lo, hi=hi, periodic=(1, 0, 0), steady=1 if steady else 0)
+    z = np.zeros_like(x)
+    return Problem(name or f"poiseuille_{ny}", prm, x, z.copy(), z.copy(), np.zeros(x.shape[0]), nf, nw)
 
 
 def dam_break(dx: float = 0.002, width: float = 1.0, height: float = 2.0, tank: float = 4.0,
