@@ -30,6 +30,8 @@ if ROOT not in sys.path:
 # Algorithmic floating-point work of one neighbour pair in the pass kernel
 # (FMA = 2): 50 in 2D, 60 in 3D (count in the pass kernel's formula).
 FLOP_PER_PAIR = {2: 50, 3: 60}
+# with the convective sum of the steady-state solve: + 12 in 2D, + 18 in 3D
+FLOP_PER_PAIR_CONV = {2: 62, 3: 78}
 # FP32 vector peak without packed instructions: 256 CU x 4 SIMD x 16 lanes x
 # 2.4 GHz x 2 (FMA) = 78.6 TFLOP/s; FP64 vector: 78.6 TFLOP/s.
 PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
@@ -123,6 +125,46 @@ def traffic_sweep(problems, prec):
         log(f"sweep leg {i}: lanes {shape[0]} block {shape[1]} cell_div {shape[3]}")
         run_leg(problems, prec, 10, 3, 0, shape)
     print(json.dumps({"traffic_sweep": [dict(lanes=s[0], block=s[1], cell_div=s[3]) for s in SWEEP_SHAPES]}))
+
+
+def steady_leg(n=150, segments=5, iters=100, timing_every=4):
+    """Steady lid-driven cavity (sections 2.3, 3.3; Re 100, n x n particles):
+    segments of a fixed number of pseudo-iterations, particles fixed."""
+    import torch
+    from paper_1904_00861_amd import dtsph as D
+    from paper_1904_00861_amd import inputs as I
+
+    prob = I.cavity(n, re=100.0, steady=True)
+    sim = D.Sim(prob, precision=D.FP32)
+    tune = sim.autotune()
+    sim.predict()
+    sim.pseudo_iterate(iters)  # warm-up segment
+    sim.correct()
+    sim.set_option(D.OPT_TIMING, timing_every)
+    sim.set_option(D.OPT_RESET_TIMING, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals = 0
+    for _ in range(segments):
+        sim.predict()
+        _, rep = sim.pseudo_iterate(iters)
+        sim.correct()
+        evals += rep[0]["pairs"] * rep[0]["iters"]
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    tm = sim.timing()
+    sim.close()
+    out = dict(workload=f"steady lid-driven cavity, Re 100, {n}x{n} particles, FP32 sums, "
+                        f"{segments} segments of {iters} pseudo-iterations",
+               value=evals / secs, unit="pair-evals/s", ms_per_iteration=secs * 1e3 / (segments * iters),
+               launch_shape=dict(lanes_per_particle=tune["lanes"], block=tune["block"]))
+    if tm["pass_launches"]:
+        us = tm["pass_ms"] * 1e3 / tm["pass_launches"]
+        achieved = FLOP_PER_PAIR_CONV[2] * tm["pass_pairs"] / (tm["pass_ms"] * 1e-3) / 1e12
+        out["pass"] = dict(kernel="k_pass (pseudo-time pair pass with the convective sum)",
+                           avg_launch_us=round(us, 3), flop_per_pair=FLOP_PER_PAIR_CONV[2],
+                           achieved_tflops=round(achieved, 3), frac=round(achieved / PEAK_TFLOPS["f32"], 4))
+    return out
 
 
 def cpu_baseline(prob, budget_s=12.0, max_steps=400):
@@ -262,6 +304,8 @@ def main():
             sl = run_leg(shifted, prec, args.steps, args.warmup, 0)
             extras["with_shifting_value"] = pair_evals(sl["reports"]) / sl["seconds"]
             extras["with_shifting_ms_per_step"] = sl["seconds"] * 1e3 / args.steps
+        log("steady-state leg (lid-driven cavity)")
+        extras["steady"] = steady_leg()
     extras["iterations_per_step_mean"] = sum(iters) / len(iters)
     if tm["pass_launches"]:
         launches_all = sum(max(r["iters"] for r in step) for step in main_leg["reports"])

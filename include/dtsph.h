@@ -111,7 +111,18 @@ extern "C" {
  *                  corrector (section 3.5, eqs. shift, shift-deltar,
  *                  shift-correct; free-surface particles are not shifted)
  *   shift_r, shift_n  shifting coefficient 1 + shift_r (W_ij / W(h))^shift_n;
- *                  the printed form is shift_r = 1, shift_n = 1 (n in 1..8)  */
+ *                  the printed form is shift_r = 1, shift_n = 1 (n in 1..8)
+ *   steady         1: steady-state solve (sections 2.3 and 3.3): pressure rate
+ *                  eq. dp-dtau-frozen (no EDAC term), momentum eq. mom-steady
+ *                  (no real-time term; minus the convective sum
+ *                  sum_j (V_i . gradW_ij)(V_i + V_j) m/rho, a wall giving its
+ *                  ghost velocity); particles never move. A real step
+ *                  (dtsph_step, or predict / pseudo_iterate / correct) is then
+ *                  one run of the pseudo-time loop from the current state,
+ *                  started with the steady pressure rate there, whose end state
+ *                  becomes the new state (V^{n-1} <- V^n, V^n <- V^K, p <- p^K);
+ *                  eq. conv uses dt as given. Needs shift = 0. Steady and
+ *                  time-accurate sims may share a context.                  */
 typedef struct dtsph_sim_desc {
     int32_t dim;
     int32_t max_neighbors;
@@ -131,6 +142,7 @@ typedef struct dtsph_sim_desc {
     int32_t periodic[3], reserved1;
     int32_t shift, shift_n;
     double shift_r;
+    int32_t steady, reserved2;
 } dtsph_sim_desc;
 
 /* ---- state views (device pointers, caller order, n = all particles) -----

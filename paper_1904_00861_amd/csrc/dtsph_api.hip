@@ -165,6 +165,8 @@ void check_desc(const dtsph_sim_desc &d, int s, int64_t nf, int64_t nw)
     if (d.shift != 0 && d.shift != 1) bad("shift must be 0 or 1");
     if (d.shift && (d.shift_n < 1 || d.shift_n > 8)) bad("shift_n must be in [1, 8]");
     if (d.shift && !(d.shift_r >= 0 && std::isfinite(d.shift_r))) bad("shift_r must be finite and >= 0");
+    if (d.steady != 0 && d.steady != 1) bad("steady must be 0 or 1");
+    if (d.steady && d.shift) bad("a steady solve keeps its particles fixed: shift must be 0");
     for (int a = 0; a < d.dim; ++a) {
         if (!(d.hi[a] > d.lo[a])) bad("hi must exceed lo on every axis");
         if (d.periodic[a] && !(d.kappa * d.h < 0.5 * (d.hi[a] - d.lo[a])))
@@ -280,6 +282,15 @@ SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
     S.k_grad = -(m / (rho * rho)) * S.kg;
     S.k_visc = 4.0 * m * d.nu / (2.0 * rho) * S.kg;
     S.k_av = -d.alpha * d.h * S.c * rho;                 // rho^2 Pi = k_av * min(phi, 0)
+    if (d.steady) {
+        // eq. dp-dtau-frozen and eq. mom-steady: no EDAC term, no real-time term,
+        // minus sum_j (V_i . gradW_ij)(V_i + V_j) m/rho with gradW = kg G r_ij
+        S.steady = 1;
+        S.k_lap = 0.0;
+        S.gamma = 1.0;
+        S.inv2dt = 0.0;
+        S.k_conv = -(m / rho) * S.kg;
+    }
     S.den_v = d.eta * d.h * d.h;
     S.den_e = d.edac_reg_literal ? d.h * d.h : d.eta * d.h * d.h;
     S.den_a = d.eps_av * d.h * d.h;
@@ -446,7 +457,8 @@ template <typename T> void do_predict(Ctx &c)
     launch_pass<T>(c, MODE_PRE, use_cand);
     c.xb ^= 1;
     c.in_loop = true;
-    c.cells_valid = false;
+    // steady sims keep their particles where they are: their lists stay exact
+    c.cells_valid = c.all_steady && c.cells_valid;
     c.cand_ok = false;
     c.records_fresh = false;
     c.p_half = false;
@@ -617,7 +629,7 @@ template <typename T> void do_correct(Ctx &c)
     if (!c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_correct: not inside a step (call dtsph_predict)");
     launch_correct<T>(c);
     c.in_loop = false;
-    c.cells_valid = false;
+    c.cells_valid = c.all_steady && c.cells_valid;
     c.cand_ok = c.cand_next;
     c.p_half = false;
     c.records_fresh = true;
@@ -825,6 +837,8 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             c.any_walls = c.any_walls || n_wall[s] > 0;
             c.any_av = c.any_av || d.alpha > 0;
             c.any_shift = c.any_shift || d.shift;
+            c.any_steady = c.any_steady || d.steady;
+            c.all_steady = c.all_steady && d.steady;
             c.sep_den = c.sep_den || S.den_e != S.den_v || (d.alpha > 0 && S.den_a != S.den_v);
             double est;
             if (d.max_neighbors > 0) {

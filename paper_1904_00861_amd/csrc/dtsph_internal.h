@@ -70,6 +70,10 @@ struct SimDev {
     // particle shifting (section 3.5): on/off, coefficient 1 + shift_r (W/W(h))^shift_n
     int shift, shift_n;
     double shift_r, vol;          // vol = m / rho0
+    // steady-state solve (sections 2.3, 3.3): no real-time term (gamma = 1,
+    // inv2dt = 0), no EDAC term (k_lap = 0), convective sum with k_conv
+    int steady, pad1;
+    double k_conv;
 };
 
 // Per-sim pseudo-time loop state (device).
@@ -103,6 +107,7 @@ struct Ctx {
     int xcd_remap = 1;
     int max_dim = 2;
     bool any_walls = false, any_av = false, sep_den = false, any_shift = false;
+    bool any_steady = false, all_steady = true;  // steady-state sims (fixed particles)
     hipStream_t stream = nullptr;
     int device = 0;
 

@@ -109,14 +109,16 @@ template <typename T> struct PassConst {
 };
 
 template <typename T> struct Acc {
-    T div = 0, lap = 0, grad[3] = {0, 0, 0}, vis[3] = {0, 0, 0};
+    T div = 0, lap = 0, grad[3] = {0, 0, 0}, vis[3] = {0, 0, 0}, conv[3] = {0, 0, 0};
 };
 
 // One neighbour's contribution. vd: V_ij for the divergence term; vv: V_ij for
 // the viscous and artificial-viscosity terms (they differ only for walls).
-template <typename T, int DIM, bool AV, bool SEPDEN>
+// CONV adds the convective sum of eq. mom-steady, (V_i . gradW)(V_i + V_j),
+// with V_j = V_i - vv (a wall's ghost velocity).
+template <typename T, int DIM, bool AV, bool SEPDEN, bool CONV>
 __device__ __forceinline__ void pair_terms(const PassConst<T> &K, const T r[3], const T vd[3], const T vv[3],
-                                           T pi, T pj, Acc<T> &acc)
+                                           const T vi[3], T pi, T pj, Acc<T> &acc)
 {
     T r2 = r[0] * r[0] + r[1] * r[1];
     if (DIM == 3) r2 += r[2] * r[2];
@@ -154,6 +156,13 @@ __device__ __forceinline__ void pair_terms(const PassConst<T> &K, const T r[3], 
     for (int d = 0; d < DIM; ++d) {
         acc.vis[d] += Fv * vv[d];
         acc.grad[d] += PG * r[d];
+    }
+    if (CONV) {
+        T dvi = vi[0] * r[0] + vi[1] * r[1];
+        if (DIM == 3) dvi += vi[2] * r[2];
+        const T sG = G * dvi;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) acc.conv[d] += sG * (T(2) * vi[d] - vv[d]);
     }
 }
 
@@ -217,7 +226,7 @@ template <typename T, int DIM, bool HEAVY> struct PassWaves {
     static constexpr int value = sizeof(T) == 4 ? (DIM == 2 ? 6 : 4) : (DIM == 2 && !HEAVY ? 5 : 4);
 };
 
-template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP>
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP, bool CONV>
 __global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(PassWaves<T, DIM, WALLS && AV && SEPDEN>::value)))
 k_pass(PassArgs<T> A)
 {
@@ -301,7 +310,7 @@ k_pass(PassArgs<T> A)
                 vd[0] = vi[0] - vj[m].x;
                 vd[1] = vi[1] - vj[m].y;
                 vd[2] = DIM == 3 ? vi[2] - vj[m].z : T(0);
-                pair_terms<T, DIM, AV, SEPDEN>(K, r, vd, vd, pi, pres<DIM>(vj[m]), acc);
+                pair_terms<T, DIM, AV, SEPDEN, CONV>(K, r, vd, vd, vi, pi, pres<DIM>(vj[m]), acc);
             }
         }
         for (; k < nfl; k += LPP) {
@@ -313,7 +322,7 @@ k_pass(PassArgs<T> A)
             vd[0] = vi[0] - vj.x;
             vd[1] = vi[1] - vj.y;
             vd[2] = DIM == 3 ? vi[2] - vj.z : T(0);
-            pair_terms<T, DIM, AV, SEPDEN>(K, r, vd, vd, pi, pres<DIM>(vj), acc);
+            pair_terms<T, DIM, AV, SEPDEN, CONV>(K, r, vd, vd, vi, pi, pres<DIM>(vj), acc);
         }
         if (WALLS) {
             for (int k = nfl + sub; k < nfl + nwl; k += LPP) {
@@ -327,7 +336,7 @@ k_pass(PassArgs<T> A)
                 vv[0] = vi[0] - gj.x;
                 vv[1] = vi[1] - gj.y;
                 vv[2] = DIM == 3 ? vi[2] - gj.z : T(0);
-                pair_terms<T, DIM, AV, SEPDEN>(K, r, vd, vv, pi, pres<DIM>(gj), acc);
+                pair_terms<T, DIM, AV, SEPDEN, CONV>(K, r, vd, vv, vi, pi, pres<DIM>(gj), acc);
             }
         }
     }
@@ -337,6 +346,7 @@ k_pass(PassArgs<T> A)
         for (int d = 0; d < DIM; ++d) {
             lane_sum(acc.grad[d], LPP);
             lane_sum(acc.vis[d], LPP);
+            if (CONV) lane_sum(acc.conv[d], LPP);
         }
     }
 
@@ -344,6 +354,8 @@ k_pass(PassArgs<T> A)
     if (owner) {
         Dv = (T)S.k_div * acc.div + (T)S.k_lap * acc.lap;
         for (int d = 0; d < DIM; ++d) R[d] = (T)S.k_grad * acc.grad[d] + (T)S.k_visc * acc.vis[d] + (T)S.g[d];
+        if (CONV)
+            for (int d = 0; d < DIM; ++d) R[d] += (T)S.k_conv * acc.conv[d];
 
         if (MODE == MODE_PSEUDO) {
             const T inv2dt = (T)S.inv2dt, gamma = (T)S.gamma, dtau = (T)S.dtau, dt = (T)S.dt;
@@ -365,7 +377,8 @@ k_pass(PassArgs<T> A)
             A.dp[i] = Dv;
             vout[i] = make_rec<T, DIM>(vnew, (T)pm);
         } else {
-            const double dt = S.dt, hdt2 = 0.5 * S.dt * S.dt;
+            // a steady solve keeps its particles where they are and starts from V^n
+            const double dt = S.steady ? 0.0 : S.dt, hdt2 = 0.5 * dt * dt;
             for (int d = 0; d < DIM; ++d) {
                 const double xv = A.x[d * N + i];
                 const double vv = (double)A.vn[d * Nf + i];
@@ -649,7 +662,7 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
     A.tickets[s] = 0u;
     const double sd = red[0], sv = red[1], md = red[2], mv = red[3], mw = red[4], np = red[5];
     int *done_out = A.done_out;
-    It.disp = 0.5 * S.dt * sqrt(mw);
+    It.disp = S.steady ? 0.0 : 0.5 * S.dt * sqrt(mw);  // steady sims never move
     It.pairs = (long long)np;
     const double pscale = S.dt / (S.rho0 * S.c * S.c);
     const double rp = sd * S.res_p, rv = sv * S.res_v;
@@ -779,7 +792,7 @@ __global__ void k_correct(int N, int Nf, const int *__restrict__ simid, const Si
         const T v0 = vn[d * Nf + i];
         const T v1 = v0 + w[d * Nf + i];
         vr[d] = v1;
-        double xv = xn[d * N + i] + 0.5 * S.dt * ((double)v0 + (double)v1);
+        double xv = S.steady ? xn[d * N + i] : xn[d * N + i] + 0.5 * S.dt * ((double)v0 + (double)v1);
         if (S.periodic[d]) {
             if (xv >= S.hi[d]) xv -= S.L[d];
             else if (xv < S.lo[d]) xv += S.L[d];
@@ -1084,17 +1097,29 @@ template <typename T> PassArgs<T> pass_args(Ctx &c, int mode, bool cand_lists)
 
 // A timed pair pass goes through hipExtLaunchKernelGGL, whose events take the
 // kernel's own start and end timestamps (no queue gaps in the interval).
+// Pseudo-iterations of a context with steady sims take the variant with the
+// convective sum (zero coefficient for the time-accurate sims).
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int LPP, bool CONV>
+void dispatch_pseudo(Ctx &c, const PassArgs<T> &a, dim3 grid)
+{
+    if (c.ext_start)
+        hipExtLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP, CONV>), grid, dim3(c.block), 0,
+                              c.stream, c.ext_start, c.ext_stop, 0, a);
+    else
+        DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP, CONV>), grid, dim3(c.block), 0,
+                     c.stream, a);
+}
+
 template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int LPP>
 void dispatch_mode(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
 {
     if (mode == MODE_PRE)
-        DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PRE, LPP>), grid, dim3(c.block), 0, c.stream, a);
-    else if (c.ext_start)
-        hipExtLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP>), grid, dim3(c.block), 0,
-                              c.stream, c.ext_start, c.ext_stop, 0, a);
+        DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PRE, LPP, false>), grid, dim3(c.block), 0, c.stream,
+                     a);
+    else if (c.any_steady)
+        dispatch_pseudo<T, DIM, WALLS, AV, SEPDEN, LPP, true>(c, a, grid);
     else
-        DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP>), grid, dim3(c.block), 0, c.stream,
-                           a);
+        dispatch_pseudo<T, DIM, WALLS, AV, SEPDEN, LPP, false>(c, a, grid);
 }
 
 template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN>
