@@ -54,11 +54,13 @@ def pair_evals(reports):
     return sum(r["pairs"] * r["iters"] for step in reports for r in step)
 
 
-def run_leg(problems, precision, steps, warmup, timing_every, shape=None):
+def run_leg(problems, precision, steps, warmup, timing_every, shape=None, pair_cache=0):
     import torch
     from paper_1904_00861_amd import dtsph as D
 
     sim = D.Sim(problems, precision=precision)
+    if pair_cache:
+        sim.set_option(D.OPT_PAIR_CACHE, pair_cache)
     if shape:  # fixed launch configuration instead of the autotuner
         lanes, block, nbr_lanes, cell_div = shape
         sim.set_option(D.OPT_LANES, lanes)
@@ -127,7 +129,7 @@ def traffic_sweep(problems, prec):
     print(json.dumps({"traffic_sweep": [dict(lanes=s[0], block=s[1], cell_div=s[3]) for s in SWEEP_SHAPES]}))
 
 
-def steady_leg(n=150, segments=5, iters=100, timing_every=4):
+def steady_leg(n=150, segments=5, iters=100, timing_every=4, pair_cache=0):
     """Steady lid-driven cavity (sections 2.3, 3.3; Re 100, n x n particles):
     segments of a fixed number of pseudo-iterations, particles fixed."""
     import torch
@@ -137,6 +139,8 @@ def steady_leg(n=150, segments=5, iters=100, timing_every=4):
     prob = I.cavity(n, re=100.0, steady=True)
     sim = D.Sim(prob, precision=D.FP32)
     tune = sim.autotune()
+    if pair_cache:
+        sim.set_option(D.OPT_PAIR_CACHE, pair_cache)
     sim.predict()
     sim.pseudo_iterate(iters)  # warm-up segment
     sim.correct()
@@ -155,7 +159,8 @@ def steady_leg(n=150, segments=5, iters=100, timing_every=4):
     tm = sim.timing()
     sim.close()
     out = dict(workload=f"steady lid-driven cavity, Re 100, {n}x{n} particles, FP32 sums, "
-                        f"{segments} segments of {iters} pseudo-iterations",
+                        f"{segments} segments of {iters} pseudo-iterations" +
+                        (", cached pair coefficients" if pair_cache else ""),
                value=evals / secs, unit="pair-evals/s", ms_per_iteration=secs * 1e3 / (segments * iters),
                launch_shape=dict(lanes_per_particle=tune["lanes"], block=tune["block"]))
     if tm["pass_launches"]:
@@ -199,6 +204,8 @@ def main():
     ap.add_argument("--timing-every", type=int, default=4, metavar="N",
                     help="HIP events around every N-th pair-pass launch in the timed region (each "
                          "event record costs host time; sampling keeps it off the step time)")
+    ap.add_argument("--pair-cache", type=int, default=0, choices=[0, 1, 2],
+                    help="cached pair coefficients in the main leg: 0 off, 1 on, 2 automatic")
     ap.add_argument("--traffic-sweep", action="store_true",
                     help="only run the workload for 3+10 steps in each launch shape of a fixed list, "
                          "for the HBM byte counters of a profiler")
@@ -242,7 +249,8 @@ def main():
         traffic_sweep(problems, prec)
         return
     shape = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
-    main_leg = run_leg(problems, prec, args.steps, args.warmup, 0 if args.no_timing else args.timing_every, shape)
+    main_leg = run_leg(problems, prec, args.steps, args.warmup, 0 if args.no_timing else args.timing_every, shape,
+                       args.pair_cache)
     evals = pair_evals(main_leg["reports"])
     secs = main_leg["seconds"]
     value = evals / secs
@@ -306,6 +314,7 @@ def main():
             extras["with_shifting_ms_per_step"] = sl["seconds"] * 1e3 / args.steps
         log("steady-state leg (lid-driven cavity)")
         extras["steady"] = steady_leg()
+        extras["steady_pair_cache"] = steady_leg(pair_cache=1)
     extras["iterations_per_step_mean"] = sum(iters) / len(iters)
     if tm["pass_launches"]:
         launches_all = sum(max(r["iters"] for r in step) for step in main_leg["reports"])
@@ -331,7 +340,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "particles": n_particles,
                    "particle_shifting": bool(any(p.params.get("shift", 0) for p in problems)),
-                   "pair_sums": args.precision,
+                   "pair_sums": args.precision, "pair_cache": args.pair_cache,
                    "positions_pressure_residuals": "f64"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -318,6 +318,29 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
                                   launches, which measured faster on MI355X
                                   for every workload here. Steps with a timed
                                   pair-pass launch run plainly.               */
+#define DTSPH_OPT_PAIR_CACHE 11 /* cached pair coefficients (the paper's
+                                  suggestion in the performance part of
+                                  section 4): the first pseudo-iteration of a
+                                  loop stores {G r_ij, F_ij} per neighbour-list
+                                  entry (with artificial viscosity also
+                                  r_ij / (r^2 + eps h^2)) and later iterations
+                                  read them instead of the positions; a context
+                                  of steady sims keeps them from loop to loop.
+                                  0 (default): recompute; 1: always; 2: when
+                                  the loop is expected to run >= 3 iterations
+                                  (the previous loop's count or the fixed
+                                  count) and the last loop's pairs need at most
+                                  32 MiB of coefficients (streaming them from
+                                  HBM is slower than recomputing; they pay
+                                  only while they stay in the last-level
+                                  cache). Results equal recomputation to
+                                  rounding. Contexts whose EDAC or artificial-
+                                  viscosity regulariser differs from eta h^2
+                                  recompute. Enabling allocates cap x n
+                                  entries of 16 B in FP32, 32 B in FP64 (with
+                                  artificial viscosity 8 / 16 B more in 2D,
+                                  16 / 32 B in 3D), which adds to
+                                  dtsph_workspace_bytes; between steps only. */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the pair pass's launch shape. Between steps only (EINVAL in

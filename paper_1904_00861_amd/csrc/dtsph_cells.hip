@@ -730,6 +730,7 @@ void launch_nbr_lists(Ctx &c, bool filter)
     a.x = c.x[c.xb]; a.simid = c.simid[c.buf]; a.sims = c.sims; a.cell_start = c.cell_start;
     a.nbr = c.nbr; a.cnt = c.cnt; a.prec = c.prec; a.flags = c.flags;
     a.capc = c.capc; a.cand = c.cand; a.ccnt = c.ccnt; a.xr = c.xr;
+    c.coef_valid = false;  // cached pair coefficients belong to the old lists
     launch_grouped<T>(c, a, filter);
     DTSPH_HIP_CHECK(hipGetLastError());
 }

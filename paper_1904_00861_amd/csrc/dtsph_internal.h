@@ -108,6 +108,12 @@ struct Ctx {
     int max_dim = 2;
     bool any_walls = false, any_av = false, sep_den = false, any_shift = false;
     bool any_steady = false, all_steady = true;  // steady-state sims (fixed particles)
+    // cached pair coefficients (DTSPH_OPT_PAIR_CACHE): 0 off, 1 on, 2 automatic;
+    // cache_phase of the next pseudo-iteration launch: 0 none, 1 write, 2 read
+    int pair_cache = 0, cache_phase = 0;
+    bool loop_cached = false;
+    bool coef_valid = false;  // coef holds the coefficients of the current lists
+    void *coef = nullptr, *coef_av = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
 

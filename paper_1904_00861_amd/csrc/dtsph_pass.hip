@@ -108,6 +108,11 @@ template <typename T> struct PassConst {
           den_a((T)S.den_a), k_av((T)S.k_av) {}
 };
 
+// Cached artificial-viscosity factor per list entry: r_ij / (r^2 + eps h^2).
+template <typename T, int DIM> struct AvC { using type = typename V4<T>::type; };
+template <> struct AvC<float, 2> { using type = float2; };
+template <> struct AvC<double, 2> { using type = double2; };
+
 template <typename T> struct Acc {
     T div = 0, lap = 0, grad[3] = {0, 0, 0}, vis[3] = {0, 0, 0}, conv[3] = {0, 0, 0};
 };
@@ -116,9 +121,14 @@ template <typename T> struct Acc {
 // the viscous and artificial-viscosity terms (they differ only for walls).
 // CONV adds the convective sum of eq. mom-steady, (V_i . gradW)(V_i + V_j),
 // with V_j = V_i - vv (a wall's ghost velocity).
-template <typename T, int DIM, bool AV, bool SEPDEN, bool CONV>
+// With CACHE_OUT the pair's geometric coefficients {G r_ij, F_ij} (see
+// pair_cached) are stored at `out`, with artificial viscosity also
+// r_ij / (r^2 + eps h^2) at `out_av`.
+template <typename T, int DIM, bool AV, bool SEPDEN, bool CONV, bool CACHE_OUT = false>
 __device__ __forceinline__ void pair_terms(const PassConst<T> &K, const T r[3], const T vd[3], const T vv[3],
-                                           const T vi[3], T pi, T pj, Acc<T> &acc)
+                                           const T vi[3], T pi, T pj, Acc<T> &acc,
+                                           typename V4<T>::type *out = nullptr,
+                                           typename AvC<T, DIM>::type *out_av = nullptr)
 {
     T r2 = r[0] * r[0] + r[1] * r[1];
     if (DIM == 3) r2 += r[2] * r[2];
@@ -164,6 +174,59 @@ __device__ __forceinline__ void pair_terms(const PassConst<T> &K, const T r[3], 
 #pragma unroll
         for (int d = 0; d < DIM; ++d) acc.conv[d] += sG * (T(2) * vi[d] - vv[d]);
     }
+    if (CACHE_OUT) {
+        typename V4<T>::type c;
+        c.x = G * r[0];
+        c.y = G * r[1];
+        c.z = DIM == 3 ? G * r[2] : T(0);
+        c.w = Fv;
+        *out = c;
+        if (AV) {
+            typename AvC<T, DIM>::type u;
+            u.x = r[0] * rden;
+            u.y = r[1] * rden;
+            if constexpr (DIM == 3) {
+                u.z = r[2] * rden;
+                u.w = T(0);
+            }
+            *out_av = u;
+        }
+    }
+}
+
+// One neighbour's contribution from cached coefficients (the performance part of
+// section 4 suggests caching kernel values in pseudo-time): c = {G r_ij, F_ij} with
+// kernel factor G = poly / r and F_ij = poly r / (r^2 + eta h^2). Only for
+// sims with a single regulariser (eta h^2 for the viscous, EDAC and
+// artificial-viscosity terms), where these and u = r_ij / (r^2 + eta h^2)
+// carry every geometric factor of the pass.
+template <typename T, int DIM, bool AV, bool CONV>
+__device__ __forceinline__ void pair_cached(const PassConst<T> &K, const typename V4<T>::type &c,
+                                            const typename AvC<T, DIM>::type &u, const T vd[3], const T vv[3],
+                                            const T vi[3], T pi, T pj, Acc<T> &acc)
+{
+    const T g[3] = {c.x, c.y, c.z};
+    T dotd = vd[0] * g[0] + vd[1] * g[1];
+    if (DIM == 3) dotd += vd[2] * g[2];
+    acc.div += dotd;
+    acc.lap += c.w * (pi - pj);
+    T P = pi + pj;
+    if (AV) {
+        T phi = vv[0] * u.x + vv[1] * u.y;
+        if constexpr (DIM == 3) phi += vv[2] * u.z;
+        P += K.k_av * (phi < T(0) ? phi : T(0));
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        acc.vis[d] += c.w * vv[d];
+        acc.grad[d] += P * g[d];
+    }
+    if (CONV) {
+        T sG = vi[0] * g[0] + vi[1] * g[1];
+        if (DIM == 3) sG += vi[2] * g[2];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) acc.conv[d] += sG * (T(2) * vi[d] - vv[d]);
+    }
 }
 
 __device__ inline int tile_of_block(int n_tiles, int remap)
@@ -197,6 +260,8 @@ template <typename T> struct PassArgs {
     double *x_alt, *xn;
     double4 *partials;
     double2 *partials2;   // per tile: {max |V^{k+1} - V^(0)|^2, neighbour pairs}
+    Q *coef;              // cached pair coefficients, entry k of slot i at k*N + i
+    void *coef_av;        // cached artificial-viscosity factors, same layout
 };
 
 template <typename T> __device__ inline int launch_tile(const PassArgs<T> &A, int v)
@@ -226,7 +291,10 @@ template <typename T, int DIM, bool HEAVY> struct PassWaves {
     static constexpr int value = sizeof(T) == 4 ? (DIM == 2 ? 6 : 4) : (DIM == 2 && !HEAVY ? 5 : 4);
 };
 
-template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP, bool CONV>
+// CACHE (pseudo-iterations without artificial viscosity): 0 recompute every
+// pair's geometry; 1 recompute and store {G r_ij, F_ij} per list entry (first
+// iteration of a loop); 2 read them back instead of the position records.
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP, bool CONV, int CACHE = 0>
 __global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(PassWaves<T, DIM, WALLS && AV && SEPDEN>::value)))
 k_pass(PassArgs<T> A)
 {
@@ -288,8 +356,13 @@ k_pass(PassArgs<T> A)
         const int nfl = (int)(cn & 0xffffu), nwl = (int)(cn >> 16);
         npairs = nfl + nwl;
         const int *__restrict__ nb = A.nbr + i;
+        using AvT = typename AvC<T, DIM>::type;
+        Q *__restrict__ cf = CACHE ? A.coef + i : nullptr;  // cached coefficients
+        AvT *__restrict__ cu = (CACHE && AV) ? (AvT *)A.coef_av + i : nullptr;
+        const AvT u0{};
         // fluid neighbours in batches of U: U index loads, then 2U record
-        // gathers in flight, then U pair evaluations
+        // gathers (or U coefficient loads and U gathers) in flight, then U pair
+        // evaluations
         constexpr int U = sizeof(T) == 4 ? 4 : 2;
         int k = sub;
         for (; k + (U - 1) * LPP < nfl; k += U * LPP) {
@@ -297,46 +370,73 @@ k_pass(PassArgs<T> A)
 #pragma unroll
             for (int m = 0; m < U; ++m) jj[m] = nb[(size_t)(k + m * LPP) * N];
             Rec rj[U];
-            Q vj[U];
+            Q vj[U], cc[U];
+            AvT ua[U];
 #pragma unroll
             for (int m = 0; m < U; ++m) {
-                rj[m] = prec[jj[m]];
+                if (CACHE == 2) {
+                    cc[m] = cf[(size_t)(k + m * LPP) * N];
+                    ua[m] = AV ? cu[(size_t)(k + m * LPP) * N] : u0;
+                } else {
+                    rj[m] = prec[jj[m]];
+                }
                 vj[m] = vin[jj[m]];
             }
 #pragma unroll
             for (int m = 0; m < U; ++m) {
                 T r[3], vd[3];
-                pos.delta(ri, rj[m], r);
                 vd[0] = vi[0] - vj[m].x;
                 vd[1] = vi[1] - vj[m].y;
                 vd[2] = DIM == 3 ? vi[2] - vj[m].z : T(0);
-                pair_terms<T, DIM, AV, SEPDEN, CONV>(K, r, vd, vd, vi, pi, pres<DIM>(vj[m]), acc);
+                if (CACHE == 2) {
+                    pair_cached<T, DIM, AV, CONV>(K, cc[m], ua[m], vd, vd, vi, pi, pres<DIM>(vj[m]), acc);
+                } else {
+                    pos.delta(ri, rj[m], r);
+                    const size_t e = (size_t)(k + m * LPP) * N;
+                    pair_terms<T, DIM, AV, SEPDEN, CONV, CACHE == 1>(K, r, vd, vd, vi, pi, pres<DIM>(vj[m]), acc,
+                                                                     CACHE ? cf + e : nullptr,
+                                                                     (CACHE && AV) ? cu + e : nullptr);
+                }
             }
         }
         for (; k < nfl; k += LPP) {
             const int j = nb[(size_t)k * N];
-            const Rec rj = prec[j];
             const Q vj = vin[j];
             T r[3], vd[3];
-            pos.delta(ri, rj, r);
             vd[0] = vi[0] - vj.x;
             vd[1] = vi[1] - vj.y;
             vd[2] = DIM == 3 ? vi[2] - vj.z : T(0);
-            pair_terms<T, DIM, AV, SEPDEN, CONV>(K, r, vd, vd, vi, pi, pres<DIM>(vj), acc);
+            if (CACHE == 2) {
+                pair_cached<T, DIM, AV, CONV>(K, cf[(size_t)k * N], AV ? cu[(size_t)k * N] : u0, vd, vd, vi, pi,
+                                              pres<DIM>(vj), acc);
+            } else {
+                const Rec rj = prec[j];
+                pos.delta(ri, rj, r);
+                pair_terms<T, DIM, AV, SEPDEN, CONV, CACHE == 1>(K, r, vd, vd, vi, pi, pres<DIM>(vj), acc,
+                                                                 CACHE ? cf + (size_t)k * N : nullptr,
+                                                                 (CACHE && AV) ? cu + (size_t)k * N : nullptr);
+            }
         }
         if (WALLS) {
             for (int k = nfl + sub; k < nfl + nwl; k += LPP) {
                 const int j = nb[(size_t)k * N];
-                const Rec rj = prec[j];
                 const Q gj = vin[j];  // ghost velocity and wall pressure
                 const int jw = j - Nf;
                 T r[3], vd[3], vv[3];
-                pos.delta(ri, rj, r);
                 for (int d = 0; d < 3; ++d) vd[d] = d < DIM ? vi[d] - A.vwall[d * A.Nw + jw] : T(0);
                 vv[0] = vi[0] - gj.x;
                 vv[1] = vi[1] - gj.y;
                 vv[2] = DIM == 3 ? vi[2] - gj.z : T(0);
-                pair_terms<T, DIM, AV, SEPDEN, CONV>(K, r, vd, vv, vi, pi, pres<DIM>(gj), acc);
+                if (CACHE == 2) {
+                    pair_cached<T, DIM, AV, CONV>(K, cf[(size_t)k * N], AV ? cu[(size_t)k * N] : u0, vd, vv, vi, pi,
+                                                  pres<DIM>(gj), acc);
+                } else {
+                    const Rec rj = prec[j];
+                    pos.delta(ri, rj, r);
+                    pair_terms<T, DIM, AV, SEPDEN, CONV, CACHE == 1>(K, r, vd, vv, vi, pi, pres<DIM>(gj), acc,
+                                                                     CACHE ? cf + (size_t)k * N : nullptr,
+                                                                     (CACHE && AV) ? cu + (size_t)k * N : nullptr);
+                }
             }
         }
     }
@@ -1092,6 +1192,8 @@ template <typename T> PassArgs<T> pass_args(Ctx &c, int mode, bool cand_lists)
     a.x = c.x[c.xb]; a.x_alt = c.x[c.xb ^ 1]; a.xn = c.xn[b];
     a.partials = c.partials;
     a.partials2 = c.partials2;
+    a.coef = (Q *)c.coef;
+    a.coef_av = c.coef_av;
     return a;
 }
 
@@ -1099,15 +1201,25 @@ template <typename T> PassArgs<T> pass_args(Ctx &c, int mode, bool cand_lists)
 // kernel's own start and end timestamps (no queue gaps in the interval).
 // Pseudo-iterations of a context with steady sims take the variant with the
 // convective sum (zero coefficient for the time-accurate sims).
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int LPP, bool CONV, int CACHE>
+void launch_pseudo(Ctx &c, const PassArgs<T> &a, dim3 grid)
+{
+    if (c.ext_start)
+        hipExtLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP, CONV, CACHE>), grid,
+                              dim3(c.block), 0, c.stream, c.ext_start, c.ext_stop, 0, a);
+    else
+        DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP, CONV, CACHE>), grid, dim3(c.block), 0,
+                     c.stream, a);
+}
+
+// Cached pair coefficients hold one regulariser: contexts with separate EDAC
+// or artificial-viscosity regularisers always recompute.
 template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int LPP, bool CONV>
 void dispatch_pseudo(Ctx &c, const PassArgs<T> &a, dim3 grid)
 {
-    if (c.ext_start)
-        hipExtLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP, CONV>), grid, dim3(c.block), 0,
-                              c.stream, c.ext_start, c.ext_stop, 0, a);
-    else
-        DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP, CONV>), grid, dim3(c.block), 0,
-                     c.stream, a);
+    if (SEPDEN || c.cache_phase == 0) launch_pseudo<T, DIM, WALLS, AV, SEPDEN, LPP, CONV, 0>(c, a, grid);
+    else if (c.cache_phase == 1) launch_pseudo<T, DIM, WALLS, AV, false, LPP, CONV, 1>(c, a, grid);
+    else launch_pseudo<T, DIM, WALLS, AV, false, LPP, CONV, 2>(c, a, grid);
 }
 
 template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int LPP>
