@@ -48,7 +48,7 @@ class Params(C.Structure):
         ("pad2", C.c_int32),
         ("shift", C.c_int32), ("shift_n", C.c_int32),
         ("shift_r", C.c_double),
-        ("steady", C.c_int32), ("pad3", C.c_int32),
+        ("steady", C.c_int32), ("move", C.c_int32),
     ]
 
 
@@ -95,6 +95,8 @@ def lib():
                                    P(C.c_int32), C.c_int64]
         L.or_rates.restype = C.c_int64
         L.or_rates.argtypes = [P(Params), C.c_int, C.c_int, d, d, d, C.c_int, d, d, d, d]
+        L.or_rates_vt.restype = C.c_int64
+        L.or_rates_vt.argtypes = [P(Params), C.c_int, C.c_int, d, d, d, d, C.c_int, d, d, d, d]
         L.or_predict.restype = C.c_int64
         L.or_predict.argtypes = [P(Params), C.c_int, C.c_int, d, d, d, d, d, d, d, d]
         L.or_pseudo_loop.restype = C.c_int
@@ -127,7 +129,7 @@ def params(p: dict) -> Params:
         elif name == "periodic":
             getattr(s, name)[:] = [int(t) for t in val]
         elif name in ("dim", "max_iter", "stall_window", "conv_norm", "edac_reg_literal",
-                      "edac_rho_literal", "shift", "shift_n", "steady"):
+                      "edac_rho_literal", "shift", "shift_n", "steady", "move"):
             setattr(s, name, int(val))
         else:
             setattr(s, name, float(val))
@@ -170,19 +172,23 @@ def neighbors(prm: dict, nf: int, nw: int, x, method: str = "bins"):
     return off, idx[:total]
 
 
-def rates(prm: dict, nf: int, nw: int, x, v, p, method: str = "bins"):
+def rates(prm: dict, nf: int, nw: int, x, v, p, method: str = "bins", vt=None):
     """D (pressure rate) and R (momentum right side incl. g) of every fluid particle
-    at (x, v, p), walls set by the wall pass first. Returns D[nf], R[nf,3], p_w[n],
-    ghost velocity[n,3] and the number of fluid-row pairs."""
+    at (x, v, p), walls set by the wall pass first; with vt (pseudo-time velocity
+    Vtilde per particle, (n, 3)) the advective terms of the moving-particle
+    scheme are included. Returns D[nf], R[nf,3], p_w[n], ghost velocity[n,3] and
+    the number of fluid-row pairs."""
     n = nf + nw
     x, v, p = _f64(x, (n, 3)), _f64(v, (n, 3)), _f64(p, (n,))
+    vt_arr = None if vt is None else _f64(vt, (n, 3))
+    vtp = None if vt_arr is None else _d(vt_arr)
     D = np.zeros(n + 1)
     R = np.zeros((n + 1, 3))
     pw = np.zeros(n + 1)
     vg = np.zeros((n + 1, 3))
     P = params(prm)
-    pairs = lib().or_rates(C.byref(P), nf, nw, _d(x), _d(v), _d(p), 0 if method == "brute" else 1,
-                           _d(D), _d(R), _d(pw), _d(vg))
+    pairs = lib().or_rates_vt(C.byref(P), nf, nw, _d(x), _d(v), _d(p), vtp, 0 if method == "brute" else 1,
+                              _d(D), _d(R), _d(pw), _d(vg))
     return D[:nf], R[:nf], pw[:n], vg[:n], pairs
 
 

@@ -54,6 +54,21 @@
  *            started with the steady pressure rate there, whose result is
  *            committed as the new state (V^{n-1} <- V^n, V^n <- V^K); eq. conv
  *            is applied with the configured dt.
+ *  R-move    moving particles in pseudo-time (section 2.1, section 3.1,
+ *            Algorithm 1): the rate before the loop and the predictor are those
+ *            of the frozen scheme (Vtilde^0 = 0 makes the advective terms
+ *            vanish there); iteration k evaluates the rates at r^{k+1/2} =
+ *            r^k + dtau/2 Vtilde^k with Vtilde^k in the advective terms; the
+ *            pressure's advective term is rho_i Vtilde_i . sum_j m_j (p_i/rho_i^2
+ *            + p_j/rho_j^2) gradW_ij (the printed sum is grad(p)/rho; the factor
+ *            rho_i makes it the Vtilde . grad(p) of eq. CE_material, the same
+ *            for rho = 1), the momentum's is sum_j (Vtilde_i . gradW_ij)
+ *            (V_i m_i/rho_i + V_j m_j/rho_j) with a wall's ghost velocity; then
+ *            Vtilde^{k+1} = dt (dV/dtau) (eq. vtilde) and r^{k+1} = r^{k+1/2} +
+ *            dtau/2 Vtilde^{k+1} (eq. rkp1), each half step wrapped. Walls stay.
+ *            Neighbours: move = 1 keeps the lists of r^(0) for the whole loop
+ *            (a pair leaving the support adds zero); move = 2 recomputes them at
+ *            every r^{k+1/2}. After the loop eq. r-update starts from r^n.
  */
 #include <math.h>
 #include <stdint.h>
@@ -85,7 +100,7 @@ typedef struct {
     int32_t shift, shift_n; /* particle shifting on/off and the exponent n (R-shift) */
     double shift_r;         /* R of the shifting coefficient (R-shift)              */
     int32_t steady;         /* steady-state solve (R-steady)                        */
-    int32_t pad3;
+    int32_t move;           /* 0 frozen, 1 moving, 2 moving + neighbour update (R-move) */
 } or_params;
 
 typedef struct {
@@ -384,11 +399,12 @@ static void wall_pass(const or_params *P, int nf, int nw, const double *x, const
  * and artificial-viscosity terms; pall: pressure of every particle.          */
 static void rates_one(const or_params *P, int i, const double *x, const double *vdiv,
                       const double *vvis, const double *pall, const int32_t *nb, int64_t nnb,
-                      double *Di, double Ri[3])
+                      const double *vt, double *Di, double Ri[3])
 {
     const double h = P->h, c = sound(P), c2 = c * c, nue = nu_edac(P);
     const double rhoi = P->rho0, rhoj = P->rho0, mj = P->mass;
     double D = 0.0, R[3] = {0, 0, 0};
+    const double *Vt = vt ? vt + 3 * i : NULL; /* Vtilde_i (R-move) */
     for (int64_t k = 0; k < nnb; ++k) {
         int j = nb[k];
         double d[3];
@@ -430,18 +446,27 @@ static void rates_one(const or_params *P, int i, const double *x, const double *
             double s = Vi[0] * gw[0] + Vi[1] * gw[1] + Vi[2] * gw[2];
             for (int a = 0; a < 3; ++a) R[a] -= s * (Vi[a] * P->mass / rhoi + Vj[a] * mj / rhoj);
         }
+        if (Vt) {
+            /* eq. dp-dtau, first term (R-move): rho_i Vtilde_i . m_j (p_i/rho_i^2 + p_j/rho_j^2) grad W */
+            double tg = Vt[0] * gw[0] + Vt[1] * gw[1] + Vt[2] * gw[2];
+            D += rhoi * mj * (pall[i] / (rhoi * rhoi) + pall[j] / (rhoj * rhoj)) * tg;
+            /* eq. discrete_ME, first term: (Vtilde_i . grad W)(V_i m_i/rho_i + V_j m_j/rho_j) */
+            const double *Vi = vvis + 3 * i, *Vj = vvis + 3 * j;
+            for (int a = 0; a < 3; ++a) R[a] += tg * (Vi[a] * P->mass / rhoi + Vj[a] * mj / rhoj);
+        }
     }
     for (int a = 0; a < 3; ++a) Ri[a] = a < P->dim ? R[a] + P->g[a] : 0.0;
     *Di = D;
 }
 
 static void rates(const or_params *P, int nf, const double *x, const double *vdiv,
-                  const double *vvis, const double *pall, const nlist *L, double *D, double *R)
+                  const double *vvis, const double *pall, const nlist *L, const double *vt, double *D,
+                  double *R)
 {
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < nf; ++i)
         rates_one(P, i, x, vdiv, vvis, pall, L->idx + L->off[i], L->off[i + 1] - L->off[i],
-                  D + i, R + 3 * i);
+                  vt, D + i, R + 3 * i);
 }
 
 /* Assemble the per-particle arrays the rate sums read: fluid entries from the
@@ -459,9 +484,22 @@ static void assemble(int nf, int n, const double *vk, const double *pf, const do
     }
 }
 
-/* ---- public: rates at (x, v, p) (walls handled by the wall pass first) ------ */
+/* ---- public: rates at (x, v, p) (walls handled by the wall pass first); with
+ *      vt (Vtilde per particle, may be NULL) the advective terms of eq. dp-dtau
+ *      and eq. discrete_ME are included (R-move) ---------------------------- */
+int64_t or_rates_vt(const or_params *P, int nf, int nw, const double *x, const double *v,
+                    const double *p, const double *vt, int method, double *D, double *R, double *pw_out,
+                    double *vg_out);
+
 int64_t or_rates(const or_params *P, int nf, int nw, const double *x, const double *v,
                  const double *p, int method, double *D, double *R, double *pw_out, double *vg_out)
+{
+    return or_rates_vt(P, nf, nw, x, v, p, NULL, method, D, R, pw_out, vg_out);
+}
+
+int64_t or_rates_vt(const or_params *P, int nf, int nw, const double *x, const double *v,
+                    const double *p, const double *vt, int method, double *D, double *R, double *pw_out,
+                    double *vg_out)
 {
     int n = nf + nw;
     nlist L;
@@ -473,7 +511,7 @@ int64_t or_rates(const or_params *P, int nf, int nw, const double *x, const doub
     double *pall = (double *)malloc(sizeof(double) * ((size_t)n + 1));
     wall_pass(P, nf, nw, x, v, p, &L, pw, vg);
     assemble(nf, n, v, p, v, pw, vg, vdiv, vvis, pall);
-    rates(P, nf, x, vdiv, vvis, pall, &L, D, R);
+    rates(P, nf, x, vdiv, vvis, pall, &L, vt, D, R);
     if (pw_out) memcpy(pw_out, pw, sizeof(double) * (size_t)n);
     if (vg_out) memcpy(vg_out, vg, sizeof(double) * 3 * (size_t)n);
     int64_t pairs = fluid_pairs(&L, nf);
@@ -548,7 +586,10 @@ static int stop_reason(const or_params *P, const double *hp, const double *hv, i
  * In: frozen positions x0, V^n (vn), V^{n-1} (vnm1); walls' prescribed velocity
  * in vn. In/out: V^k (vk), p^k (pk), (dp/dtau)^k (dk). On return the wall
  * entries of pk hold the last wall pressure. fixed_iters > 0 runs exactly that
- * many iterations without the stop test.                                      */
+ * many iterations without the stop test.
+ * With P->move the particles move in pseudo-time from x0 (Algorithm 1 inner
+ * loop: eqs. rkstar, pkstar, vkp1, rkp1, pkp1, vtilde with eq. dp-dtau and
+ * eq. discrete_ME; R-move); x0 itself is not changed.                        */
 int or_pseudo_loop(const or_params *P, int nf, int nw, const double *x0, const double *vn,
                    const double *vnm1, double *vk, double *pk, double *dk, int fixed_iters,
                    int method, or_report *rep)
@@ -573,16 +614,36 @@ int or_pseudo_loop(const or_params *P, int nf, int nw, const double *x0, const d
     double *D = (double *)calloc((size_t)n + 1, sizeof(double));
     double *R = (double *)calloc(3 * (size_t)n + 3, sizeof(double));
     double *vt = (double *)calloc((size_t)n + 1, sizeof(double));
+    /* moving particles (R-move): r^k, r^{k+1/2} and Vtilde^k, Vtilde^0 = 0 */
+    double *xk = NULL, *xh = NULL, *vtil = NULL;
+    if (P->move) {
+        xk = (double *)malloc(sizeof(double) * (3 * (size_t)n + 3));
+        xh = (double *)malloc(sizeof(double) * (3 * (size_t)n + 3));
+        vtil = (double *)calloc(3 * (size_t)n + 3, sizeof(double));
+        memcpy(xk, x0, sizeof(double) * 3 * (size_t)n);
+        memcpy(xh, x0, sizeof(double) * 3 * (size_t)n);
+    }
     int k = 0, reason = 0;
     while (!reason) {
         /* stage 1: p^{k+1/2} = p^k + dtau/2 (dp/dtau)^k */
         for (int i = 0; i < nf; ++i) phalf[i] = pk[i] + 0.5 * dtau * dk[i];
+        /* moving: r^{k+1/2} = r^k + dtau/2 Vtilde^k (eq. rkstar), lists there with move = 2 */
+        const double *xe = x0;
+        if (P->move) {
+            for (int i = 0; i < nf; ++i)
+                for (int a = 0; a < 3; ++a) xh[3 * i + a] = wrap(P, a, xk[3 * i + a] + 0.5 * dtau * vtil[3 * i + a]);
+            if (P->move == 2) {
+                nlist_free(&L);
+                build_nlist(P, nf, nw, xh, method, &L);
+            }
+            xe = xh;
+        }
         /* walls from (V^k, p^{k+1/2}); velocities of walls are the prescribed ones */
         for (int i = nf; i < n; ++i)
             for (int a = 0; a < 3; ++a) vk[3 * i + a] = vn[3 * i + a];
-        wall_pass(P, nf, nw, x0, vk, phalf, &L, pw, vg);
+        wall_pass(P, nf, nw, xe, vk, phalf, &L, pw, vg);
         assemble(nf, n, vk, phalf, vn, pw, vg, vdiv, vvis, pall);
-        rates(P, nf, x0, vdiv, vvis, pall, &L, D, R);
+        rates(P, nf, xe, vdiv, vvis, pall, &L, vtil, D, R);
         /* stage 2 */
         for (int i = 0; i < nf; ++i) {
             double nv = 0.0;
@@ -593,6 +654,10 @@ int or_pseudo_loop(const or_params *P, int nf, int nw, const double *x0, const d
                 vk[3 * i + a] += dtau * dvdtau;
                 double t = dt * dvdtau; /* eq. vtilde */
                 nv += t * t;
+                if (P->move) { /* eq. rkp1: r^{k+1} = r^{k+1/2} + dtau/2 Vtilde^{k+1} */
+                    vtil[3 * i + a] = t;
+                    xk[3 * i + a] = wrap(P, a, xh[3 * i + a] + 0.5 * dtau * t);
+                }
             }
             vt[i] = sqrt(nv);
             pk[i] = phalf[i] + 0.5 * dtau * D[i];
@@ -633,6 +698,7 @@ int or_pseudo_loop(const or_params *P, int nf, int nw, const double *x0, const d
     }
     free(hp); free(hv); free(hpx); free(hvx); free(phalf); free(pw); free(vg);
     free(vdiv); free(vvis); free(pall); free(D); free(R); free(vt);
+    free(xk); free(xh); free(vtil);
     nlist_free(&L);
     return reason == OR_NONFINITE ? -4 : (reason == OR_MAXITER ? 1 : 0);
 }
@@ -854,7 +920,7 @@ void or_rows(const or_params *P, int nf, int nw, int mode, const double *x, cons
             lp[e] = pj;
         }
         double D, R[3];
-        rates_one(P, 0, lx, lvd, lvv, lp, lnb + 1, nnb, &D, R);
+        rates_one(P, 0, lx, lvd, lvv, lp, lnb + 1, nnb, NULL, &D, R);
         for (int a = 0; a < 3; ++a) {
             if (mode == 0) {
                 v_out[3 * r + a] = vk[3 * i + a] + dt * R[a];

@@ -63,6 +63,8 @@ BASE_PARAMS = dict(
     shift_r=1.0,        # shifting coefficient 1 + shift_r * (W / W(dx))^shift_n,
     shift_n=1,          # dx = h; the printed form is R = n = 1
     steady=0,           # 1: steady-state solve (sections 2.3, 3.3), particles never move
+    move=0,             # particles in pseudo-time (Algorithm 1): 0 frozen, 1 moving with the
+                        # lists of r^(0), 2 moving with the lists recomputed every iteration
 )
 
 CFL = 0.25  # dt * V_ref = C * h with C = 0.25
