@@ -204,6 +204,8 @@ def main():
     ap.add_argument("--timing-every", type=int, default=4, metavar="N",
                     help="HIP events around every N-th pair-pass launch in the timed region (each "
                          "event record costs host time; sampling keeps it off the step time)")
+    ap.add_argument("--shift", type=int, default=None, choices=[0, 1],
+                    help="override the workload's particle shifting (section 3.5)")
     ap.add_argument("--pair-cache", type=int, default=0, choices=[0, 1, 2],
                     help="cached pair coefficients in the main leg: 0 off, 1 on, 2 automatic")
     ap.add_argument("--traffic-sweep", action="store_true",
@@ -240,6 +242,9 @@ def main():
     dtype = "f32" if args.precision == "fp32" else "f64"
     prob = I.config(args.config)
     problems = prob if isinstance(prob, list) else [prob]
+    if args.shift is not None:
+        for p in problems:
+            p.params = dict(p.params, shift=args.shift)
     dim = problems[0].params["dim"]
     n_particles = sum(p.n for p in problems)
 

@@ -122,7 +122,20 @@ extern "C" {
  *                  started with the steady pressure rate there, whose end state
  *                  becomes the new state (V^{n-1} <- V^n, V^n <- V^K, p <- p^K);
  *                  eq. conv uses dt as given. Needs shift = 0. Steady and
- *                  time-accurate sims may share a context.                  */
+ *                  time-accurate sims may share a context.
+ *   move           particles in pseudo-time (sections 2.1 and 3.1, Algorithm
+ *                  1): 0 frozen (Algorithm 2); 1 moving, r^{k+1/2} = r^k +
+ *                  dtau/2 Vtilde^k, r^{k+1} = r^{k+1/2} + dtau/2 Vtilde^{k+1},
+ *                  Vtilde^{k+1} = dt dV/dtau (eqs. rkstar, rkp1, vtilde), with
+ *                  the advective terms Vtilde_i . sum_j (p_i + p_j) m/rho gradW
+ *                  in the pressure rate (rho_i times the printed eq. dp-dtau
+ *                  term, which is grad(p)/rho) and sum_j (Vtilde_i . gradW_ij)
+ *                  (V_i + V_j) m/rho in the momentum rate (eq. discrete_ME),
+ *                  over the lists of r^(0); 2 as 1 with the lists recomputed at
+ *                  every r^{k+1/2} (from candidate lists: a particle moving
+ *                  more than 0.45 skin from r^(0) inside one loop raises
+ *                  EOVERFLOW). The loop's motion is discarded by eq. r-update.
+ *                  Needs steady = 0.                                      */
 typedef struct dtsph_sim_desc {
     int32_t dim;
     int32_t max_neighbors;
@@ -142,7 +155,7 @@ typedef struct dtsph_sim_desc {
     int32_t periodic[3], reserved1;
     int32_t shift, shift_n;
     double shift_r;
-    int32_t steady, reserved2;
+    int32_t steady, move;
 } dtsph_sim_desc;
 
 /* ---- state views (device pointers, caller order, n = all particles) -----

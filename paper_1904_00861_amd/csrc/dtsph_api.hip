@@ -167,6 +167,8 @@ void check_desc(const dtsph_sim_desc &d, int s, int64_t nf, int64_t nw)
     if (d.shift && !(d.shift_r >= 0 && std::isfinite(d.shift_r))) bad("shift_r must be finite and >= 0");
     if (d.steady != 0 && d.steady != 1) bad("steady must be 0 or 1");
     if (d.steady && d.shift) bad("a steady solve keeps its particles fixed: shift must be 0");
+    if (d.move < 0 || d.move > 2) bad("move must be 0, 1 or 2");
+    if (d.move && d.steady) bad("a steady solve keeps its particles fixed: move must be 0");
     for (int a = 0; a < d.dim; ++a) {
         if (!(d.hi[a] > d.lo[a])) bad("hi must exceed lo on every axis");
         if (d.periodic[a] && !(d.kappa * d.h < 0.5 * (d.hi[a] - d.lo[a])))
@@ -291,6 +293,13 @@ SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
         S.inv2dt = 0.0;
         S.k_conv = -(m / rho) * S.kg;
     }
+    if (d.move) {
+        // Algorithm 1: + sum_j (Vtilde_i . gradW_ij)(V_i + V_j) m/rho in the momentum
+        // rate, + rho_i Vtilde_i . sum_j m (p_i + p_j)/rho^2 gradW_ij in the pressure rate
+        S.move = d.move;
+        S.k_conv = (m / rho) * S.kg;
+        S.k_padv = (m / rho) * S.kg;
+    }
     S.den_v = d.eta * d.h * d.h;
     S.den_e = d.edac_reg_literal ? d.h * d.h : d.eta * d.h * d.h;
     S.den_a = d.eps_av * d.h * d.h;
@@ -347,6 +356,11 @@ template <typename T> void alloc_state(Ctx &c)
     }
     dev_alloc(c, c.prec, (sizeof(T) == 4 ? 16 : 32) * N);
     dev_alloc(c, c.xr, 32 * N);
+    if (c.any_move) {  // loop state of particles moving in pseudo-time
+        dev_alloc(c, c.prec2, (sizeof(T) == 4 ? 16 : 32) * N);
+        dev_alloc(c, c.xm, 8 * 3 * Nf);
+        dev_alloc(c, c.vt, sizeof(T) * 3 * Nf);
+    }
 }
 
 // ---- timing -------------------------------------------------------------------
@@ -383,7 +397,11 @@ void check_host_flags(Ctx &c)
     if (c.timing) resolve_timers(c);
     const int over = c.flags_host[F_NBR_OVERFLOW], need = c.flags_host[F_NBR_NEEDED];
     const int cell = c.flags_host[F_CELL_OVERFLOW], outside = c.flags_host[F_OUTSIDE];
+    const int skin = c.flags_host[F_SKIN];
     for (int k = 0; k < F_COUNT; ++k) c.flags_host[k] = 0;
+    if (skin)
+        throw ApiError(DTSPH_EOVERFLOW, "a particle moving in pseudo-time (move = 2) left the candidate-list skin "
+                                        "of its loop; lower dtau or dt");
     if (outside)
         throw ApiError(DTSPH_EINVAL, "a position on a periodic axis lies outside [lo, hi); the state was not "
                                      "accepted (set it again)");
@@ -505,12 +523,13 @@ struct LoopRun {
 constexpr int kCacheMinIters = 3;
 constexpr double kCacheMaxBytes = 32.0 * 1048576.0;
 
-bool cache_usable(const Ctx &c) { return c.coef && !c.sep_den && (!c.any_av || c.coef_av); }
+bool cache_usable(const Ctx &c) { return c.coef && !c.sep_den && !c.any_move && (!c.any_av || c.coef_av); }
 
 template <typename T> void loop_prologue(Ctx &c, int fixed, LoopRun &L)
 {
     if (!c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_pseudo_iterate: not inside a step (call dtsph_predict)");
     if (fixed < 0) throw ApiError(DTSPH_EINVAL, "fixed_iters must be >= 0");
+    if (c.any_move2) c.cand_ok = false;  // list updates filter candidates centred at r^(0)
     if (!c.cells_valid && !c.cand_ok) {
         // full build at the frozen positions, with the loop set-up in its gather
         build_cells<T>(c, fixed);
@@ -519,6 +538,7 @@ template <typename T> void loop_prologue(Ctx &c, int fixed, LoopRun &L)
         ensure_cells<T>(c);
         launch_loop_begin<T>(c, fixed);
     }
+    launch_move_begin<T>(c);
     set_active_ranges(c, true);
     c.pass_times.clear();
     L.fixed = fixed;
@@ -545,6 +565,8 @@ template <typename T> void launch_chunk(Ctx &c, LoopRun &L)
     const int n = std::min(L.chunk, L.max_it - L.launched);
     for (int k = 0; k < n; ++k) {
         c.pass_index = L.launched + k;
+        // moving sims with neighbour updates: exact lists at r^{k+1/2}
+        if (c.any_move2 && L.launched + k > 0) filter_lists<T>(c);
         launch_wall<T>(c, MODE_PSEUDO);
         // with cached coefficients the loop's first pass stores them, later ones
         // read; steady contexts keep them from loop to loop (lists and positions
@@ -863,6 +885,8 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             c.any_av = c.any_av || d.alpha > 0;
             c.any_shift = c.any_shift || d.shift;
             c.any_steady = c.any_steady || d.steady;
+            c.any_move = c.any_move || d.move;
+            c.any_move2 = c.any_move2 || d.move == 2;
             c.all_steady = c.all_steady && d.steady;
             c.sep_den = c.sep_den || S.den_e != S.den_v || (d.alpha > 0 && S.den_a != S.den_v);
             double est;

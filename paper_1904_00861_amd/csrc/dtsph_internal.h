@@ -37,7 +37,7 @@ constexpr int kSegTiles = 256;       // tiles per residual segment (one finalize
 enum PassMode { MODE_PRE = 0, MODE_PSEUDO = 1 };
 
 // Device flag words
-enum Flag { F_NBR_OVERFLOW = 0, F_NBR_NEEDED = 1, F_CELL_OVERFLOW = 2, F_OUTSIDE = 3, F_COUNT = 4 };
+enum Flag { F_NBR_OVERFLOW = 0, F_NBR_NEEDED = 1, F_CELL_OVERFLOW = 2, F_OUTSIDE = 3, F_SKIN = 4, F_COUNT = 5 };
 
 // Per-sim constants (device). Everything the kernels need, precomputed on the
 // host in float64; FP32 kernels convert once per thread.
@@ -72,8 +72,11 @@ struct SimDev {
     double shift_r, vol;          // vol = m / rho0
     // steady-state solve (sections 2.3, 3.3): no real-time term (gamma = 1,
     // inv2dt = 0), no EDAC term (k_lap = 0), convective sum with k_conv
-    int steady, pad1;
-    double k_conv;
+    int steady;
+    // moving particles in pseudo-time (Algorithm 1): 0 frozen, 1 moving, 2
+    // moving with neighbour updates; k_padv: pressure advection coefficient
+    int move;
+    double k_conv, k_padv;
 };
 
 // Per-sim pseudo-time loop state (device).
@@ -108,6 +111,10 @@ struct Ctx {
     int max_dim = 2;
     bool any_walls = false, any_av = false, sep_den = false, any_shift = false;
     bool any_steady = false, all_steady = true;  // steady-state sims (fixed particles)
+    bool any_move = false, any_move2 = false;   // sims moving in pseudo-time (any / with list updates)
+    void *prec2 = nullptr;   // second position-record buffer (moving sims ping-pong)
+    double *xm = nullptr;    // r^{k+1/2} of the fluid in the loop, float64 [3][Nf]
+    void *vt = nullptr;      // Vtilde^k of the fluid [3][Nf] (pass type)
     // cached pair coefficients (DTSPH_OPT_PAIR_CACHE): 0 off, 1 on, 2 automatic;
     // cache_phase of the next pseudo-iteration launch: 0 none, 1 write, 2 read
     int pair_cache = 0, cache_phase = 0;
@@ -256,6 +263,7 @@ template <typename T> void launch_pass(Ctx &c, int mode, bool cand_lists = false
 void launch_finalize(Ctx &c, bool publish);
 void launch_publish(Ctx &c);
 template <typename T> void launch_loop_begin(Ctx &c, int fixed_iters);
+template <typename T> void launch_move_begin(Ctx &c);
 template <typename T> void launch_correct(Ctx &c);
 template <typename T> void launch_shift(Ctx &c, bool cand_lists);  // sums, apply, max
 template <typename T> void launch_set_state(Ctx &c, const dtsph_state_view &s, bool in_loop);

@@ -114,19 +114,20 @@ template <> struct AvC<float, 2> { using type = float2; };
 template <> struct AvC<double, 2> { using type = double2; };
 
 template <typename T> struct Acc {
-    T div = 0, lap = 0, grad[3] = {0, 0, 0}, vis[3] = {0, 0, 0}, conv[3] = {0, 0, 0};
+    T div = 0, lap = 0, grad[3] = {0, 0, 0}, vis[3] = {0, 0, 0}, conv[3] = {0, 0, 0}, padv = 0;
 };
 
 // One neighbour's contribution. vd: V_ij for the divergence term; vv: V_ij for
 // the viscous and artificial-viscosity terms (they differ only for walls).
-// CONV adds the convective sum of eq. mom-steady, (V_i . gradW)(V_i + V_j),
-// with V_j = V_i - vv (a wall's ghost velocity).
+// CONV adds the advective sums (a . gradW)(V_i + V_j) and (a . gradW)(p_i + p_j)
+// with V_j = V_i - vv (a wall's ghost velocity): a = V_i for the convective
+// term of eq. mom-steady, a = Vtilde_i for eq. discrete_ME and eq. dp-dtau.
 // With CACHE_OUT the pair's geometric coefficients {G r_ij, F_ij} (see
 // pair_cached) are stored at `out`, with artificial viscosity also
 // r_ij / (r^2 + eps h^2) at `out_av`.
 template <typename T, int DIM, bool AV, bool SEPDEN, bool CONV, bool CACHE_OUT = false>
 __device__ __forceinline__ void pair_terms(const PassConst<T> &K, const T r[3], const T vd[3], const T vv[3],
-                                           const T vi[3], T pi, T pj, Acc<T> &acc,
+                                           const T vi[3], const T av[3], T pi, T pj, Acc<T> &acc,
                                            typename V4<T>::type *out = nullptr,
                                            typename AvC<T, DIM>::type *out_av = nullptr)
 {
@@ -155,6 +156,13 @@ __device__ __forceinline__ void pair_terms(const PassConst<T> &K, const T r[3], 
     acc.div += G * dotd;
     acc.lap += Fe * (pi - pj);
     T P = pi + pj;
+    T sG = 0;
+    if (CONV) {
+        T dvi = av[0] * r[0] + av[1] * r[1];
+        if (DIM == 3) dvi += av[2] * r[2];
+        sG = G * dvi;
+        acc.padv += sG * P;
+    }
     if (AV) {
         T dotv = vv[0] * r[0] + vv[1] * r[1];
         if (DIM == 3) dotv += vv[2] * r[2];
@@ -168,9 +176,6 @@ __device__ __forceinline__ void pair_terms(const PassConst<T> &K, const T r[3], 
         acc.grad[d] += PG * r[d];
     }
     if (CONV) {
-        T dvi = vi[0] * r[0] + vi[1] * r[1];
-        if (DIM == 3) dvi += vi[2] * r[2];
-        const T sG = G * dvi;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) acc.conv[d] += sG * (T(2) * vi[d] - vv[d]);
     }
@@ -203,7 +208,7 @@ __device__ __forceinline__ void pair_terms(const PassConst<T> &K, const T r[3], 
 template <typename T, int DIM, bool AV, bool CONV>
 __device__ __forceinline__ void pair_cached(const PassConst<T> &K, const typename V4<T>::type &c,
                                             const typename AvC<T, DIM>::type &u, const T vd[3], const T vv[3],
-                                            const T vi[3], T pi, T pj, Acc<T> &acc)
+                                            const T vi[3], const T av[3], T pi, T pj, Acc<T> &acc)
 {
     const T g[3] = {c.x, c.y, c.z};
     T dotd = vd[0] * g[0] + vd[1] * g[1];
@@ -211,6 +216,12 @@ __device__ __forceinline__ void pair_cached(const PassConst<T> &K, const typenam
     acc.div += dotd;
     acc.lap += c.w * (pi - pj);
     T P = pi + pj;
+    T sG = 0;
+    if (CONV) {
+        sG = av[0] * g[0] + av[1] * g[1];
+        if (DIM == 3) sG += av[2] * g[2];
+        acc.padv += sG * P;
+    }
     if (AV) {
         T phi = vv[0] * u.x + vv[1] * u.y;
         if constexpr (DIM == 3) phi += vv[2] * u.z;
@@ -222,8 +233,6 @@ __device__ __forceinline__ void pair_cached(const PassConst<T> &K, const typenam
         acc.grad[d] += P * g[d];
     }
     if (CONV) {
-        T sG = vi[0] * g[0] + vi[1] * g[1];
-        if (DIM == 3) sG += vi[2] * g[2];
 #pragma unroll
         for (int d = 0; d < DIM; ++d) acc.conv[d] += sG * (T(2) * vi[d] - vv[d]);
     }
@@ -262,6 +271,13 @@ template <typename T> struct PassArgs {
     double2 *partials2;   // per tile: {max |V^{k+1} - V^(0)|^2, neighbour pairs}
     Q *coef;              // cached pair coefficients, entry k of slot i at k*N + i
     void *coef_av;        // cached artificial-viscosity factors, same layout
+    // particles moving in pseudo-time: second position-record buffer, r^{k+1/2}
+    // and Vtilde^k of the fluid, packed positions for the list filter, flags
+    void *prec2;
+    double *xm;
+    T *vt;
+    void *xr;
+    int *flags;
 };
 
 template <typename T> __device__ inline int launch_tile(const PassArgs<T> &A, int v)
@@ -291,10 +307,13 @@ template <typename T, int DIM, bool HEAVY> struct PassWaves {
     static constexpr int value = sizeof(T) == 4 ? (DIM == 2 ? 6 : 4) : (DIM == 2 && !HEAVY ? 5 : 4);
 };
 
-// CACHE (pseudo-iterations without artificial viscosity): 0 recompute every
-// pair's geometry; 1 recompute and store {G r_ij, F_ij} per list entry (first
-// iteration of a loop); 2 read them back instead of the position records.
-template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP, bool CONV, int CACHE = 0>
+// CACHE (pseudo-iterations): 0 recompute every pair's geometry; 1 recompute and
+// store {G r_ij, F_ij} per list entry (first iteration of a loop); 2 read them
+// back instead of the position records. MOVE (with CONV): sims with particles
+// moving in pseudo-time read the position records of their iteration's parity,
+// add the advective terms with Vtilde^k and write r^{k+3/2} to the other buffer.
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP, bool CONV, int CACHE = 0,
+          bool MOVE = false>
 __global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(PassWaves<T, DIM, WALLS && AV && SEPDEN>::value)))
 k_pass(PassArgs<T> A)
 {
@@ -316,18 +335,21 @@ k_pass(PassArgs<T> A)
     // Record buffers: the rate pass reads buffer `cur`; iteration k of sim s reads
     // buffer (cur + k) & 1 and writes the other, so a sim whose loop has stopped
     // simply drops out (uniform per block).
-    int par = A.cur;
+    int par = A.cur, ppar = 0;
     if (MODE == MODE_PSEUDO) {
         const SimIter &It = A.iters[s];
         if (It.done) return;
         par = (A.cur + It.iters) & 1;
+        ppar = It.iters & 1;
     }
     const Q *__restrict__ vin = par ? A.vp1 : A.vp0;
     Q *__restrict__ vout = par ? A.vp0 : A.vp1;
 
     const PassConst<T> K(S);
     const PosT pos(S);
-    const Rec *__restrict__ prec = (const Rec *)A.prec;
+    // moving sims ping-pong their position records with the iteration parity
+    const bool moving = MOVE && MODE == MODE_PSEUDO && S.move;
+    const Rec *__restrict__ prec = (const Rec *)((moving && ppar) ? A.prec2 : A.prec);
 
     Acc<T> acc;
     T pi = 0, vi[3] = {0, 0, 0};
@@ -345,6 +367,7 @@ k_pass(PassArgs<T> A)
         }
         st_pm = A.pm[i];
     }
+    T av[3] = {0, 0, 0};  // dot vector of the advective sums: V_i (steady) or Vtilde_i
     if (active) {
         const Rec ri = prec[i];
         const Q me = vin[i];
@@ -352,6 +375,11 @@ k_pass(PassArgs<T> A)
         vi[1] = me.y;
         vi[2] = DIM == 3 ? me.z : T(0);
         pi = pres<DIM>(me);
+        if (CONV) {
+            for (int d = 0; d < 3; ++d) av[d] = vi[d];
+            if (moving)
+                for (int d = 0; d < DIM; ++d) av[d] = A.vt[d * Nf + i];
+        }
         const uint32_t cn = A.cnt[i];
         const int nfl = (int)(cn & 0xffffu), nwl = (int)(cn >> 16);
         npairs = nfl + nwl;
@@ -389,11 +417,11 @@ k_pass(PassArgs<T> A)
                 vd[1] = vi[1] - vj[m].y;
                 vd[2] = DIM == 3 ? vi[2] - vj[m].z : T(0);
                 if (CACHE == 2) {
-                    pair_cached<T, DIM, AV, CONV>(K, cc[m], ua[m], vd, vd, vi, pi, pres<DIM>(vj[m]), acc);
+                    pair_cached<T, DIM, AV, CONV>(K, cc[m], ua[m], vd, vd, vi, av, pi, pres<DIM>(vj[m]), acc);
                 } else {
                     pos.delta(ri, rj[m], r);
                     const size_t e = (size_t)(k + m * LPP) * N;
-                    pair_terms<T, DIM, AV, SEPDEN, CONV, CACHE == 1>(K, r, vd, vd, vi, pi, pres<DIM>(vj[m]), acc,
+                    pair_terms<T, DIM, AV, SEPDEN, CONV, CACHE == 1>(K, r, vd, vd, vi, av, pi, pres<DIM>(vj[m]), acc,
                                                                      CACHE ? cf + e : nullptr,
                                                                      (CACHE && AV) ? cu + e : nullptr);
                 }
@@ -407,12 +435,12 @@ k_pass(PassArgs<T> A)
             vd[1] = vi[1] - vj.y;
             vd[2] = DIM == 3 ? vi[2] - vj.z : T(0);
             if (CACHE == 2) {
-                pair_cached<T, DIM, AV, CONV>(K, cf[(size_t)k * N], AV ? cu[(size_t)k * N] : u0, vd, vd, vi, pi,
+                pair_cached<T, DIM, AV, CONV>(K, cf[(size_t)k * N], AV ? cu[(size_t)k * N] : u0, vd, vd, vi, av, pi,
                                               pres<DIM>(vj), acc);
             } else {
                 const Rec rj = prec[j];
                 pos.delta(ri, rj, r);
-                pair_terms<T, DIM, AV, SEPDEN, CONV, CACHE == 1>(K, r, vd, vd, vi, pi, pres<DIM>(vj), acc,
+                pair_terms<T, DIM, AV, SEPDEN, CONV, CACHE == 1>(K, r, vd, vd, vi, av, pi, pres<DIM>(vj), acc,
                                                                  CACHE ? cf + (size_t)k * N : nullptr,
                                                                  (CACHE && AV) ? cu + (size_t)k * N : nullptr);
             }
@@ -428,12 +456,12 @@ k_pass(PassArgs<T> A)
                 vv[1] = vi[1] - gj.y;
                 vv[2] = DIM == 3 ? vi[2] - gj.z : T(0);
                 if (CACHE == 2) {
-                    pair_cached<T, DIM, AV, CONV>(K, cf[(size_t)k * N], AV ? cu[(size_t)k * N] : u0, vd, vv, vi, pi,
+                    pair_cached<T, DIM, AV, CONV>(K, cf[(size_t)k * N], AV ? cu[(size_t)k * N] : u0, vd, vv, vi, av, pi,
                                                   pres<DIM>(gj), acc);
                 } else {
                     const Rec rj = prec[j];
                     pos.delta(ri, rj, r);
-                    pair_terms<T, DIM, AV, SEPDEN, CONV, CACHE == 1>(K, r, vd, vv, vi, pi, pres<DIM>(gj), acc,
+                    pair_terms<T, DIM, AV, SEPDEN, CONV, CACHE == 1>(K, r, vd, vv, vi, av, pi, pres<DIM>(gj), acc,
                                                                      CACHE ? cf + (size_t)k * N : nullptr,
                                                                      (CACHE && AV) ? cu + (size_t)k * N : nullptr);
                 }
@@ -448,24 +476,28 @@ k_pass(PassArgs<T> A)
             lane_sum(acc.vis[d], LPP);
             if (CONV) lane_sum(acc.conv[d], LPP);
         }
+        if (CONV) lane_sum(acc.padv, LPP);
     }
 
     T Dv = 0, R[3] = {0, 0, 0}, vt2 = 0, dw2 = 0;
     if (owner) {
         Dv = (T)S.k_div * acc.div + (T)S.k_lap * acc.lap;
         for (int d = 0; d < DIM; ++d) R[d] = (T)S.k_grad * acc.grad[d] + (T)S.k_visc * acc.vis[d] + (T)S.g[d];
-        if (CONV)
+        if (CONV) {
             for (int d = 0; d < DIM; ++d) R[d] += (T)S.k_conv * acc.conv[d];
+            Dv += (T)S.k_padv * acc.padv;
+        }
 
         if (MODE == MODE_PSEUDO) {
             const T inv2dt = (T)S.inv2dt, gamma = (T)S.gamma, dtau = (T)S.dtau, dt = (T)S.dt;
-            T vnew[3] = {0, 0, 0};
+            T vnew[3] = {0, 0, 0}, vtn[3] = {0, 0, 0};
             for (int d = 0; d < DIM; ++d) {
                 const T wk = st_w[d];
                 const T bdf = (T(3) * wk - st_dv[d]) * inv2dt;
                 const T dvdtau = (R[d] - bdf) * gamma;
                 const T wn = wk + dtau * dvdtau;
                 const T vt = dt * dvdtau;
+                vtn[d] = vt;
                 vt2 += vt * vt;
                 const T dw = wn - st_w0[d];
                 dw2 += dw * dw;
@@ -476,6 +508,29 @@ k_pass(PassArgs<T> A)
             A.pm[i] = pm;
             A.dp[i] = Dv;
             vout[i] = make_rec<T, DIM>(vnew, (T)pm);
+            if (moving) {
+                // eq. vtilde and eq. rkp1, then the next eq. rkstar: r^{k+1} = r^{k+1/2}
+                // + dtau/2 Vtilde^{k+1}, r^{k+3/2} = r^{k+1} + dtau/2 Vtilde^{k+1}
+                double xo[3] = {0.0, 0.0, 0.0}, e2 = 0.0;
+                for (int d = 0; d < DIM; ++d) {
+                    const double hv = 0.5 * S.dtau * (double)vtn[d];
+                    double x1 = A.xm[d * Nf + i] + hv;
+                    if (S.periodic[d]) x1 = x1 >= S.hi[d] ? x1 - S.L[d] : (x1 < S.lo[d] ? x1 + S.L[d] : x1);
+                    double x2 = x1 + hv;
+                    if (S.periodic[d]) x2 = x2 >= S.hi[d] ? x2 - S.L[d] : (x2 < S.lo[d] ? x2 + S.L[d] : x2);
+                    A.xm[d * Nf + i] = x2;
+                    A.vt[d * Nf + i] = vtn[d];
+                    xo[d] = x2;
+                    double e = x2 - A.x[d * N + i];  // from r^(0), minimum image
+                    if (S.periodic[d]) e = e > S.halfL[d] ? e - S.L[d] : (e < -S.halfL[d] ? e + S.L[d] : e);
+                    e2 += e * e;
+                }
+                write_pos_record<T>(S, ppar ? const_cast<void *>(A.prec) : A.prec2, i, xo);
+                if (DIM == 2) ((double2 *)A.xr)[i] = make_double2(xo[0], xo[1]);
+                else ((double4 *)A.xr)[i] = make_double4(xo[0], xo[1], xo[2], 0.0);
+                const double lim = 0.45 * S.skin;
+                if (S.move == 2 && e2 > lim * lim) atomicOr(&A.flags[F_SKIN], 1);
+            }
         } else {
             // a steady solve keeps its particles where they are and starts from V^n
             const double dt = S.steady ? 0.0 : S.dt, hdt2 = 0.5 * dt * dt;
@@ -547,6 +602,7 @@ template <typename T> struct WallArgs {
     const uint32_t *cnt;
     const void *prec;
     Q *vp0, *vp1;    // reads fluid records, writes wall records (same buffer)
+    const void *prec2;  // position records of odd iterations of moving sims
     int cur;
     const T *vwall;
     T *pwall;
@@ -566,17 +622,18 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
     const int N = A.N;
     const int s = A.simid[i];
     const SimDev &S = A.sims[s];
-    int par = A.cur;
+    int par = A.cur, ppar = 0;
     if (A.mode == MODE_PRE) {
         for (int d = 0; d < 3; ++d) A.x_alt[d * N + i] = A.x[d * N + i];
     } else {
         const SimIter &It = A.iters[s];
         if (It.done) return;
         par = (A.cur + It.iters) & 1;
+        ppar = S.move ? It.iters & 1 : 0;  // moving fluid: records at r^{k+1/2}
     }
     Q *__restrict__ vin = par ? A.vp1 : A.vp0;
     const PosT pos(S);
-    const Rec *__restrict__ prec = (const Rec *)A.prec;
+    const Rec *__restrict__ prec = (const Rec *)(ppar ? A.prec2 : A.prec);
     const Rec ri = prec[i];
     const T inv_h = (T)S.inv_h, rho = (T)S.rho0;
     const uint32_t cn = A.cnt[i];
@@ -1194,6 +1251,7 @@ template <typename T> PassArgs<T> pass_args(Ctx &c, int mode, bool cand_lists)
     a.partials2 = c.partials2;
     a.coef = (Q *)c.coef;
     a.coef_av = c.coef_av;
+    a.prec2 = c.prec2; a.xm = c.xm; a.vt = (T *)c.vt; a.xr = c.xr; a.flags = c.flags;
     return a;
 }
 
@@ -1201,15 +1259,15 @@ template <typename T> PassArgs<T> pass_args(Ctx &c, int mode, bool cand_lists)
 // kernel's own start and end timestamps (no queue gaps in the interval).
 // Pseudo-iterations of a context with steady sims take the variant with the
 // convective sum (zero coefficient for the time-accurate sims).
-template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int LPP, bool CONV, int CACHE>
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int LPP, bool CONV, int CACHE, bool MOVE = false>
 void launch_pseudo(Ctx &c, const PassArgs<T> &a, dim3 grid)
 {
     if (c.ext_start)
-        hipExtLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP, CONV, CACHE>), grid,
+        hipExtLaunchKernelGGL((k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP, CONV, CACHE, MOVE>), grid,
                               dim3(c.block), 0, c.stream, c.ext_start, c.ext_stop, 0, a);
     else
-        DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP, CONV, CACHE>), grid, dim3(c.block), 0,
-                     c.stream, a);
+        DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PSEUDO, LPP, CONV, CACHE, MOVE>), grid,
+                     dim3(c.block), 0, c.stream, a);
 }
 
 // Cached pair coefficients hold one regulariser: contexts with separate EDAC
@@ -1228,6 +1286,8 @@ void dispatch_mode(Ctx &c, int mode, const PassArgs<T> &a, dim3 grid)
     if (mode == MODE_PRE)
         DTSPH_LAUNCH(c, (k_pass<T, DIM, WALLS, AV, SEPDEN, MODE_PRE, LPP, false>), grid, dim3(c.block), 0, c.stream,
                      a);
+    else if (c.any_move)  // moving particles: advective sums, no coefficient cache
+        launch_pseudo<T, DIM, WALLS, AV, SEPDEN, LPP, true, 0, true>(c, a, grid);
     else if (c.any_steady)
         dispatch_pseudo<T, DIM, WALLS, AV, SEPDEN, LPP, true>(c, a, grid);
     else
@@ -1299,6 +1359,7 @@ void launch_wall(Ctx &c, int mode, bool cand_lists)
     a.cnt = cand_lists ? c.ccnt : c.cnt;
     a.vp0 = (Q *)c.vp[0];
     a.vp1 = (Q *)c.vp[1];
+    a.prec2 = c.prec2;
     a.cur = c.cur;
     a.vwall = (const T *)c.vw[b];
     a.pwall = (T *)c.pw[b];
@@ -1346,6 +1407,39 @@ void launch_pre_records(Ctx &c)
         DTSPH_LAUNCH(c, (k_records<T, 3>), dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.Nf, c.simid[b], c.sims,
                            (const T *)c.vn[b], (const T *)nullptr, c.pm[b], (const T *)c.dp[b], (Q *)c.vp[c.cur], 0,
                            0, c.iters, c.n_sims, 0);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+// Loop start of sims moving in pseudo-time (Algorithm 1): r^{1/2} = r^(0),
+// Vtilde^0 = 0, and the second position-record buffer equal to the first (wall
+// and frozen entries are only ever read there).
+template <typename T, int DIM>
+__global__ void k_move_begin(int N, int Nf, const int *__restrict__ simid, const SimDev *__restrict__ sims,
+                             const double *__restrict__ x, const void *__restrict__ prec, void *__restrict__ prec2,
+                             double *__restrict__ xm, T *__restrict__ vt)
+{
+    using Rec = typename Pos<T, DIM>::Rec;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    ((Rec *)prec2)[i] = ((const Rec *)prec)[i];
+    if (i < Nf && sims[simid[i]].move)
+        for (int d = 0; d < DIM; ++d) {
+            xm[d * Nf + i] = x[d * N + i];
+            vt[d * Nf + i] = T(0);
+        }
+}
+
+template <typename T>
+void launch_move_begin(Ctx &c)
+{
+    if (!c.any_move) return;
+    const int b = c.buf;
+    if (c.max_dim == 2)
+        DTSPH_LAUNCH(c, (k_move_begin<T, 2>), dim3(grid_for(c.N)), dim3(256), 0, c.stream, c.N, c.Nf, c.simid[b],
+                     c.sims, c.x[c.xb], c.prec, c.prec2, c.xm, (T *)c.vt);
+    else
+        DTSPH_LAUNCH(c, (k_move_begin<T, 3>), dim3(grid_for(c.N)), dim3(256), 0, c.stream, c.N, c.Nf, c.simid[b],
+                     c.sims, c.x[c.xb], c.prec, c.prec2, c.xm, (T *)c.vt);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -1445,6 +1539,7 @@ void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop)
     template void launch_wall<T>(Ctx &, int, bool);                            \
     template void launch_pre_records<T>(Ctx &);                                \
     template void launch_loop_begin<T>(Ctx &, int);                            \
+    template void launch_move_begin<T>(Ctx &);                                 \
     template void launch_correct<T>(Ctx &);                                    \
     template void launch_shift<T>(Ctx &, bool);                                \
     template void launch_set_state<T>(Ctx &, const dtsph_state_view &, bool);  \

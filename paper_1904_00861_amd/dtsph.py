@@ -57,7 +57,7 @@ class SimDesc(C.Structure):
         ("periodic", C.c_int32 * 3), ("reserved1", C.c_int32),
         ("shift", C.c_int32), ("shift_n", C.c_int32),
         ("shift_r", C.c_double),
-        ("steady", C.c_int32), ("reserved2", C.c_int32),
+        ("steady", C.c_int32), ("move", C.c_int32),
     ]
 
 
@@ -166,7 +166,7 @@ def desc_from_params(p: dict) -> SimDesc:
         elif name == "periodic":
             getattr(d, name)[:] = [int(t) for t in val]
         elif name in ("dim", "max_neighbors", "max_iter", "stall_window", "conv_norm",
-                      "edac_reg_literal", "edac_rho_literal", "shift", "shift_n", "steady"):
+                      "edac_reg_literal", "edac_rho_literal", "shift", "shift_n", "steady", "move"):
             setattr(d, name, int(val))
         else:
             setattr(d, name, float(val))

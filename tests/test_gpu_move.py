@@ -1,0 +1,137 @@
+"""GPU parity of particles moving in pseudo-time (Algorithm 1) against the
+oracle: whole steps with the lists of r^(0) (move = 1) and with the lists
+recomputed every iteration (move = 2), free running and at fixed iteration
+counts, with walls, artificial viscosity, 3D and shifting; batches mixing
+frozen, moving and steady sims; exact lists after moving steps; the skin
+check of the list updates."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1904_00861_amd import dtsph as D
+from paper_1904_00861_amd import inputs as I
+
+from gpu_helpers import banner, oracle_steps, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+PREC = {"fp64": D.FP64, "fp32": D.FP32}
+TOL = {"fp64": dict(v=1e-10, p=1e-9, x=1e-12), "fp32": dict(v=1e-4, p=1e-3, x=1e-7)}
+
+
+def _with(prob, **kw):
+    prob = prob.copy()
+    prob.params = dict(prob.params, **kw)
+    return prob
+
+
+CASES = {
+    "tgv2d_30": lambda m: _with(I.tgv2d(30, seed=5, jitter=0.05), move=m),
+    "cavity_16": lambda m: _with(I.cavity(16), move=m),
+    "dam_0.05": lambda m: _with(I.dam_break(0.05), move=m),
+    "tgv3d_8": lambda m: _with(I.tgv3d(8, seed=2), move=m),
+    "tgv2d_30_shift": lambda m: _with(I.tgv2d(30, seed=6, jitter=0.1), move=m, shift=1),
+}
+
+
+def gpu_fixed(prob, n_steps, fixed, precision):
+    sim = D.Sim(prob, precision=precision)
+    try:
+        reps = []
+        for _ in range(n_steps):
+            sim.predict()
+            reps.append(sim.pseudo_iterate(fixed)[1])
+            sim.correct()
+        return sim.get_state(), reps, sim.sim_slices()
+    finally:
+        sim.close()
+
+
+def _check(g, x, v, vp, p, nf, t, loose=1.0, vscale=1.0):
+    assert np.abs(g["x"] - x).max() <= t["x"] * loose
+    assert rel_l2(g["v"][:nf], v[:nf]) <= t["v"] * loose * vscale
+    assert rel_l2(g["v_prev"][:nf], vp[:nf]) <= t["v"] * loose * vscale
+    assert rel_l2(g["p"][:nf], p[:nf]) <= t["p"] * loose
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("move", [1, 2])
+@pytest.mark.parametrize("case,steps,fixed", [("tgv2d_30", 3, 8), ("cavity_16", 3, 6), ("dam_0.05", 2, 6),
+                                              ("tgv3d_8", 2, 4), ("tgv2d_30_shift", 3, 5)])
+def test_fixed_iterations_match_oracle(case, steps, fixed, move, prec):
+    prob = CASES[case](move)
+    banner(f"moving particles {case} move={move} {steps}x{fixed} {prec}")
+    nf = prob.n_fluid
+    x, v, vp, p, oreps, _ = oracle_steps(prob, steps, fixed)
+    g, greps, _ = gpu_fixed(prob, steps, fixed, PREC[prec])
+    # the dam break's momentum rate is a cancellation of grad p / rho and g
+    _check(g, x, v, vp, p, nf, TOL[prec], vscale=10.0 if case.startswith("dam") else 1.0)
+    # positions after the first step carry the rounding of summation order, so a
+    # pair at the support edge may fall on either side: FP64 counts agree closely
+    # (FP32 positions move pairs across the edge more often)
+    if prec == "fp64":
+        for a, b in zip([r[0]["pairs"] for r in greps], [r["pairs"] for r in oreps]):
+            assert abs(a - b) <= max(2, b // 1000)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("move", [1, 2])
+def test_free_running_steps_match_oracle(move, prec):
+    prob = CASES["tgv2d_30"](move)
+    banner(f"moving particles free running move={move} {prec}")
+    nf = prob.n_fluid
+    x, v, vp, p, oreps, _ = oracle_steps(prob, 5)
+    sim = D.Sim(prob, precision=PREC[prec])
+    st, greps = sim.step(5)
+    g = sim.get_state()
+    sim.close()
+    gi, oi = [r[0]["iters"] for r in greps], [r["iters"] for r in oreps]
+    if prec == "fp64":
+        assert gi == oi
+    else:
+        assert all(abs(a - b) <= 1 for a, b in zip(gi, oi))
+    _check(g, x, v, vp, p, nf, TOL[prec], loose=1.0 if gi == oi else 20.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_of_frozen_moving_and_steady_sims(prec):
+    probs = [CASES["tgv2d_30"](1), I.cavity(12), CASES["cavity_16"](2), I.cavity(14, steady=True),
+             _with(I.tgv2d(20, seed=3), move=2)]
+    banner(f"batch frozen / moving / steady {prec}")
+    g, greps, sl = gpu_fixed(probs, 2, 5, PREC[prec])
+    t = TOL[prec]
+    for s, prob in enumerate(probs):
+        x, v, vp, p, oreps, _ = oracle_steps(prob, 2, 5)
+        nf = prob.n_fluid
+        sub = {k: g[k][sl[s]] for k in g}
+        _check(sub, x, v, vp, p, nf, t)
+
+
+def test_lists_exact_after_moving_steps():
+    prob = CASES["cavity_16"](2)
+    banner("lists after moving steps")
+    sim = D.Sim(prob, precision=D.FP64)
+    sim.step(4)
+    g = sim.get_state()
+    off, idx = sim.neighbor_list()
+    sim.close()
+    ob, ib = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, g["x"], "brute")
+    assert np.array_equal(off, ob) and np.array_equal(idx, ib)
+
+
+def test_list_update_beyond_the_skin_is_reported():
+    prob = CASES["tgv2d_30"](2)
+    banner("moving particles leave a zero skin")
+    sim = D.Sim(prob, precision=D.FP64)
+    sim.set_option(D.OPT_SKIN, 0)  # no skin: any motion in pseudo-time leaves it
+    with pytest.raises(D.DtsphError) as e:
+        sim.step(2)
+    assert e.value.status == D.EOVERFLOW
+    sim.close()
+
+
+def test_moving_and_steady_are_exclusive():
+    prob = _with(I.cavity(12, steady=True), move=1)
+    banner("steady with move is rejected")
+    with pytest.raises(D.DtsphError):
+        D.Sim(prob, precision=D.FP64)
