@@ -205,6 +205,14 @@ typedef struct dtsph_timing {
     double wall_ms;
     int64_t build_launches; /* cell + neighbour-list builds                   */
     double build_ms;
+    /* counted on every call (timing on or off), reset with the timers:       */
+    int64_t full_builds;    /* sorts + neighbour-list builds                  */
+    int64_t list_filters;   /* exact lists filtered from candidate lists      */
+    double last_max_shift;  /* largest particle shift of the last shifting    */
+    double last_disp;       /* largest |r^{n+1} - r^(0)| of the last loop     */
+    int64_t spec_tries;     /* speculative ends of step queued (see
+                               DTSPH_OPT_SPECULATE) and how many of them ran */
+    int64_t spec_hits;
 } dtsph_timing;
 
 /* ---- sizes (host memory) ------------------------------------------------- */
@@ -354,6 +362,14 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
                                   artificial viscosity 8 / 16 B more in 2D,
                                   16 / 32 B in 3D), which adds to
                                   dtsph_workspace_bytes; between steps only. */
+#define DTSPH_OPT_SPECULATE 12 /* 1 (default): dtsph_step queues the corrector
+                                  and the next step's rate pass behind a device
+                                  gate (every sim stopped, no non-finite
+                                  residual, candidate lists still valid)
+                                  before it waits for the loop's reports; when
+                                  the gate is closed they do nothing and the
+                                  step ends as with 0. Off for contexts with
+                                  shifting or graphs. Results are identical. */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the pair pass's launch shape. Between steps only (EINVAL in

@@ -513,7 +513,11 @@ void set_active_ranges(Ctx &c, bool all)
 // and the bookkeeping at its end.
 struct LoopRun {
     int fixed = 0, max_it = 0, launched = 0, chunk = 1;
+    bool spec = false, spec_next = false;  // speculative end of step after each chunk
+    int tries = 0;
 };
+
+template <typename T> void launch_speculation(Ctx &c, bool next_pre);
 
 // Automatic pair-coefficient caching: the first iteration of a loop writes the
 // coefficients (16 B per pair in FP32) and later ones read them. Streaming them
@@ -590,9 +594,15 @@ template <typename T> int loop_finish(Ctx &c, LoopRun &L, dtsph_iter_report *rep
         bool all = true;
         for (int s = 0; s < c.n_sims; ++s) all = all && c.flags_host[F_COUNT + s];
         if (all || L.launched >= L.max_it) break;
-        L.chunk = c.chunk > 0 ? c.chunk : 2;
+        // more iterations than the last loop needed: chunks grow with the loop
+        // (sims that stop inside a chunk leave only no-op launches behind)
+        L.chunk = c.chunk > 0 ? c.chunk : std::max(2, std::min(L.launched / 2, 32));
         set_active_ranges(c, false);
         launch_chunk<T>(c, L);
+        if (L.spec) {
+            launch_speculation<T>(c, L.spec_next);
+            L.tries++;
+        }
     }
     set_active_ranges(c, true);
     c.p_half = true;  // p^K = p^{K+1/2} - dtau/2 (dp/dtau)^K is applied lazily
@@ -604,6 +614,7 @@ template <typename T> int loop_finish(Ctx &c, LoopRun &L, dtsph_iter_report *rep
         // candidate lists built at r^(0) still hold every neighbour at r^{n+1}
         cand = cand && c.sims_h[s].skin > 0 && it.disp < 0.4 * c.sims_h[s].skin;
         c.last_disp[s] = it.disp;
+        c.tstats.last_disp = s == 0 ? it.disp : std::max(c.tstats.last_disp, it.disp);
         const int64_t pairs = (int64_t)c.pairs_host[s];
         most = std::max(most, it.iters);
         if (rep) {
@@ -661,6 +672,7 @@ template <typename T> void do_shift(Ctx &c)
     launch_shift<T>(c, use_cand);
     DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
     const double mx = *(volatile double *)c.sh_max_h;
+    c.tstats.last_max_shift = mx;
     bool ok = true;
     for (int s = 0; s < c.n_sims; ++s) {
         const double moved = (use_cand ? c.last_disp[s] : 0.0) + mx;
@@ -754,16 +766,87 @@ template <typename T> void step_segment(Ctx &c, LoopRun &L)
     DTSPH_HIP_CHECK(hipGraphLaunch(ex, c.stream));
 }
 
+// Speculative end of step: behind a device gate (k_gate: every sim stopped, no
+// non-finite residual, candidate lists still cover r^{n+1}) queue the corrector
+// and, when another step follows, the next rate pass on the candidate lists, so
+// the GPU works while the host waits for the reports. When the gate is closed
+// these launches return at once and the host proceeds as without them.
+template <typename T> void launch_speculation(Ctx &c, bool next_pre)
+{
+    c.tstats.spec_tries++;
+    launch_gate(c);
+    c.gate_use = c.gate;
+    const bool p_half = c.p_half;
+    c.p_half = true;  // state at the end of a loop: p^K is still pending
+    launch_correct<T>(c);
+    c.p_half = p_half;
+    if (next_pre) {
+        // after the corrector the records are fresh; the lists are those of
+        // r^(0) (candidates) or, for steady contexts, still exact
+        const bool use_cand = !(c.all_steady && c.cells_valid);
+        launch_wall<T>(c, MODE_PRE, use_cand);
+        launch_pass<T>(c, MODE_PRE, use_cand);
+    }
+    c.gate_use = nullptr;
+}
+
+// The host's reading of the gate, from the published reports.
+bool gate_open(const Ctx &c)
+{
+    if (!c.cand_next) return false;
+    for (int s = 0; s < c.n_sims; ++s)
+        if (!c.flags_host[F_COUNT + s] || c.reps_host[s].reason == DTSPH_NONFINITE) return false;
+    return true;
+}
+
 template <typename T> int do_step(Ctx &c, int n_steps, dtsph_iter_report *reps)
 {
     if (n_steps < 0) throw ApiError(DTSPH_EINVAL, "n_steps must be >= 0");
     if (c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_step: inside a step (call dtsph_correct first)");
     int status = DTSPH_OK;
+    c.spec_ready = false;
     for (int s = 0; s < n_steps; ++s) {
         LoopRun L;
-        step_segment<T>(c, L);
+        if (c.spec_ready) {  // this step's rate pass and predictor already ran
+            c.spec_ready = false;
+            loop_prologue<T>(c, 0, L);
+            launch_chunk<T>(c, L);
+        } else {
+            step_segment<T>(c, L);
+        }
+        // speculate while it mostly pays (a closed gate costs a few no-op
+        // launches); after a run of misses, probe again every 16 steps
+        L.spec = c.speculate && !c.any_shift && !c.graphs && (c.spec_score > 0 || ++c.spec_idle % 16 == 0);
+        L.spec_next = s + 1 < n_steps;
+        if (L.spec) {
+            launch_speculation<T>(c, L.spec_next);
+            L.tries++;
+        }
         int st = loop_finish<T>(c, L, reps ? reps + (size_t)s * c.n_sims : nullptr);
-        do_correct<T>(c);
+        const bool hit = L.spec && gate_open(c);
+        if (L.spec) {
+            c.spec_score = std::min(8, c.spec_score + (hit ? 1 : 0) - 2 * (L.tries - (hit ? 1 : 0)));
+            if (c.spec_score > 0) c.spec_idle = 0;
+        }
+        if (hit) {
+            c.tstats.spec_hits++;
+            // book what the gated launches did: do_correct, then do_predict
+            c.in_loop = false;
+            c.cells_valid = c.all_steady && c.cells_valid;
+            c.cand_ok = c.cand_next;
+            c.p_half = false;
+            c.records_fresh = true;
+            if (L.spec_next) {
+                c.xb ^= 1;
+                c.in_loop = true;
+                c.cells_valid = c.all_steady && c.cells_valid;
+                c.cand_ok = false;
+                c.records_fresh = false;
+                c.spec_ready = true;
+            }
+        } else {
+            do_correct<T>(c);
+        }
         if (st < 0) return st;
         if (st > 0) status = st;
     }
@@ -943,6 +1026,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         dev_alloc(c, c.seg_p, sizeof(double4) * max_segs);
         dev_alloc(c, c.seg_p2, sizeof(double2) * max_segs);
         dev_alloc(c, c.tickets, sizeof(uint32_t) * n_sims);
+        dev_alloc(c, c.gate, 16);
         dev_alloc(c, c.pubcount, sizeof(uint32_t) * n_sims);
         dev_alloc(c, c.partials2, sizeof(double2) * max_tiles);
         dev_alloc(c, c.flags, sizeof(int) * (F_COUNT + n_sims));
@@ -1245,6 +1329,10 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
                 c.coef_valid = false;
             }
             c.pair_cache = (int)value;
+            break;
+        case DTSPH_OPT_SPECULATE:
+            if (value != 0 && value != 1) throw ApiError(DTSPH_EINVAL, "speculate must be 0 or 1");
+            c.speculate = value != 0;
             break;
         case DTSPH_OPT_GRAPHS:
             if (value != 0 && value != 1) throw ApiError(DTSPH_EINVAL, "graphs must be 0 or 1");

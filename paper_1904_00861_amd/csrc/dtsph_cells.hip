@@ -666,6 +666,7 @@ template <typename T> void launch_grouped(Ctx &c, const NbrArgs<T> &a, bool filt
 template <typename T>
 void build_cells(Ctx &c, int loop_fixed)
 {
+    c.tstats.full_builds++;
     hipStream_t st = c.stream;
     const int N = c.N, nkeys = 2 * c.C;
     const int b = c.buf, o = c.buf ^ 1;
@@ -715,6 +716,7 @@ void build_cells(Ctx &c, int loop_fixed)
 template <typename T>
 void filter_lists(Ctx &c)
 {
+    c.tstats.list_filters++;
     int t0 = timer_begin(c, 2);
     launch_nbr_lists<T>(c, true);
     timer_end(c, t0, 2);

@@ -194,6 +194,12 @@ struct Ctx {
     double4 *seg_p = nullptr;             // per segment: partial sums of the residual terms
     double2 *seg_p2 = nullptr;
     uint32_t *tickets = nullptr;          // per sim: segments of the running finalize done
+    // speculative end of step (dtsph_step): the corrector and the next rate pass
+    // are queued behind a device gate before the host reads the loop's reports
+    int *gate = nullptr;                  // 1: every sim stopped, lists still cover
+    const int *gate_use = nullptr;        // gate the next launches of these kernels
+    bool speculate = true, spec_ready = false;
+    int spec_score = 4, spec_idle = 0;    // recent success of speculation (adaptive)
     double4 *partials = nullptr;
     double2 *partials2 = nullptr;         // per tile: max |V^{k+1} - V^(0)|^2, pairs
     int *flags = nullptr;
@@ -265,6 +271,7 @@ void launch_publish(Ctx &c);
 template <typename T> void launch_loop_begin(Ctx &c, int fixed_iters);
 template <typename T> void launch_move_begin(Ctx &c);
 template <typename T> void launch_correct(Ctx &c);
+void launch_gate(Ctx &c);
 template <typename T> void launch_shift(Ctx &c, bool cand_lists);  // sums, apply, max
 template <typename T> void launch_set_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
 template <typename T> void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
