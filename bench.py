@@ -317,6 +317,19 @@ def main():
             sl = run_leg(shifted, prec, args.steps, args.warmup, 0)
             extras["with_shifting_value"] = pair_evals(sl["reports"]) / sl["seconds"]
             extras["with_shifting_ms_per_step"] = sl["seconds"] * 1e3 / args.steps
+        for mv, key in ((1, "moving"), (2, "moving_list_updates")):
+            # Algorithm 1 on the same workload: particles advected in pseudo-time,
+            # with the lists of r^(0) or recomputed every iteration
+            moved = []
+            for p in problems:
+                q = p.copy()
+                q.params = dict(p.params, move=mv)
+                moved.append(q)
+            log(f"leg with particles moving in pseudo-time (move={mv})")
+            ml = run_leg(moved, prec, args.steps, args.warmup, 0)
+            extras[f"{key}_value"] = pair_evals(ml["reports"]) / ml["seconds"]
+            extras[f"{key}_ms_per_step"] = ml["seconds"] * 1e3 / args.steps
+            extras[f"{key}_step_time_over_frozen"] = (ml["seconds"] / args.steps) / (secs / args.steps)
         log("steady-state leg (lid-driven cavity)")
         extras["steady"] = steady_leg()
         extras["steady_pair_cache"] = steady_leg(pair_cache=1)
