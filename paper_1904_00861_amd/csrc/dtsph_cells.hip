@@ -473,6 +473,11 @@ __device__ __forceinline__ void scan_run(const typename XR<DIM>::type *__restric
 // Cell rows of one particle's search block, visited in order (type, plane,
 // row); each row is at most two runs of consecutive cell keys along x. The
 // bounds of the next row are loaded while the current one is scanned.
+// Off the GENERAL path a row's x-run is trimmed to the cells the candidate
+// sphere reaches there: with d the distance from the particle to the row's
+// y (and z) slab, only |x_j - x_i| <= sqrt(R^2 - d^2) can hold a candidate.
+// Edge cells of a non-periodic axis hold the particles clamped into them, so
+// their slab is open on the outer side; a margin of 1e-7 h covers rounding.
 template <typename T, int DIM, int G, bool GENERAL>
 __device__ __forceinline__ void scan_block(const NbrArgs<T> &A, const SimDev &S, int i, const Probe<DIM> &P,
                                            int cx, int cy, int cz, bool fluid, int &cf, int &cw, int &ccf,
@@ -498,6 +503,7 @@ __device__ __forceinline__ void scan_block(const NbrArgs<T> &A, const SimDev &S,
     int *__restrict__ nbr = A.nbr + i;
     int *__restrict__ cand = A.cand + i;
     const double cr2 = S.cand_r2;
+    const double tol = 1e-7 * S.h;
     auto row_key = [&](int r, int &u, int &v, int &tp) {
         tp = r >= per_tp;
         const int rr = r - tp * per_tp;
@@ -505,26 +511,60 @@ __device__ __forceinline__ void scan_block(const NbrArgs<T> &A, const SimDev &S,
         v = rr - u * ry.count;
         return S.key_base + (tp ? A.C : 0) + (rz.at(u) * ny + ry.at(v)) * nx;
     };
+    // distance from the particle to a row's slab along axis a (block index k)
+    auto slab_d = [&](const AxisRange &ra, int k, int a, double pa, double La, int per) {
+        const int c = ra.at(k);
+        double lo = S.lo[a] + (double)c * S.cs[a] - ra.shift(k, La);
+        double hi = lo + S.cs[a];
+        if (!per && c == 0) lo = -INFINITY;
+        if (!per && c == ra.n - 1) hi = INFINITY;
+        const double d = fmax(0.0, fmax(lo - pa, pa - hi)) - tol;
+        return d > 0.0 ? d : 0.0;
+    };
+    // the row's runs: [a0, b0] unshifted, [a1, b1] with shift s1 (b < a: empty)
+    auto row_runs = [&](int u, int v, int &a0, int &b0, int &a1, int &b1, double &s1) {
+        a0 = xa0; b0 = xb0; a1 = xa1; b1 = xb1; s1 = sx1;
+        if (GENERAL) return;
+        const double dy = slab_d(ry, v, 1, P.yi, P.Ly, P.py);
+        const double dz = DIM == 3 ? slab_d(rz, u, 2, P.zi, P.Lz, P.pz) : 0.0;
+        const double rem = cr2 - (dy * dy + dz * dz);
+        if (rem < 0.0) { b0 = a0 - 1; b1 = a1 - 1; return; }
+        const double w = sqrt(rem) + tol;
+        int lo_c = (int)floor((P.xi - w - S.lo[0]) * S.inv_cs[0]);
+        int hi_c = (int)floor((P.xi + w - S.lo[0]) * S.inv_cs[0]);
+        lo_c = lo_c > cx - md ? lo_c : cx - md;
+        hi_c = hi_c < cx + md ? hi_c : cx + md;
+        a0 = lo_c > 0 ? lo_c : 0;
+        b0 = hi_c < nx - 1 ? hi_c : nx - 1;
+        a1 = 0; b1 = -1; s1 = 0.0;
+        if (P.px && lo_c < 0) { a1 = nx + lo_c; b1 = nx - 1; s1 = P.Lx; }
+        else if (P.px && hi_c > nx - 1) { a1 = 0; b1 = hi_c - nx; s1 = -P.Lx; }
+    };
     int u, v, tp;
     int row = row_key(0, u, v, tp);
-    int b0 = (int)cstart[row + xa0], e0 = (int)cstart[row + xb0 + 1];
-    int b1 = 0, e1 = 0;
-    if (xb1 >= xa1) { b1 = (int)cstart[row + xa1]; e1 = (int)cstart[row + xb1 + 1]; }
+    int a0, c0, a1, c1;
+    double s1;
+    row_runs(u, v, a0, c0, a1, c1, s1);
+    int b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+    if (c0 >= a0) { b0 = (int)cstart[row + a0]; e0 = (int)cstart[row + c0 + 1]; }
+    if (c1 >= a1) { b1 = (int)cstart[row + a1]; e1 = (int)cstart[row + c1 + 1]; }
     cf = -1;
     for (int r = 0; r < nrows; ++r) {
         const int cu = u, cv = v, ctp = tp;
         const int jb0 = b0, je0 = e0, jb1 = b1, je1 = e1;
+        const double rs1 = s1;
         if (r + 1 < nrows) {  // prefetch the next row's bounds
             row = row_key(r + 1, u, v, tp);
-            b0 = (int)cstart[row + xa0];
-            e0 = (int)cstart[row + xb0 + 1];
-            if (xb1 >= xa1) { b1 = (int)cstart[row + xa1]; e1 = (int)cstart[row + xb1 + 1]; }
+            row_runs(u, v, a0, c0, a1, c1, s1);
+            b0 = e0 = b1 = e1 = 0;
+            if (c0 >= a0) { b0 = (int)cstart[row + a0]; e0 = (int)cstart[row + c0 + 1]; }
+            if (c1 >= a1) { b1 = (int)cstart[row + a1]; e1 = (int)cstart[row + c1 + 1]; }
         }
         if (ctp == 1 && cf < 0) { cf = cur.total; ccf = cur.ctotal; }
         const double sy = ry.shift(cv, P.Ly), sz = DIM == 3 ? rz.shift(cu, P.Lz) : 0.0;
         const int nrun = jb1 < je1 ? 2 : 1;
         for (int k = 0; k < nrun; ++k)  // one code copy for both runs
-            scan_run<DIM, G, GENERAL>(xr, k ? jb1 : jb0, k ? je1 : je0, i, P, k ? sx1 : 0.0, sy, sz, cr2, nbr,
+            scan_run<DIM, G, GENERAL>(xr, k ? jb1 : jb0, k ? je1 : je0, i, P, k ? rs1 : 0.0, sy, sz, cr2, nbr,
                                       cand, N, A.cap, A.capc, grp, cur);
     }
     if (cf < 0) { cf = cur.total; ccf = cur.ctotal; }
