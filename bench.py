@@ -191,7 +191,7 @@ def cpu_baseline(prob, budget_s=12.0, max_steps=400):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C1", choices=["C0", "C1", "C2", "C3", "C4"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
@@ -201,7 +201,7 @@ def main():
     ap.add_argument("--shape", default=None, metavar="L,B,G,M",
                     help="fixed launch shape instead of the autotuner: pair-pass lanes per particle, "
                          "workgroup size, neighbour-build lanes, cell subdivision (for profiling runs)")
-    ap.add_argument("--timing-every", type=int, default=4, metavar="N",
+    ap.add_argument("--timing-every", type=int, default=8, metavar="N",
                     help="HIP events around every N-th pair-pass launch in the timed region (each "
                          "event record costs host time; sampling keeps it off the step time)")
     ap.add_argument("--shift", type=int, default=None, choices=[0, 1],

@@ -369,7 +369,9 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
                                   before it waits for the loop's reports; when
                                   the gate is closed they do nothing and the
                                   step ends as with 0. Off for contexts with
-                                  shifting or graphs. Results are identical. */
+                                  shifting or graphs or more than 64 sims, and
+                                  while recent gates mostly stayed closed.
+                                  Results are identical.                      */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the pair pass's launch shape. Between steps only (EINVAL in

@@ -766,16 +766,16 @@ template <typename T> void step_segment(Ctx &c, LoopRun &L)
     DTSPH_HIP_CHECK(hipGraphLaunch(ex, c.stream));
 }
 
-// Speculative end of step: behind a device gate (k_gate: every sim stopped, no
-// non-finite residual, candidate lists still cover r^{n+1}) queue the corrector
+// Speculative end of step: behind a device gate (spec_gate, evaluated by every
+// gated workgroup: every sim stopped, no non-finite residual, candidate lists
+// still cover r^{n+1}) queue the corrector
 // and, when another step follows, the next rate pass on the candidate lists, so
 // the GPU works while the host waits for the reports. When the gate is closed
 // these launches return at once and the host proceeds as without them.
 template <typename T> void launch_speculation(Ctx &c, bool next_pre)
 {
     c.tstats.spec_tries++;
-    launch_gate(c);
-    c.gate_use = c.gate;
+    c.gated = true;
     const bool p_half = c.p_half;
     c.p_half = true;  // state at the end of a loop: p^K is still pending
     launch_correct<T>(c);
@@ -787,7 +787,7 @@ template <typename T> void launch_speculation(Ctx &c, bool next_pre)
         launch_wall<T>(c, MODE_PRE, use_cand);
         launch_pass<T>(c, MODE_PRE, use_cand);
     }
-    c.gate_use = nullptr;
+    c.gated = false;
 }
 
 // The host's reading of the gate, from the published reports.
@@ -816,7 +816,8 @@ template <typename T> int do_step(Ctx &c, int n_steps, dtsph_iter_report *reps)
         }
         // speculate while it mostly pays (a closed gate costs a few no-op
         // launches); after a run of misses, probe again every 16 steps
-        L.spec = c.speculate && !c.any_shift && !c.graphs && (c.spec_score > 0 || ++c.spec_idle % 16 == 0);
+        L.spec = c.speculate && !c.any_shift && !c.graphs && c.n_sims <= 64 &&
+                 (c.spec_score > 0 || ++c.spec_idle % 16 == 0);
         L.spec_next = s + 1 < n_steps;
         if (L.spec) {
             launch_speculation<T>(c, L.spec_next);
@@ -1026,7 +1027,6 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         dev_alloc(c, c.seg_p, sizeof(double4) * max_segs);
         dev_alloc(c, c.seg_p2, sizeof(double2) * max_segs);
         dev_alloc(c, c.tickets, sizeof(uint32_t) * n_sims);
-        dev_alloc(c, c.gate, 16);
         dev_alloc(c, c.pubcount, sizeof(uint32_t) * n_sims);
         dev_alloc(c, c.partials2, sizeof(double2) * max_tiles);
         dev_alloc(c, c.flags, sizeof(int) * (F_COUNT + n_sims));

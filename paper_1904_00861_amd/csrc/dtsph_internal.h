@@ -196,8 +196,7 @@ struct Ctx {
     uint32_t *tickets = nullptr;          // per sim: segments of the running finalize done
     // speculative end of step (dtsph_step): the corrector and the next rate pass
     // are queued behind a device gate before the host reads the loop's reports
-    int *gate = nullptr;                  // 1: every sim stopped, lists still cover
-    const int *gate_use = nullptr;        // gate the next launches of these kernels
+    bool gated = false;                   // the next launches are speculative
     bool speculate = true, spec_ready = false;
     int spec_score = 4, spec_idle = 0;    // recent success of speculation (adaptive)
     double4 *partials = nullptr;
@@ -271,7 +270,6 @@ void launch_publish(Ctx &c);
 template <typename T> void launch_loop_begin(Ctx &c, int fixed_iters);
 template <typename T> void launch_move_begin(Ctx &c);
 template <typename T> void launch_correct(Ctx &c);
-void launch_gate(Ctx &c);
 template <typename T> void launch_shift(Ctx &c, bool cand_lists);  // sums, apply, max
 template <typename T> void launch_set_state(Ctx &c, const dtsph_state_view &s, bool in_loop);
 template <typename T> void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop);

@@ -101,6 +101,20 @@ template <int DIM> struct Pos<double, DIM> {
     }
 };
 
+// Gate of the speculative end of step, evaluated by each gated workgroup from
+// the loop states: every sim stopped without a non-finite residual and every
+// sim's candidate lists still hold all neighbours at r^{n+1} (the rule the host
+// applies to the same, published, values).
+__device__ inline bool spec_gate(int n_sims, const SimIter *__restrict__ iters, const SimDev *__restrict__ sims)
+{
+    bool go = true;
+    for (int s = 0; s < n_sims; ++s) {
+        const SimIter &It = iters[s];
+        go = go && It.done && It.reason != DTSPH_NONFINITE && sims[s].skin > 0 && It.disp < 0.4 * sims[s].skin;
+    }
+    return go;
+}
+
 template <typename T> struct PassConst {
     T inv_h, tiny, den_v, den_e, den_a, k_av;
     __device__ explicit PassConst(const SimDev &S)
@@ -278,7 +292,7 @@ template <typename T> struct PassArgs {
     T *vt;
     void *xr;
     int *flags;
-    const int *gate;  // non-null: run only if *gate (speculative launch)
+    int gated, n_sims;  // gated: run only if spec_gate holds (speculative launch)
 };
 
 template <typename T> __device__ inline int launch_tile(const PassArgs<T> &A, int v)
@@ -323,7 +337,7 @@ k_pass(PassArgs<T> A)
     using Rec = typename PosT::Rec;
     const int v = tile_of_block(A.n_tiles, A.remap);
     if (v < 0) return;
-    if (A.gate && !*A.gate) return;
+    if (A.gated && !spec_gate(A.n_sims, A.iters, A.sims)) return;
     const int t = launch_tile(A, v);
     const int2 tl = A.tiles[t];
     const int s = tl.x;
@@ -605,7 +619,7 @@ template <typename T> struct WallArgs {
     const void *prec;
     Q *vp0, *vp1;    // reads fluid records, writes wall records (same buffer)
     const void *prec2;  // position records of odd iterations of moving sims
-    const int *gate;    // non-null: run only if *gate (speculative launch)
+    int gated, n_sims;  // gated: run only if spec_gate holds (speculative launch)
     int cur;
     const T *vwall;
     T *pwall;
@@ -621,7 +635,7 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
     using Rec = typename PosT::Rec;
     const int iw = blockIdx.x * blockDim.x + threadIdx.x;
     if (iw >= A.Nw) return;
-    if (A.gate && !*A.gate) return;
+    if (A.gated && !spec_gate(A.n_sims, A.iters, A.sims)) return;
     const int i = A.Nf + iw;
     const int N = A.N;
     const int s = A.simid[i];
@@ -937,11 +951,12 @@ __global__ void k_correct(int N, int Nf, const int *__restrict__ simid, const Si
                           double *__restrict__ x, const double *__restrict__ xn, T *__restrict__ vn,
                           T *__restrict__ dv, T *__restrict__ w, void *__restrict__ xr, double *__restrict__ pm,
                           const T *__restrict__ dp, int half, void *__restrict__ prec,
-                          typename V4<T>::type *__restrict__ vrec, const int *__restrict__ gate)
+                          typename V4<T>::type *__restrict__ vrec, int gated, int n_sims,
+                          const SimIter *__restrict__ iters)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Nf) return;
-    if (gate && !*gate) return;
+    if (gated && !spec_gate(n_sims, iters, sims)) return;
     const SimDev &S = sims[simid[i]];
     double p = pm[i];
     if (half) {
@@ -1257,7 +1272,8 @@ template <typename T> PassArgs<T> pass_args(Ctx &c, int mode, bool cand_lists)
     a.coef = (Q *)c.coef;
     a.coef_av = c.coef_av;
     a.prec2 = c.prec2; a.xm = c.xm; a.vt = (T *)c.vt; a.xr = c.xr; a.flags = c.flags;
-    a.gate = c.gate_use;
+    a.gated = c.gated ? 1 : 0;
+    a.n_sims = c.n_sims;
     return a;
 }
 
@@ -1366,7 +1382,8 @@ void launch_wall(Ctx &c, int mode, bool cand_lists)
     a.vp0 = (Q *)c.vp[0];
     a.vp1 = (Q *)c.vp[1];
     a.prec2 = c.prec2;
-    a.gate = c.gate_use;
+    a.gated = c.gated ? 1 : 0;
+    a.n_sims = c.n_sims;
     a.cur = c.cur;
     a.vwall = (const T *)c.vw[b];
     a.pwall = (T *)c.pw[b];
@@ -1376,28 +1393,6 @@ void launch_wall(Ctx &c, int mode, bool cand_lists)
     else DTSPH_LAUNCH(c, (k_wall<T, 3>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
     DTSPH_HIP_CHECK(hipGetLastError());
     if (mode == MODE_PSEUDO) timer_end(c, t0, 1);
-}
-
-// Gate of the speculative end of step: 1 when every sim's loop has stopped
-// without a non-finite residual and every sim's candidate lists still hold all
-// neighbours at r^{n+1} (the rule the host applies to the same reports).
-__global__ void k_gate(int n_sims, const SimIter *__restrict__ iters, const SimDev *__restrict__ sims,
-                       int *__restrict__ gate)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int go = 1;
-    for (int s = 0; s < n_sims; ++s) {
-        const SimIter &It = iters[s];
-        const SimDev &S = sims[s];
-        go &= It.done && It.reason != DTSPH_NONFINITE && S.skin > 0 && It.disp < 0.4 * S.skin;
-    }
-    gate[0] = go;
-}
-
-void launch_gate(Ctx &c)
-{
-    DTSPH_LAUNCH(c, k_gate, dim3(1), dim3(64), 0, c.stream, c.n_sims, c.iters, c.sims, c.gate);
-    DTSPH_HIP_CHECK(hipGetLastError());
 }
 
 void launch_publish(Ctx &c)
@@ -1495,7 +1490,8 @@ void launch_correct(Ctx &c)
     using Q = typename V4<T>::type;
     DTSPH_LAUNCH(c, k_correct<T>, dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.N, c.Nf, c.simid[b], c.sims,
                        c.x[c.xb], c.xn[b], (T *)c.vn[b], (T *)c.dv[b], (T *)c.w[b], c.xr, c.pm[b],
-                       (const T *)c.dp[b], c.p_half ? 1 : 0, c.prec, (Q *)c.vp[c.cur], c.gate_use);
+                       (const T *)c.dp[b], c.p_half ? 1 : 0, c.prec, (Q *)c.vp[c.cur], c.gated ? 1 : 0, c.n_sims,
+                       c.iters);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
