@@ -305,7 +305,8 @@ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Position record of slot i read by the pair passes: FP32 path 32-bit fixed
 // point per axis, x_q = floor((x - lo) * q_inv) mod 2^32 (exact wrap on periodic
-// axes, whose q_len divides the period); FP64 path the float64 coordinates.
+// axes, whose q_len divides the period); FP64 path the float64 coordinates. Two
+// components in 2D (uint2 / double2), four in 3D (uint4 / double4).
 template <typename T>
 __device__ inline void write_pos_record(const SimDev &S, void *prec, int i, const double xi[3]);
 
@@ -317,14 +318,15 @@ __device__ inline void write_pos_record<float>(const SimDev &S, void *prec, int 
         double v = floor((xi[a] - S.lo[a]) * S.q_inv[a]);
         q[a] = (uint32_t)(unsigned long long)(long long)v;
     }
-    ((uint4 *)prec)[i] = make_uint4(q[0], q[1], q[2], 0u);
+    if (S.dim == 2) ((uint2 *)prec)[i] = make_uint2(q[0], q[1]);
+    else ((uint4 *)prec)[i] = make_uint4(q[0], q[1], q[2], 0u);
 }
 
 template <>
 __device__ inline void write_pos_record<double>(const SimDev &S, void *prec, int i, const double xi[3])
 {
-    (void)S;
-    ((double4 *)prec)[i] = make_double4(xi[0], xi[1], xi[2], 0.0);
+    if (S.dim == 2) ((double2 *)prec)[i] = make_double2(xi[0], xi[1]);
+    else ((double4 *)prec)[i] = make_double4(xi[0], xi[1], xi[2], 0.0);
 }
 
 }  // namespace dtsph

@@ -27,6 +27,8 @@
 // the same XCD so that neighbouring tiles share that XCD's L2.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "dtsph_internal.h"
 
 namespace dtsph {
@@ -59,11 +61,12 @@ template <typename T, int DIM> __device__ inline typename V4<T>::type make_rec(c
     return r;
 }
 
-// Position records and separations r_i - r_j.
+// Position records and separations r_i - r_j. In 2D a record is two words
+// (8 B in FP32, 16 B in FP64), so a gather touches half as many cache lines.
 template <typename T, int DIM> struct Pos;
 
 template <int DIM> struct Pos<float, DIM> {
-    using Rec = uint4;
+    using Rec = typename std::conditional<DIM == 2, uint2, uint4>::type;
     float step[3];
     __device__ explicit Pos(const SimDev &S)
     {
@@ -73,12 +76,13 @@ template <int DIM> struct Pos<float, DIM> {
     {
         r[0] = (float)(int)(a.x - b.x) * step[0];
         r[1] = (float)(int)(a.y - b.y) * step[1];
-        r[2] = DIM == 3 ? (float)(int)(a.z - b.z) * step[2] : 0.0f;
+        if constexpr (DIM == 3) r[2] = (float)(int)(a.z - b.z) * step[2];
+        else r[2] = 0.0f;
     }
 };
 
 template <int DIM> struct Pos<double, DIM> {
-    using Rec = double4;
+    using Rec = typename std::conditional<DIM == 2, double2, double4>::type;
     double L[3], halfL[3];
     int per[3];
     __device__ explicit Pos(const SimDev &S)
@@ -97,7 +101,8 @@ template <int DIM> struct Pos<double, DIM> {
     {
         r[0] = mi(a.x - b.x, 0);
         r[1] = mi(a.y - b.y, 1);
-        r[2] = DIM == 3 ? mi(a.z - b.z, 2) : 0.0;
+        if constexpr (DIM == 3) r[2] = mi(a.z - b.z, 2);
+        else r[2] = 0.0;
     }
 };
 
