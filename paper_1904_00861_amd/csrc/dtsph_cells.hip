@@ -449,6 +449,22 @@ __device__ __forceinline__ void scan_run(const typename XR<DIM>::type *__restric
                 if (in_x && cur.total < cap) nbr[(size_t)cur.total * N] = j;
                 cur.ctotal += in_c;
                 cur.total += in_x;
+            } else if (G == 2) {
+                // the partner lane's two hits by one lane swap (DPP quad_perm 1,0,3,2);
+                // both lanes of a group are always active here
+                const int h = (int)in_c | ((int)in_x << 1);
+                const int o = __builtin_amdgcn_update_dpp(0, h, 0xB1, 0xF, 0xF, false);
+                const int oc = o & 1, ox = o >> 1;
+                if (in_c) {  // entry offsets are non-negative: one 32 x 32 -> 64 bit multiply
+                    const int qq = cur.ctotal + (grp.sub ? oc : 0);
+                    if (qq < capc) cand[(size_t)(unsigned)qq * (unsigned)N] = j;
+                }
+                if (in_x) {
+                    const int qq = cur.total + (grp.sub ? ox : 0);
+                    if (qq < cap) nbr[(size_t)(unsigned)qq * (unsigned)N] = j;
+                }
+                cur.ctotal += (int)in_c + oc;
+                cur.total += (int)in_x + ox;
             } else {
                 const unsigned bc = grp.bits(in_c), bx = grp.bits(in_x);
                 if (in_c) {
