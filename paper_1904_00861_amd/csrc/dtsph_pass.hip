@@ -1048,36 +1048,56 @@ __global__ void __launch_bounds__(256) k_shift_sums(ShiftArgs<T> A)
             const uint32_t cn = A.cnt[i];
             const int total = (int)(cn & 0xffffu) + (int)(cn >> 16);
             const int *__restrict__ nb = A.nbr + i;
-            for (int k = sub; k < total; k += SL) {
-                const int j = nb[(size_t)k * A.N];
-                T r[3];
-                pos.delta(ri, prec[j], r);
-                T r2 = r[0] * r[0] + r[1] * r[1];
-                if (DIM == 3) r2 += r[2] * r[2];
-                if (!(r2 > T(0))) continue;
-                const T rinv = rsq<T>(r2);
-                const T q = r2 * rinv * inv_h;
-                T t3 = T(3) - q, t2 = T(2) - q, t1 = T(1) - q;
-                t3 = t3 > T(0) ? t3 : T(0);
-                t2 = t2 > T(0) ? t2 : T(0);
-                t1 = t1 > T(0) ? t1 : T(0);
-                const T a4 = t3 * t3 * t3 * t3, b4 = t2 * t2 * t2 * t2, c4 = t1 * t1 * t1 * t1;
-                const T f = kg * (T(15) * c4 + (T(-6) * b4 + a4)) * rinv;  // dW/dr / r
-                const T w5 = T(15) * c4 * t1 + (T(-6) * b4 * t2 + a4 * t3);
-                divr -= vol * f * r2;
-                const T ratio = w5 * T(1.0 / 26.0);  // W / W(h): w(1) = 2^5 - 6 = 26
-                T pw = T(1);
-                for (int e = 0; e < nexp; ++e) pw *= ratio;
-                const T cf = vol * (T(1) + rco * pw) * f;
-                for (int a = 0; a < DIM; ++a) sd[a] += cf * r[a];
-                if (j < A.Nf) {
-                    const Q vj = A.vrec[j];
-                    const T cp = vol * (pres<DIM>(vj) - pi) * f;
-                    const T vjv[3] = {vj.x, vj.y, DIM == 3 ? vj.z : T(0)};
-                    for (int a = 0; a < DIM; ++a) gp[a] += cp * r[a];
-                    for (int b = 0; b < DIM; ++b) {
-                        const T cv = vol * (vjv[b] - vi[b]) * f;
-                        for (int a = 0; a < DIM; ++a) gv[b][a] += cv * r[a];
+            // neighbours in batches of U per lane: U index loads, then 2U record
+            // gathers in flight, then U pair evaluations (each lane keeps its
+            // own summation order: entries sub, sub + SL, ...)
+            constexpr int U = sizeof(T) == 4 ? 4 : 2;
+            for (int k0 = sub; k0 < total; k0 += U * SL) {
+                int jj[U];
+#pragma unroll
+                for (int m = 0; m < U; ++m) {
+                    const int k = k0 + m * SL;
+                    jj[m] = k < total ? nb[(size_t)k * A.N] : i;
+                }
+                Rec rj[U];
+                Q vq[U];
+#pragma unroll
+                for (int m = 0; m < U; ++m) {
+                    rj[m] = prec[jj[m]];
+                    vq[m] = A.vrec[jj[m]];
+                }
+#pragma unroll
+                for (int m = 0; m < U; ++m) {
+                    const int j = jj[m];
+                    T r[3];
+                    pos.delta(ri, rj[m], r);
+                    T r2 = r[0] * r[0] + r[1] * r[1];
+                    if (DIM == 3) r2 += r[2] * r[2];
+                    if (!(r2 > T(0))) continue;  // itself (padding) or a coincident particle
+                    const T rinv = rsq<T>(r2);
+                    const T q = r2 * rinv * inv_h;
+                    T t3 = T(3) - q, t2 = T(2) - q, t1 = T(1) - q;
+                    t3 = t3 > T(0) ? t3 : T(0);
+                    t2 = t2 > T(0) ? t2 : T(0);
+                    t1 = t1 > T(0) ? t1 : T(0);
+                    const T a4 = t3 * t3 * t3 * t3, b4 = t2 * t2 * t2 * t2, c4 = t1 * t1 * t1 * t1;
+                    const T f = kg * (T(15) * c4 + (T(-6) * b4 + a4)) * rinv;  // dW/dr / r
+                    const T w5 = T(15) * c4 * t1 + (T(-6) * b4 * t2 + a4 * t3);
+                    divr -= vol * f * r2;
+                    const T ratio = w5 * T(1.0 / 26.0);  // W / W(h): w(1) = 2^5 - 6 = 26
+                    T pw = T(1);
+                    for (int e = 0; e < nexp; ++e) pw *= ratio;
+                    const T cf = vol * (T(1) + rco * pw) * f;
+                    for (int a = 0; a < DIM; ++a) sd[a] += cf * r[a];
+                    if (j < A.Nf) {
+                        const Q vj = vq[m];
+                        const T cp = vol * (pres<DIM>(vj) - pi) * f;
+                        const T vjv[3] = {vj.x, vj.y, DIM == 3 ? vj.z : T(0)};
+                        for (int a = 0; a < DIM; ++a) gp[a] += cp * r[a];
+                        for (int b = 0; b < DIM; ++b) {
+                            const T cv = vol * (vjv[b] - vi[b]) * f;
+                            for (int a = 0; a < DIM; ++a) gv[b][a] += cv * r[a];
+                        }
                     }
                 }
             }
