@@ -509,6 +509,47 @@ void set_active_ranges(Ctx &c, bool all)
     for (int q = 0; q < n; ++q) c.ranges[q] = r[q];
 }
 
+// Do the candidate lists cover the shifted positions? (the loop's move plus the
+// largest shift within 0.4 skin for every sim)
+bool shift_cand_ok(const Ctx &c, double mx, bool use_cand, const std::vector<double> &disp)
+{
+    bool ok = true;
+    for (int s = 0; s < c.n_sims; ++s) {
+        const double moved = (use_cand ? disp[s] : 0.0) + mx;
+        ok = ok && c.sims_h[s].skin > 0 && moved < 0.4 * c.sims_h[s].skin;
+    }
+    return ok;
+}
+
+void shift_outcome(Ctx &c, bool ok)
+{
+    c.shift_miss = ok ? 0 : c.shift_miss + 1;
+    c.shift_nosync = c.shift_miss >= 3;
+}
+
+// After the shift kernels: the next rate pass may run on the candidate lists
+// only if they cover the shifted positions, which needs the largest shift read
+// back (a stream sync). After three steps in a row whose shifts left the skin,
+// the sync is skipped and a rebuild taken; the value is read at the next wait
+// (free by then), and a shift back inside the skin resumes the check.
+void shift_decision(Ctx &c, bool use_cand)
+{
+    if (c.shift_nosync) {
+        c.cand_ok = false;
+        c.shift_pending = true;
+        c.shift_pending_cand = use_cand;
+        c.shift_disp = c.last_disp;
+    } else {
+        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+        const double mx = *(volatile double *)c.sh_max_h;
+        c.tstats.last_max_shift = mx;
+        c.cand_ok = shift_cand_ok(c, mx, use_cand, c.last_disp);
+        shift_outcome(c, c.cand_ok);
+    }
+    c.cells_valid = false;
+    c.records_fresh = true;  // k_shift_apply rewrote the records
+}
+
 // A pseudo-time loop: set-up, chunks of iterations with a stop check after each,
 // and the bookkeeping at its end.
 struct LoopRun {
@@ -591,6 +632,12 @@ template <typename T> int loop_finish(Ctx &c, LoopRun &L, dtsph_iter_report *rep
     for (;;) {
         wait_reports(c);  // k_finalize wrote the mapped reports
         check_host_flags(c);
+        if (c.shift_pending) {  // the last shift has finished: book its size
+            c.shift_pending = false;
+            const double mx = *(volatile double *)c.sh_max_h;
+            c.tstats.last_max_shift = mx;
+            shift_outcome(c, shift_cand_ok(c, mx, c.shift_pending_cand, c.shift_disp));
+        }
         bool all = true;
         for (int s = 0; s < c.n_sims; ++s) all = all && c.flags_host[F_COUNT + s];
         if (all || L.launched >= L.max_it) break;
@@ -670,17 +717,7 @@ template <typename T> void do_shift(Ctx &c)
         launch_pre_records<T>(c);
     }
     launch_shift<T>(c, use_cand);
-    DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
-    const double mx = *(volatile double *)c.sh_max_h;
-    c.tstats.last_max_shift = mx;
-    bool ok = true;
-    for (int s = 0; s < c.n_sims; ++s) {
-        const double moved = (use_cand ? c.last_disp[s] : 0.0) + mx;
-        ok = ok && c.sims_h[s].skin > 0 && moved < 0.4 * c.sims_h[s].skin;
-    }
-    c.cand_ok = ok;
-    c.cells_valid = false;
-    c.records_fresh = true;  // k_shift_apply rewrote the records
+    shift_decision(c, use_cand);
 }
 
 template <typename T> void do_correct(Ctx &c)
@@ -780,6 +817,7 @@ template <typename T> void launch_speculation(Ctx &c, bool next_pre)
     c.p_half = true;  // state at the end of a loop: p^K is still pending
     launch_correct<T>(c);
     c.p_half = p_half;
+    if (c.any_shift) launch_shift<T>(c, true);  // the gate implies valid candidate lists
     if (next_pre) {
         // after the corrector the records are fresh; the lists are those of
         // r^(0) (candidates) or, for steady contexts, still exact
@@ -816,9 +854,8 @@ template <typename T> int do_step(Ctx &c, int n_steps, dtsph_iter_report *reps)
         }
         // speculate while it mostly pays (a closed gate costs a few no-op
         // launches); after a run of misses, probe again every 16 steps
-        L.spec = c.speculate && !c.any_shift && !c.graphs && c.n_sims <= 64 &&
-                 (c.spec_score > 0 || ++c.spec_idle % 16 == 0);
-        L.spec_next = s + 1 < n_steps;
+        L.spec = c.speculate && !c.graphs && c.n_sims <= 64 && (c.spec_score > 0 || ++c.spec_idle % 16 == 0);
+        L.spec_next = s + 1 < n_steps && !c.any_shift;  // shifting: the rate pass waits for the shift's size
         if (L.spec) {
             launch_speculation<T>(c, L.spec_next);
             L.tries++;
@@ -837,6 +874,7 @@ template <typename T> int do_step(Ctx &c, int n_steps, dtsph_iter_report *reps)
             c.cand_ok = c.cand_next;
             c.p_half = false;
             c.records_fresh = true;
+            if (c.any_shift) shift_decision(c, true);  // the gated shift ran on the candidate lists
             if (L.spec_next) {
                 c.xb ^= 1;
                 c.in_loop = true;

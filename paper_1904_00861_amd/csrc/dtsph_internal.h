@@ -199,6 +199,11 @@ struct Ctx {
     bool gated = false;                   // the next launches are speculative
     bool speculate = true, spec_ready = false;
     int spec_score = 4, spec_idle = 0;    // recent success of speculation (adaptive)
+    // after shifting: skip the read-back of the largest shift while shifts keep
+    // leaving the candidate skin (checked later, at the next wait)
+    int shift_miss = 0;
+    bool shift_nosync = false, shift_pending = false, shift_pending_cand = false;
+    std::vector<double> shift_disp;
     double4 *partials = nullptr;
     double2 *partials2 = nullptr;         // per tile: max |V^{k+1} - V^(0)|^2, pairs
     int *flags = nullptr;

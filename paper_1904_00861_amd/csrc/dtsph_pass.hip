@@ -1017,6 +1017,8 @@ template <typename T> struct ShiftArgs {
     void *xr;
     T *vn, *vdiff;      // V^{n+1}; V^{n+1} - V^n
     double *pm;
+    int gated, n_sims;  // gated: run only if spec_gate holds (speculative launch)
+    const SimIter *iters;
 };
 
 // SL lanes share one particle (list entries sub, sub + SL, ...), combined by
@@ -1028,6 +1030,7 @@ __global__ void __launch_bounds__(256) k_shift_sums(ShiftArgs<T> A)
     using PosT = Pos<T, DIM>;
     using Rec = typename PosT::Rec;
     __shared__ double lds[4];
+    if (A.gated && !spec_gate(A.n_sims, A.iters, A.sims)) return;  // uniform in the grid
     const int sub = (int)threadIdx.x & (SL - 1);
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) / SL;
     double m2 = 0.0;
@@ -1138,6 +1141,7 @@ __global__ void __launch_bounds__(256) k_shift_apply(ShiftArgs<T> A)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.Nf) return;
+    if (A.gated && !spec_gate(A.n_sims, A.iters, A.sims)) return;
     const SimDev &S = A.sims[A.simid[i]];
     if (!S.shift) return;
     const int N = A.N, Nf = A.Nf;
@@ -1165,8 +1169,11 @@ __global__ void __launch_bounds__(256) k_shift_apply(ShiftArgs<T> A)
 }
 
 // Largest shift of the launch into mapped memory (one workgroup).
-__global__ void __launch_bounds__(256) k_shift_max(const double *__restrict__ part, int n, double *out)
+__global__ void __launch_bounds__(256) k_shift_max(const double *__restrict__ part, int n, double *out, int gated,
+                                                   int n_sims, const SimIter *__restrict__ iters,
+                                                   const SimDev *__restrict__ sims)
 {
+    if (gated && !spec_gate(n_sims, iters, sims)) return;
     __shared__ double lds[4];
     double m = 0.0;
     for (int k = threadIdx.x; k < n; k += 256) m = fmax(m, part[k]);
@@ -1535,6 +1542,7 @@ void launch_shift(Ctx &c, bool cand_lists)
     a.dr = c.sh_dr; a.dp = c.sh_dp; a.dv = (T *)c.sh_dv; a.part = c.sh_part;
     a.x = c.x[c.xb]; a.xr = c.xr;
     a.vn = (T *)c.vn[b]; a.vdiff = (T *)c.dv[b]; a.pm = c.pm[b];
+    a.gated = c.gated ? 1 : 0; a.n_sims = c.n_sims; a.iters = c.iters;
     // lanes per particle: 4 for the ~110 neighbours of 3D, 2 for the ~26 of 2D
     const int nblk = grid_for(c.Nf), nsum = grid_for(c.Nf * (c.max_dim == 2 ? 2 : 4));
     if (c.max_dim == 2) {
@@ -1544,7 +1552,8 @@ void launch_shift(Ctx &c, bool cand_lists)
         DTSPH_LAUNCH(c, (k_shift_sums<T, 3, 4>), dim3(nsum), dim3(256), 0, c.stream, a);
         DTSPH_LAUNCH(c, (k_shift_apply<T, 3>), dim3(nblk), dim3(256), 0, c.stream, a);
     }
-    DTSPH_LAUNCH(c, k_shift_max, dim3(1), dim3(256), 0, c.stream, c.sh_part, nsum, c.sh_max_d);
+    DTSPH_LAUNCH(c, k_shift_max, dim3(1), dim3(256), 0, c.stream, c.sh_part, nsum, c.sh_max_d, c.gated ? 1 : 0,
+                 c.n_sims, c.iters, c.sims);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 

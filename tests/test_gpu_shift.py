@@ -106,3 +106,30 @@ def test_batch_with_mixed_shifting_matches_solo_runs():
         assert rel_l2(gb["v"][sl[s]][:nf], g["v"][:nf]) <= 1e-5
         assert rel_l2(gb["p"][sl[s]][:nf], g["p"][:nf]) <= 1e-5
         assert [x[0]["iters"] for x in r] == [x[s]["iters"] for x in reps]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_shifts_beyond_a_tiny_skin_match_oracle(prec):
+    # a skin of 0.001 h: every shift leaves it, so after three steps the
+    # library stops reading the largest shift back and rebuilds unconditionally
+    prob = CASES["tgv2d_30"]()
+    banner(f"shifted steps beyond a tiny skin {prec}")
+    nf = prob.n_fluid
+    x, v, vp, p, oreps, _ = oracle_steps(prob, 7)
+    sim = D.Sim(prob, precision=PREC[prec])
+    sim.set_option(D.OPT_SKIN, 1)
+    st, greps = sim.step(7)
+    g = sim.get_state()
+    tm = sim.timing()
+    sim.close()
+    assert tm["full_builds"] >= 2 * 7 - 1  # a rebuild after every shift
+    gi, oi = [r[0]["iters"] for r in greps], [r["iters"] for r in oreps]
+    t = TOL_STEPS[prec]
+    if prec == "fp64":
+        assert gi == oi
+    else:
+        assert all(abs(a - b) <= 1 for a, b in zip(gi, oi))
+    loose = 1.0 if gi == oi else 20.0
+    assert rel_l2(g["v"][:nf], v[:nf]) <= t["v"] * loose
+    assert rel_l2(g["p"][:nf], p[:nf]) <= t["p"] * loose
+    assert np.abs(g["x"] - x).max() <= t["x"] * loose

@@ -2,7 +2,7 @@
 corrector and the next rate pass queued behind the device gate gives the same
 bits as without, whether the gate opens (converged sims, valid candidate
 lists) or stays closed (tiny skin, loops needing more chunks), for single
-sims, batches, steady and moving sims, with timing on."""
+sims, batches, steady, moving and shifting sims, with timing on."""
 import numpy as np
 import pytest
 
@@ -27,6 +27,8 @@ CASES = {
     "tgv2d_30_move2": lambda: _with(I.tgv2d(30, seed=7), move=2),
     "dam_0.05": lambda: I.dam_break(0.05),
     "tgv3d_8": lambda: I.tgv3d(8, seed=3),
+    "tgv2d_30_shift": lambda: _with(I.tgv2d(30, seed=6, jitter=0.1), shift=1),
+    "dam_0.05_shift": lambda: _with(I.dam_break(0.05), shift=1),
 }
 
 
