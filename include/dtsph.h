@@ -363,14 +363,15 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
                                   16 / 32 B in 3D), which adds to
                                   dtsph_workspace_bytes; between steps only. */
 #define DTSPH_OPT_SPECULATE 12 /* 1 (default): dtsph_step queues the corrector
-                                  and the next step's rate pass behind a device
-                                  gate (every sim stopped, no non-finite
-                                  residual, candidate lists still valid)
-                                  before it waits for the loop's reports; when
-                                  the gate is closed they do nothing and the
-                                  step ends as with 0. Off for contexts with
-                                  shifting or graphs or more than 64 sims, and
-                                  while recent gates mostly stayed closed.
+                                  and the next step's rate pass (with shifting:
+                                  the shift kernels instead of the rate pass)
+                                  behind a device gate (every sim stopped, no
+                                  non-finite residual, candidate lists still
+                                  valid) before it waits for the loop's
+                                  reports; when the gate is closed they do
+                                  nothing and the step ends as with 0. Off for
+                                  contexts with graphs or more than 64 sims,
+                                  and while recent gates mostly stayed closed.
                                   Results are identical.                      */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
