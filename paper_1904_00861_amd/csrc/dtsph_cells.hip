@@ -364,7 +364,8 @@ template <int G> struct Group {
 
 // Candidates are taken U at a time per lane: all U position loads are in
 // flight before the first test, and list writes happen after the batch.
-constexpr int kBatch = 8;
+constexpr int kBatch = 8;   // the filter
+constexpr int kBatchNbr = 4;  // the neighbour kernel (more in flight costs occupancy)
 
 template <int DIM> struct Probe {
     double xi, yi, zi, kh2;
@@ -407,7 +408,7 @@ struct ListCursor {
 };
 
 // Tests the candidates in slots [jb, je) (one run of consecutive cells), G
-// lanes at a time with kBatch positions per lane in flight, and appends the
+// lanes at a time with kBatchNbr positions per lane in flight, and appends the
 // hits to the exact and candidate lists in scan order. GENERAL: minimum image
 // per candidate (needed when a periodic axis has fewer than 2m+3 cells);
 // otherwise the run's periodic shift (sx, sy, sz) applies to all of it.
@@ -418,7 +419,7 @@ __device__ __forceinline__ void scan_run(const typename XR<DIM>::type *__restric
                                          const Group<G> &grp, ListCursor &cur)
 {
     using Q = typename XR<DIM>::type;
-    constexpr int kB = DIM == 2 ? kBatch : kBatch / 2;  // 3D records are twice as wide
+    constexpr int kB = kBatchNbr;
     if (jb >= je) return;
     // software pipeline: the next batch's positions are in flight while the
     // current batch is tested
@@ -492,8 +493,10 @@ __device__ __forceinline__ void scan_run(const typename XR<DIM>::type *__restric
 // Off the GENERAL path a row's x-run is trimmed to the cells the candidate
 // sphere reaches there: with d the distance from the particle to the row's
 // y (and z) slab, only |x_j - x_i| <= sqrt(R^2 - d^2) can hold a candidate.
-// Edge cells of a non-periodic axis hold the particles clamped into them, so
-// their slab is open on the outer side; a margin of 1e-7 h covers rounding.
+// The trimming runs in float in cell units relative to the particle's cell,
+// widened by 1e-5 cells (far above its rounding), so it never drops a cell
+// the float64 predicate could accept. Edge cells of a non-periodic axis hold
+// the particles clamped into them, so their extent is open on the outer side.
 template <typename T, int DIM, int G, bool GENERAL>
 __device__ __forceinline__ void scan_block(const NbrArgs<T> &A, const SimDev &S, int i, const Probe<DIM> &P,
                                            int cx, int cy, int cz, bool fluid, int &cf, int &cw, int &ccf,
@@ -514,50 +517,62 @@ __device__ __forceinline__ void scan_block(const NbrArgs<T> &A, const SimDev &S,
     else { xa0 = cx > md ? cx - md : 0; xb0 = cx < nx - 1 - md ? cx + md : nx - 1; }
     const AxisRange ry(cy, ny, P.py, md), rz(cz, nz, P.pz, DIM == 3 ? md : 0);
     const int ntp = (fluid && S.nw > 0) ? 2 : 1;  // wall cells only where walls exist
-    const int per_tp = rz.count * ry.count;
-    const int nrows = ntp * per_tp;
+    const int nrows = ntp * rz.count * ry.count;
     int *__restrict__ nbr = A.nbr + i;
     int *__restrict__ cand = A.cand + i;
     const double cr2 = S.cand_r2;
-    const double tol = 1e-7 * S.h;
-    auto row_key = [&](int r, int &u, int &v, int &tp) {
-        tp = r >= per_tp;
-        const int rr = r - tp * per_tp;
-        u = rr / ry.count;
-        v = rr - u * ry.count;
-        return S.key_base + (tp ? A.C : 0) + (rz.at(u) * ny + ry.at(v)) * nx;
+    // the particle in cell units from the low corner of its own cell, clamped to
+    // a range that decides every row and window the same way as the exact value
+    auto frac = [&](double p, int a, int c) {
+        const double f = (p - S.lo[a]) * S.inv_cs[a] - (double)c;
+        const double lim = (double)md + 3.0;
+        return (float)(f < -lim ? -lim : (f > lim + 1.0 ? lim + 1.0 : f));
     };
-    // distance from the particle to a row's slab along axis a (block index k)
-    auto slab_d = [&](const AxisRange &ra, int k, int a, double pa, double La, int per) {
+    const float fx = GENERAL ? 0.f : frac(P.xi, 0, cx);
+    const float fy = GENERAL ? 0.f : frac(P.yi, 1, cy);
+    const float fz = (GENERAL || DIM == 2) ? 0.f : frac(P.zi, 2, cz);
+    const float csy = (float)S.cs[1], csz = (float)S.cs[2], icsx = (float)S.inv_cs[0];
+    const float cr2f = (float)cr2;
+    // distance (physical units, shortened by 1e-5 cells) from the particle to
+    // the slab of block row k along an axis
+    auto slab_d = [&](const AxisRange &ra, int k, int c_own, float f, int per, float cs) {
         const int c = ra.at(k);
-        double lo = S.lo[a] + (double)c * S.cs[a] - ra.shift(k, La);
-        double hi = lo + S.cs[a];
-        if (!per && c == 0) lo = -INFINITY;
-        if (!per && c == ra.n - 1) hi = INFINITY;
-        const double d = fmax(0.0, fmax(lo - pa, pa - hi)) - tol;
-        return d > 0.0 ? d : 0.0;
+        const float o = (float)(ra.first + k - c_own);  // the slab is [o, o + 1) in cell units
+        const float below = (!per && c == 0) ? 0.f : o - f;
+        const float above = (!per && c == ra.n - 1) ? 0.f : f - (o + 1.f);
+        const float d = fmaxf(below, above) - 1e-5f;
+        return d > 0.f ? d * cs : 0.f;
     };
     // the row's runs: [a0, b0] unshifted, [a1, b1] with shift s1 (b < a: empty)
     auto row_runs = [&](int u, int v, int &a0, int &b0, int &a1, int &b1, double &s1) {
         a0 = xa0; b0 = xb0; a1 = xa1; b1 = xb1; s1 = sx1;
         if (GENERAL) return;
-        const double dy = slab_d(ry, v, 1, P.yi, P.Ly, P.py);
-        const double dz = DIM == 3 ? slab_d(rz, u, 2, P.zi, P.Lz, P.pz) : 0.0;
-        const double rem = cr2 - (dy * dy + dz * dz);
-        if (rem < 0.0) { b0 = a0 - 1; b1 = a1 - 1; return; }
-        const double w = sqrt(rem) + tol;
-        int lo_c = (int)floor((P.xi - w - S.lo[0]) * S.inv_cs[0]);
-        int hi_c = (int)floor((P.xi + w - S.lo[0]) * S.inv_cs[0]);
+        const float dy = slab_d(ry, v, cy, fy, P.py, csy);
+        const float dz = DIM == 3 ? slab_d(rz, u, cz, fz, P.pz, csz) : 0.f;
+        const float rem = cr2f - (dy * dy + dz * dz);
+        if (rem < 0.f) { b0 = a0 - 1; b1 = a1 - 1; return; }
+        const float wc = sqrtf(rem) * icsx + 1e-5f;
+        int lo_c = cx + (int)floorf(fx - wc);
+        int hi_c = cx + (int)floorf(fx + wc);
         lo_c = lo_c > cx - md ? lo_c : cx - md;
         hi_c = hi_c < cx + md ? hi_c : cx + md;
-        a0 = lo_c > 0 ? lo_c : 0;
-        b0 = hi_c < nx - 1 ? hi_c : nx - 1;
-        a1 = 0; b1 = -1; s1 = 0.0;
-        if (P.px && lo_c < 0) { a1 = nx + lo_c; b1 = nx - 1; s1 = P.Lx; }
-        else if (P.px && hi_c > nx - 1) { a1 = 0; b1 = hi_c - nx; s1 = -P.Lx; }
+        if (P.px) {
+            a0 = lo_c > 0 ? lo_c : 0;
+            b0 = hi_c < nx - 1 ? hi_c : nx - 1;
+            a1 = 0; b1 = -1; s1 = 0.0;
+            if (lo_c < 0) { a1 = nx + lo_c; b1 = nx - 1; s1 = P.Lx; }
+            else if (hi_c > nx - 1) { a1 = 0; b1 = hi_c - nx; s1 = -P.Lx; }
+        } else {
+            // edge cells extend outwards: a window beyond the grid still meets them
+            a0 = lo_c < 0 ? 0 : (lo_c > nx - 1 ? nx - 1 : lo_c);
+            b0 = hi_c < 0 ? 0 : (hi_c > nx - 1 ? nx - 1 : hi_c);
+        }
     };
-    int u, v, tp;
-    int row = row_key(0, u, v, tp);
+    auto row_key = [&](int u, int v, int tp) {
+        return S.key_base + (tp ? A.C : 0) + (rz.at(u) * ny + ry.at(v)) * nx;
+    };
+    int u = 0, v = 0, tp = 0;
+    int row = row_key(u, v, tp);
     int a0, c0, a1, c1;
     double s1;
     row_runs(u, v, a0, c0, a1, c1, s1);
@@ -570,7 +585,11 @@ __device__ __forceinline__ void scan_block(const NbrArgs<T> &A, const SimDev &S,
         const int jb0 = b0, je0 = e0, jb1 = b1, je1 = e1;
         const double rs1 = s1;
         if (r + 1 < nrows) {  // prefetch the next row's bounds
-            row = row_key(r + 1, u, v, tp);
+            if (++v == ry.count) {
+                v = 0;
+                if (++u == rz.count) { u = 0; ++tp; }
+            }
+            row = row_key(u, v, tp);
             row_runs(u, v, a0, c0, a1, c1, s1);
             b0 = e0 = b1 = e1 = 0;
             if (c0 >= a0) { b0 = (int)cstart[row + a0]; e0 = (int)cstart[row + c0 + 1]; }

@@ -38,6 +38,17 @@ def _dam_outside():
     return prob
 
 
+def _dam_beyond_x():
+    # pairs of particles beyond both x ends of the grid box (clamped into its
+    # edge columns), each pair closer than kappa h
+    prob = I.dam_break(0.05)
+    prob.x[0, :2] = [4.6, 1.0]
+    prob.x[1, :2] = [4.65, 1.02]
+    prob.x[2, :2] = [-0.6, 1.5]
+    prob.x[3, :2] = [-0.62, 1.55]
+    return prob
+
+
 def _perfect():
     return I.tgv2d(20, jitter=0.0)
 
@@ -51,6 +62,7 @@ CASES = {
     "cavity_16": lambda: I.cavity(16),
     "dam_0.05": lambda: I.dam_break(0.05),
     "dam_outside": _dam_outside,
+    "dam_beyond_x": _dam_beyond_x,
     "tank_10": lambda: I.hydrostatic_tank(10),
 }
 
