@@ -1414,6 +1414,21 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
         hipEvent_t e0, e1;
         DTSPH_HIP_CHECK(hipEventCreate(&e0));
         DTSPH_HIP_CHECK(hipEventCreate(&e1));
+        // time per launch: the best of three windows of `reps` launches (one
+        // window can be stretched by other work on the device)
+        auto time_us = [&](auto &&launch) {
+            double best_us = 1e300;
+            for (int w = 0; w < 3; ++w) {
+                float ms = 0.f;
+                DTSPH_HIP_CHECK(hipEventRecord(e0, c.stream));
+                for (int r = 0; r < reps; ++r) launch();
+                DTSPH_HIP_CHECK(hipEventRecord(e1, c.stream));
+                DTSPH_HIP_CHECK(hipEventSynchronize(e1));
+                DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                best_us = std::min(best_us, 1e3 * (double)ms / reps);
+            }
+            return best_us;
+        };
         dtsph_tune_report rep{};
         // cell subdivision: time full builds (sort + lists; they only reorder the state)
         {
@@ -1422,18 +1437,11 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
             for (int m = 1; m <= 3; ++m) {
                 setup_keys(c, m);
                 DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
-                float ms = 0.f;
-                by_precision(c, [&](auto t) {
+                const double us = by_precision(c, [&](auto t) {
                     using T = decltype(t);
                     build_cells<T>(c);
-                    DTSPH_HIP_CHECK(hipEventRecord(e0, c.stream));
-                    for (int r = 0; r < reps; ++r) build_cells<T>(c);
-                    DTSPH_HIP_CHECK(hipEventRecord(e1, c.stream));
-                    return 0;
+                    return time_us([&] { build_cells<T>(c); });
                 });
-                DTSPH_HIP_CHECK(hipEventSynchronize(e1));
-                DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-                const double us = 1e3 * ms / reps;
                 if (us < best) { best = us; best_m = m; }
             }
             setup_keys(c, best_m);
@@ -1457,18 +1465,11 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
                 c.lpp = lanes[li];
                 c.block = blocks[bi];
                 setup_tiles(c);
-                float ms = 0.f;
-                by_precision(c, [&](auto t) {
+                const double us = by_precision(c, [&](auto t) {
                     using T = decltype(t);
                     launch_pass<T>(c, MODE_PRE);  // warm-up
-                    DTSPH_HIP_CHECK(hipEventRecord(e0, c.stream));
-                    for (int r = 0; r < reps; ++r) launch_pass<T>(c, MODE_PRE);
-                    DTSPH_HIP_CHECK(hipEventRecord(e1, c.stream));
-                    return 0;
+                    return time_us([&] { launch_pass<T>(c, MODE_PRE); });
                 });
-                DTSPH_HIP_CHECK(hipEventSynchronize(e1));
-                DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-                const double us = 1e3 * ms / reps;
                 rep.entries[rep.n_entries++] = dtsph_tune_entry{c.lpp, c.block, us};
                 if (us < rep.us) {
                     rep.us = us;
@@ -1486,18 +1487,11 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
             int best_g = 1;
             for (int g = 1; g <= 8; g *= 2) {
                 (f ? c.g_filter : c.g_nbr) = g;
-                float ms = 0.f;
-                by_precision(c, [&](auto t) {
+                const double us = by_precision(c, [&](auto t) {
                     using T = decltype(t);
                     launch_nbr_lists<T>(c, f == 1);
-                    DTSPH_HIP_CHECK(hipEventRecord(e0, c.stream));
-                    for (int r = 0; r < reps; ++r) launch_nbr_lists<T>(c, f == 1);
-                    DTSPH_HIP_CHECK(hipEventRecord(e1, c.stream));
-                    return 0;
+                    return time_us([&] { launch_nbr_lists<T>(c, f == 1); });
                 });
-                DTSPH_HIP_CHECK(hipEventSynchronize(e1));
-                DTSPH_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-                const double us = 1e3 * ms / reps;
                 if (us < best) { best = us; best_g = g; }
             }
             (f ? c.g_filter : c.g_nbr) = best_g;
