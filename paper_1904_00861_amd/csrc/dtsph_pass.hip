@@ -794,6 +794,15 @@ __device__ inline void publish_report(const FinArgs &A, int s, const SimIter &It
     A.h_seq[s] = (int)q;
 }
 
+// What the closing thread needs, read by thread 0 of every workgroup at the
+// start (only the last one to arrive uses it), so these reads overlap the
+// partial sums instead of following the arrival ticket one by one.
+struct FinState {
+    int iters, fixed, conv_norm, stall_window, max_iter, steady, seg_begin, seg_count;
+    double hp[kHist], hv[kHist];
+    double dt, pscale, res_p, res_v, vref, tol, stall_rel;
+};
+
 __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
 {
     __shared__ int last;
@@ -809,6 +818,29 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
         return;
     }
     const SimDev &S = A.sims[s];
+    FinState F;
+    if (threadIdx.x == 0) {
+        F.iters = It.iters;
+        F.fixed = It.fixed;
+#pragma unroll
+        for (int e = 0; e < kHist; ++e) {
+            F.hp[e] = It.hp[e];
+            F.hv[e] = It.hv[e];
+        }
+        F.conv_norm = S.conv_norm;
+        F.stall_window = S.stall_window;
+        F.max_iter = S.max_iter;
+        F.steady = S.steady;
+        F.seg_begin = S.seg_begin;
+        F.seg_count = S.seg_count;
+        F.dt = S.dt;
+        F.pscale = S.dt / (S.rho0 * S.c * S.c);
+        F.res_p = S.res_p;
+        F.res_v = S.res_v;
+        F.vref = S.vref;
+        F.tol = S.tol;
+        F.stall_rel = S.stall_rel;
+    }
     double red[6] = {0, 0, 0, 0, 0, 0};
     const int t = sg.y + (int)threadIdx.x;
     if (t < sg.z) {
@@ -827,9 +859,10 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
     if (!last) return;
     __threadfence();
     for (int k = 0; k < 6; ++k) red[k] = 0.0;
-    for (int q = (int)threadIdx.x; q < S.seg_count; q += kFinThreads) {
-        const double4 p = A.seg_p[S.seg_begin + q];
-        const double2 p2 = A.seg_p2[S.seg_begin + q];
+    const int seg_begin = S.seg_begin, seg_count = S.seg_count;
+    for (int q = (int)threadIdx.x; q < seg_count; q += kFinThreads) {
+        const double4 p = A.seg_p[seg_begin + q];
+        const double2 p2 = A.seg_p2[seg_begin + q];
         if (q == (int)threadIdx.x) {
             red[0] = p.x; red[1] = p.y; red[2] = p.z; red[3] = p.w; red[4] = p2.x; red[5] = p2.y;
         } else {
@@ -842,45 +875,49 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
     A.tickets[s] = 0u;
     const double sd = red[0], sv = red[1], md = red[2], mv = red[3], mw = red[4], np = red[5];
     int *done_out = A.done_out;
-    It.disp = S.steady ? 0.0 : 0.5 * S.dt * sqrt(mw);  // steady sims never move
+    It.disp = F.steady ? 0.0 : 0.5 * F.dt * sqrt(mw);  // steady sims never move
     It.pairs = (long long)np;
-    const double pscale = S.dt / (S.rho0 * S.c * S.c);
-    const double rp = sd * S.res_p, rv = sv * S.res_v;
-    const double rpx = md * pscale, rvx = mv / S.vref;
-    const int k = It.iters;
+    const double rp = sd * F.res_p, rv = sv * F.res_v;
+    const double rpx = md * F.pscale, rvx = mv / F.vref;
+    const int k = F.iters;
     const int slot = k % kHist;
-    It.hp[slot] = S.conv_norm == 1 ? rpx : rp;
-    It.hv[slot] = S.conv_norm == 1 ? rvx : rv;
+    const double xp = F.conv_norm == 1 ? rpx : rp, xv = F.conv_norm == 1 ? rvx : rv;
+    It.hp[slot] = xp;
+    It.hv[slot] = xv;
     It.rp_mean = rp;
     It.rv_mean = rv;
     It.rp_max = rpx;
     It.rv_max = rvx;
     const int count = k + 1;
     It.iters = count;
-    const double xp = It.hp[slot], xv = It.hv[slot];
     int reason = 0;
     if (!isfinite(xp) || !isfinite(xv)) {
         reason = DTSPH_NONFINITE;
-    } else if (It.fixed > 0) {
-        reason = count >= It.fixed ? DTSPH_FIXED : 0;
+    } else if (F.fixed > 0) {
+        reason = count >= F.fixed ? DTSPH_FIXED : 0;
     } else {
         bool stalled[2] = {false, false};
-        const int W = S.stall_window;
+        const int W = F.stall_window;
         if (W > 0 && count >= W) {
-            for (int ser = 0; ser < 2; ++ser) {
-                const double *h = ser ? It.hv : It.hp;
-                double mn = INFINITY, mx = -INFINITY;
-                for (int m = count - W; m < count; ++m) {
-                    const double v = h[m % kHist];
-                    mn = v < mn ? v : mn;
-                    mx = v > mx ? v : mx;
+            // the window holds iterations count-W .. count-1: ring entries whose
+            // age (slot - e mod kHist) is below W, the newest being this one
+            double mn[2] = {INFINITY, INFINITY}, mx[2] = {-INFINITY, -INFINITY};
+#pragma unroll
+            for (int e = 0; e < kHist; ++e) {
+                const int age = (slot - e + kHist) % kHist;
+                if (age < W) {
+                    const double vp = e == slot ? xp : F.hp[e], vv = e == slot ? xv : F.hv[e];
+                    mn[0] = vp < mn[0] ? vp : mn[0];
+                    mx[0] = vp > mx[0] ? vp : mx[0];
+                    mn[1] = vv < mn[1] ? vv : mn[1];
+                    mx[1] = vv > mx[1] ? vv : mx[1];
                 }
-                stalled[ser] = (mx - mn) < S.stall_rel * mx;
             }
+            for (int ser = 0; ser < 2; ++ser) stalled[ser] = (mx[ser] - mn[ser]) < F.stall_rel * mx[ser];
         }
-        const bool bp = xp < S.tol, bv = xv < S.tol;
+        const bool bp = xp < F.tol, bv = xv < F.tol;
         if ((bp || stalled[0]) && (bv || stalled[1])) reason = (bp && bv) ? DTSPH_CONVERGED : DTSPH_STALLED;
-        else if (count >= S.max_iter) reason = DTSPH_MAXITER;
+        else if (count >= F.max_iter) reason = DTSPH_MAXITER;
     }
     if (reason) {
         It.done = 1;
