@@ -663,26 +663,45 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
     const int nfl = (int)(cn & 0xffffu);
     const int *__restrict__ nb = A.nbr + i;
     T S0 = 0, Sp = 0, Srr[3] = {0, 0, 0}, Sv[3] = {0, 0, 0};
-    for (int k = 0; k < nfl; ++k) {
-        const int j = nb[(size_t)k * N];
-        const Rec rj = prec[j];
-        const Q vj = vin[j];
-        T r[3];
-        pos.delta(ri, rj, r);
-        T r2 = r[0] * r[0] + r[1] * r[1];
-        if (DIM == 3) r2 += r[2] * r[2];
-        const T q = sqrt(r2) * inv_h;
-        T t3 = T(3) - q, t2 = T(2) - q, t1 = T(1) - q;
-        t3 = t3 > T(0) ? t3 : T(0);
-        t2 = t2 > T(0) ? t2 : T(0);
-        t1 = t1 > T(0) ? t1 : T(0);
-        const T a5 = t3 * t3 * t3 * t3 * t3, b5 = t2 * t2 * t2 * t2 * t2, c5 = t1 * t1 * t1 * t1 * t1;
-        const T W = T(15) * c5 + (T(-6) * b5 + a5);  // sigma cancels in the ratios
-        S0 += W;
-        Sp += pres<DIM>(vj) * W;
-        for (int d = 0; d < DIM; ++d) {
-            Srr[d] += rho * r[d] * W;
-            Sv[d] += comp(vj, d) * W;
+    // fluid neighbours U at a time: U index loads, then 2U record gathers in
+    // flight (slots past the count gather the particle's own records and are
+    // skipped), then the sums in entry order
+    constexpr int U = sizeof(T) == 4 ? 4 : 2;
+    for (int k0 = 0; k0 < nfl; k0 += U) {
+        bool ok[U];
+        int jj[U];
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            ok[m] = k0 + m < nfl;
+            jj[m] = ok[m] ? nb[(size_t)(k0 + m) * N] : i;
+        }
+        Rec rj[U];
+        Q vj[U];
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            rj[m] = prec[jj[m]];
+            vj[m] = vin[jj[m]];
+        }
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            if (!ok[m]) continue;
+            T r[3];
+            pos.delta(ri, rj[m], r);
+            T r2 = r[0] * r[0] + r[1] * r[1];
+            if (DIM == 3) r2 += r[2] * r[2];
+            const T q = sqrt(r2) * inv_h;
+            T t3 = T(3) - q, t2 = T(2) - q, t1 = T(1) - q;
+            t3 = t3 > T(0) ? t3 : T(0);
+            t2 = t2 > T(0) ? t2 : T(0);
+            t1 = t1 > T(0) ? t1 : T(0);
+            const T a5 = t3 * t3 * t3 * t3 * t3, b5 = t2 * t2 * t2 * t2 * t2, c5 = t1 * t1 * t1 * t1 * t1;
+            const T W = T(15) * c5 + (T(-6) * b5 + a5);  // sigma cancels in the ratios
+            S0 += W;
+            Sp += pres<DIM>(vj[m]) * W;
+            for (int d = 0; d < DIM; ++d) {
+                Srr[d] += rho * r[d] * W;
+                Sv[d] += comp(vj[m], d) * W;
+            }
         }
     }
     T vw[3] = {0, 0, 0}, ghost[3] = {0, 0, 0};
@@ -988,44 +1007,57 @@ __global__ void k_records(int Nf, const int *__restrict__ simid, const SimDev *_
 // next rate pass: p^K = p^{K+1/2} - dtau/2 (dp/dtau)^K (when pending), positions
 // r^{n+1} = r^n + dt/2 (V^n + V^{n+1}) with periodic wrap, history rotation,
 // position records and the {V^{n+1}, p^{n+1}} records of buffer `vrec`.
-template <typename T>
-__global__ void k_correct(int N, int Nf, const int *__restrict__ simid, const SimDev *__restrict__ sims,
-                          double *__restrict__ x, const double *__restrict__ xn, T *__restrict__ vn,
-                          T *__restrict__ dv, T *__restrict__ w, void *__restrict__ xr, double *__restrict__ pm,
-                          const T *__restrict__ dp, int half, void *__restrict__ prec,
-                          typename V4<T>::type *__restrict__ vrec, int gated, int n_sims,
-                          const SimIter *__restrict__ iters)
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_correct(int N, int Nf, const int *__restrict__ simid,
+                                                 const SimDev *__restrict__ sims, double *__restrict__ x,
+                                                 const double *__restrict__ xn, T *__restrict__ vn,
+                                                 T *__restrict__ dv, T *__restrict__ w, void *__restrict__ xr,
+                                                 double *__restrict__ pm, const T *__restrict__ dp, int half,
+                                                 void *__restrict__ prec, typename V4<T>::type *__restrict__ vrec,
+                                                 int gated, int n_sims, const SimIter *__restrict__ iters)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Nf) return;
-    if (gated && !spec_gate(n_sims, iters, sims)) return;
-    const SimDev &S = sims[simid[i]];
+    // the particle's own state first: these loads depend on nothing, so they are
+    // in flight while the gate and the sim's constants are read
+    const int sid = simid[i];
     double p = pm[i];
+    const T dpi = half ? dp[i] : T(0);
+    T v0[DIM], wk[DIM];
+    double xnd[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        v0[d] = vn[d * Nf + i];
+        wk[d] = w[d * Nf + i];
+        xnd[d] = xn[d * N + i];
+    }
+    if (gated && !spec_gate(n_sims, iters, sims)) return;
+    const SimDev &S = sims[sid];
     if (half) {
-        p -= 0.5 * S.dtau * (double)dp[i];
+        p -= 0.5 * S.dtau * (double)dpi;
         pm[i] = p;
     }
     double xo[3] = {0.0, 0.0, 0.0};
     T vr[3] = {T(0), T(0), T(0)};
-    for (int d = 0; d < S.dim; ++d) {
-        const T v0 = vn[d * Nf + i];
-        const T v1 = v0 + w[d * Nf + i];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const T v1 = v0[d] + wk[d];
         vr[d] = v1;
-        double xv = S.steady ? xn[d * N + i] : xn[d * N + i] + 0.5 * S.dt * ((double)v0 + (double)v1);
+        double xv = S.steady ? xnd[d] : xnd[d] + 0.5 * S.dt * ((double)v0[d] + (double)v1);
         if (S.periodic[d]) {
             if (xv >= S.hi[d]) xv -= S.L[d];
             else if (xv < S.lo[d]) xv += S.L[d];
         }
         x[d * N + i] = xv;
         xo[d] = xv;
-        dv[d * Nf + i] = v1 - v0;
+        dv[d * Nf + i] = v1 - v0[d];
         vn[d * Nf + i] = v1;
         w[d * Nf + i] = T(0);
     }
-    if (S.dim == 2) ((double2 *)xr)[i] = make_double2(xo[0], xo[1]);
+    if (DIM == 2) ((double2 *)xr)[i] = make_double2(xo[0], xo[1]);
     else ((double4 *)xr)[i] = make_double4(xo[0], xo[1], xo[2], 0.0);
     write_pos_record<T>(S, prec, i, xo);
-    vrec[i] = S.dim == 2 ? make_rec<T, 2>(vr, (T)p) : make_rec<T, 3>(vr, (T)p);
+    vrec[i] = make_rec<T, DIM>(vr, (T)p);
 }
 
 // ---- particle shifting (section 3.5: eqs. shift, shift-deltar, shift-correct) ---
@@ -1557,7 +1589,8 @@ void launch_correct(Ctx &c)
 {
     const int b = c.buf;
     using Q = typename V4<T>::type;
-    DTSPH_LAUNCH(c, k_correct<T>, dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.N, c.Nf, c.simid[b], c.sims,
+    auto kern = c.max_dim == 2 ? k_correct<T, 2> : k_correct<T, 3>;
+    DTSPH_LAUNCH(c, kern, dim3(grid_for(c.Nf)), dim3(256), 0, c.stream, c.N, c.Nf, c.simid[b], c.sims,
                        c.x[c.xb], c.xn[b], (T *)c.vn[b], (T *)c.dv[b], (T *)c.w[b], c.xr, c.pm[b],
                        (const T *)c.dp[b], c.p_half ? 1 : 0, c.prec, (Q *)c.vp[c.cur], c.gated ? 1 : 0, c.n_sims,
                        c.iters);
