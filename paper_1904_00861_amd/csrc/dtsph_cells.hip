@@ -218,13 +218,37 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
     if (m >= A.N) return;
     const int N = A.N, Nf = A.Nf, Nw = A.Nw;
     const int s = (int)A.perm[m];
+    // the particle's state is read as soon as its source slot is known, so these
+    // loads are in flight while the rank among the cell's members is counted
+    const int os = A.orig_in[s];
+    const int sid = A.simid_in[s];
+    double xs[3], xns[3];
+    for (int a = 0; a < 3; ++a) {
+        xs[a] = A.x_in[a * N + s];
+        xns[a] = A.xn_in[a * N + s];
+    }
+    const bool fl = s < Nf;  // slots keep their kind (fluid keys precede wall keys)
+    T vn[3] = {T(0), T(0), T(0)}, dvv[3] = {T(0), T(0), T(0)}, ww[3] = {T(0), T(0), T(0)},
+      w0[3] = {T(0), T(0), T(0)};
+    T dp = T(0);
+    double pmv = 0.0, pnv = 0.0;
+    if (fl) {
+        for (int a = 0; a < 3; ++a) {
+            vn[a] = A.vn_in[a * Nf + s];
+            dvv[a] = A.dv_in[a * Nf + s];
+            ww[a] = A.w_in[a * Nf + s];
+            w0[a] = A.w0_in[a * Nf + s];
+        }
+        dp = A.dp_in[s];
+        pmv = A.pm_in[s];
+        pnv = A.pn_in[s];
+    }
     const uint32_t k = A.key[s];
     const int b = (int)A.cell_start[k], e = (int)A.cell_start[k + 1];
     if (e - b > kMaxCellOccupancy) {
         atomicOr(&A.flags[F_CELL_OVERFLOW], 1);
         return;
     }
-    const int os = A.orig_in[s];
     int r = 0;
     for (int q0 = b; q0 < e; q0 += 8) {  // 8 members in flight at a time
         uint32_t pm[8];
@@ -236,37 +260,35 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
     const int d = b + r;
     A.src_of[d] = (uint32_t)s;
     A.orig_out[d] = os;
-    A.simid_out[d] = A.simid_in[s];
+    A.simid_out[d] = sid;
     for (int a = 0; a < 3; ++a) {
-        A.x_out[a * N + d] = A.x_in[a * N + s];
-        A.xn_out[a * N + d] = A.xn_in[a * N + s];
+        A.x_out[a * N + d] = xs[a];
+        A.xn_out[a * N + d] = xns[a];
     }
-    if (A.dim == 2) ((double2 *)A.xr)[d] = make_double2(A.x_in[s], A.x_in[N + s]);
-    else ((double4 *)A.xr)[d] = make_double4(A.x_in[s], A.x_in[N + s], A.x_in[2 * N + s], 0.0);
+    if (A.dim == 2) ((double2 *)A.xr)[d] = make_double2(xs[0], xs[1]);
+    else ((double4 *)A.xr)[d] = make_double4(xs[0], xs[1], xs[2], 0.0);
     if (d < Nf) {
         T v[3];
         for (int a = 0; a < 3; ++a) {
-            const T vn = A.vn_in[a * Nf + s], w = A.w_in[a * Nf + s];
-            A.vn_out[a * Nf + d] = vn;
-            A.dv_out[a * Nf + d] = A.dv_in[a * Nf + s];
-            A.w_out[a * Nf + d] = w;
-            A.w0_out[a * Nf + d] = A.w0_in[a * Nf + s];
-            v[a] = vn + w;
+            A.vn_out[a * Nf + d] = vn[a];
+            A.dv_out[a * Nf + d] = dvv[a];
+            A.w_out[a * Nf + d] = ww[a];
+            A.w0_out[a * Nf + d] = w0[a];
+            v[a] = vn[a] + ww[a];
         }
-        const T dp = A.dp_in[s];
-        double p = A.pm_in[s];
-        if (A.loop >= 0 && A.add_half) p += 0.5 * A.sims[A.simid_in[s]].dtau * (double)dp;
+        double p = pmv;
+        if (A.loop >= 0 && A.add_half) p += 0.5 * A.sims[sid].dtau * (double)dp;
         A.pm_out[d] = p;
-        A.pn_out[d] = A.pn_in[s];
+        A.pn_out[d] = pnv;
         A.dp_out[d] = dp;
         if (A.loop >= 0) {
             using Q = typename RecT<T>::type;
-            Q r;
-            r.x = v[0];
-            r.y = v[1];
-            if (A.dim == 2) { r.z = (T)p; r.w = T(0); }
-            else { r.z = v[2]; r.w = (T)p; }
-            ((Q *)A.rec)[d] = r;
+            Q rec;
+            rec.x = v[0];
+            rec.y = v[1];
+            if (A.dim == 2) { rec.z = (T)p; rec.w = T(0); }
+            else { rec.z = v[2]; rec.w = (T)p; }
+            ((Q *)A.rec)[d] = rec;
         }
     } else {
         const int dw = d - Nf, sw = s - Nf;
