@@ -377,13 +377,13 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the launch shapes. Between steps only (EINVAL in the loop).
  * Builds the cell lists if needed, picks the cell subdivision m in {1, 2, 3}
- * by timing full builds (they only reorder the state), then times the rate
- * pass of the predictor (it writes only scratch between steps, so the state is unchanged)
+ * together with the neighbour kernel's lanes per particle (1, 2, 4, 8) by
+ * timing full builds of every pair (they only reorder the state), then times
+ * the rate pass of the predictor (it writes only scratch between steps, so the state is unchanged)
  * for every lanes-per-particle in {1, 2, 4, 8} and workgroup size in {64, 128,
  * 256}, timed as the best of three windows of `repeats` launches (<= 0: 5),
  * and keeps the fastest for this context; then the lanes per particle (1, 2,
- * 4, 8) of the neighbour-list kernel and of the candidate filter (they
- * rewrite the same lists), timed the same way. The choice is cached per process by (dim, precision, walls,
+ * 4, 8) of the candidate filter, timed the same way. The choice is cached per process by (dim, precision, walls,
  * artificial viscosity, fluid-count bucket) and applied to later contexts of
  * the same kind. out (host, may be NULL) receives every timing.             */
 typedef struct dtsph_tune_entry {

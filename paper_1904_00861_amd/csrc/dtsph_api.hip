@@ -1430,20 +1430,26 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
             return best_us;
         };
         dtsph_tune_report rep{};
-        // cell subdivision: time full builds (sort + lists; they only reorder the state)
+        // cell subdivision and neighbour-kernel lanes together: time full builds
+        // (sort + lists; they only reorder the state) for every pair, since the
+        // best lane count depends on the subdivision
         {
             double best = 1e300;
-            int best_m = c.cell_div;
+            int best_m = c.cell_div, best_g = 1;
             for (int m = 1; m <= 3; ++m) {
                 setup_keys(c, m);
                 DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
-                const double us = by_precision(c, [&](auto t) {
-                    using T = decltype(t);
-                    build_cells<T>(c);
-                    return time_us([&] { build_cells<T>(c); });
-                });
-                if (us < best) { best = us; best_m = m; }
+                for (int g = 1; g <= 8; g *= 2) {
+                    c.g_nbr = g;
+                    const double us = by_precision(c, [&](auto t) {
+                        using T = decltype(t);
+                        build_cells<T>(c);
+                        return time_us([&] { build_cells<T>(c); });
+                    });
+                    if (us < best) { best = us; best_m = m; best_g = g; }
+                }
             }
+            c.g_nbr = best_g;
             setup_keys(c, best_m);
             DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
             by_precision(c, [&](auto t) {
@@ -1480,22 +1486,27 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
         c.lpp = rep.lanes;
         c.block = rep.block;
         setup_tiles(c);
-        // lanes per particle of the neighbour-list kernel and of the filter: both
-        // rewrite the same lists at unchanged positions, so repeats are harmless
-        for (int f = 0; f < 2; ++f) {
+        // the chosen neighbour kernel alone, and the lanes per particle of the
+        // filter (both rewrite lists at unchanged positions, so repeats are
+        // harmless)
+        rep.nbr_us = by_precision(c, [&](auto t) {
+            using T = decltype(t);
+            return time_us([&] { launch_nbr_lists<T>(c, false); });
+        });
+        {
             double best = 1e300;
             int best_g = 1;
             for (int g = 1; g <= 8; g *= 2) {
-                (f ? c.g_filter : c.g_nbr) = g;
+                c.g_filter = g;
                 const double us = by_precision(c, [&](auto t) {
                     using T = decltype(t);
-                    launch_nbr_lists<T>(c, f == 1);
-                    return time_us([&] { launch_nbr_lists<T>(c, f == 1); });
+                    launch_nbr_lists<T>(c, true);
+                    return time_us([&] { launch_nbr_lists<T>(c, true); });
                 });
                 if (us < best) { best = us; best_g = g; }
             }
-            (f ? c.g_filter : c.g_nbr) = best_g;
-            (f ? rep.filter_us : rep.nbr_us) = best;
+            c.g_filter = best_g;
+            rep.filter_us = best;
         }
         rep.nbr_lanes = c.g_nbr;
         rep.filter_lanes = c.g_filter;

@@ -1210,26 +1210,41 @@ __global__ void __launch_bounds__(256) k_shift_apply(ShiftArgs<T> A)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.Nf) return;
-    if (A.gated && !spec_gate(A.n_sims, A.iters, A.sims)) return;
-    const SimDev &S = A.sims[A.simid[i]];
-    if (!S.shift) return;
     const int N = A.N, Nf = A.Nf;
+    // the particle's state first: in flight while the gate and the sim's
+    // constants are read
+    const int sid = A.simid[i];
+    double xa[DIM], dra[DIM];
+    T dva[DIM], vna[DIM], vda[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        xa[a] = A.x[a * N + i];
+        dra[a] = A.dr[a * Nf + i];
+        dva[a] = A.dv[a * Nf + i];
+        vna[a] = A.vn[a * Nf + i];
+        vda[a] = A.vdiff[a * Nf + i];
+    }
+    const double pmi = A.pm[i], dpi = A.dp[i];
+    if (A.gated && !spec_gate(A.n_sims, A.iters, A.sims)) return;
+    const SimDev &S = A.sims[sid];
+    if (!S.shift) return;
     double xo[3] = {0.0, 0.0, 0.0};
     T v[3] = {T(0), T(0), T(0)};
+#pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        double xv = A.x[a * N + i] + A.dr[a * Nf + i];
+        double xv = xa[a] + dra[a];
         if (S.periodic[a]) {
             if (xv >= S.hi[a]) xv -= S.L[a];
             else if (xv < S.lo[a]) xv += S.L[a];
         }
         A.x[a * N + i] = xv;
         xo[a] = xv;
-        const T d = A.dv[a * Nf + i];
-        v[a] = A.vn[a * Nf + i] + d;
+        const T d = dva[a];
+        v[a] = vna[a] + d;
         A.vn[a * Nf + i] = v[a];
-        A.vdiff[a * Nf + i] += d;
+        A.vdiff[a * Nf + i] = vda[a] + d;
     }
-    const double p = A.pm[i] + A.dp[i];
+    const double p = pmi + dpi;
     A.pm[i] = p;
     if (DIM == 2) ((double2 *)A.xr)[i] = make_double2(xo[0], xo[1]);
     else ((double4 *)A.xr)[i] = make_double4(xo[0], xo[1], xo[2], 0.0);
