@@ -573,7 +573,8 @@ __device__ __forceinline__ void scan_block(const NbrArgs<T> &A, const SimDev &S,
         const float dz = DIM == 3 ? slab_d(rz, u, cz, fz, P.pz, csz) : 0.f;
         const float rem = cr2f - (dy * dy + dz * dz);
         if (rem < 0.f) { b0 = a0 - 1; b1 = a1 - 1; return; }
-        const float wc = sqrtf(rem) * icsx + 1e-5f;
+        // hardware square root (about 1 ulp, far inside the 1e-5-cell margin)
+        const float wc = __builtin_amdgcn_sqrtf(rem) * icsx + 1e-5f;
         int lo_c = cx + (int)floorf(fx - wc);
         int hi_c = cx + (int)floorf(fx + wc);
         lo_c = lo_c > cx - md ? lo_c : cx - md;
