@@ -34,13 +34,9 @@ __device__ inline int cell_coord(double x, double lo, double inv_cs, int n)
     return c;
 }
 
-__device__ inline int cell_linear(const SimDev &S, const double *x, int N, int i, int c3[3])
-{
-    c3[0] = c3[1] = c3[2] = 0;
-    for (int a = 0; a < S.dim; ++a) c3[a] = cell_coord(x[a * N + i], S.lo[a], S.inv_cs[a], S.ncell[a]);
-    return (c3[2] * S.ncell[1] + c3[1]) * S.ncell[0] + c3[0];
-}
-
+// DIM: the context's dimension, so the particle's coordinates are read together
+// with its sim index instead of after the sim's constants.
+template <int DIM>
 __global__ void __launch_bounds__(kThreads) k_keys(int N, int Nf, int C, const double *__restrict__ x,
                                                    const int *__restrict__ simid, const SimDev *__restrict__ sims,
                                                    uint32_t *__restrict__ key, uint32_t *__restrict__ rank,
@@ -50,9 +46,14 @@ __global__ void __launch_bounds__(kThreads) k_keys(int N, int Nf, int C, const d
     const bool active = i < N;
     uint32_t k = 0xffffffffu;
     if (active) {
+        double p[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) p[a] = x[a * N + i];
         const SimDev &S = sims[simid[i]];
-        int c3[3];
-        k = (uint32_t)(S.key_base + cell_linear(S, x, N, i, c3) + (i >= Nf ? C : 0));
+        int c[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) c[a] = cell_coord(p[a], S.lo[a], S.inv_cs[a], S.ncell[a]);
+        k = (uint32_t)(S.key_base + (c[2] * S.ncell[1] + c[1]) * S.ncell[0] + c[0] + (i >= Nf ? C : 0));
         key[i] = k;
     }
     // Slots are in the previous build's cell order, so equal keys sit in runs of
@@ -769,7 +770,8 @@ void build_cells(Ctx &c, int loop_fixed)
     const int N = c.N, nkeys = 2 * c.C;
     const int b = c.buf, o = c.buf ^ 1;
     int t0 = timer_begin(c, 2);
-    DTSPH_LAUNCH(c, k_keys, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.Nf, c.C, c.x[c.xb], c.simid[b],
+    auto keys = c.max_dim == 2 ? k_keys<2> : k_keys<3>;
+    DTSPH_LAUNCH(c, keys, dim3(grid_for(N)), dim3(kThreads), 0, st, N, c.Nf, c.C, c.x[c.xb], c.simid[b],
                        c.sims, c.key, c.rank, c.count);
     const int nblk = ceil_div(nkeys, kScanTile);
     DTSPH_LAUNCH(c, k_scan_reduce, dim3(nblk), dim3(kThreads), 0, st, c.count, nkeys, c.scan_tmp);
