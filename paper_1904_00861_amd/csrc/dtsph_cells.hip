@@ -595,6 +595,66 @@ __device__ __forceinline__ void scan_block(const NbrArgs<T> &A, const SimDev &S,
     auto row_key = [&](int u, int v, int tp) {
         return S.key_base + (tp ? A.C : 0) + (rz.at(u) * ny + ry.at(v)) * nx;
     };
+    auto advance = [&](int &u, int &v, int &tp) {
+        if (++v == ry.count) {
+            v = 0;
+            if (++u == rz.count) { u = 0; ++tp; }
+        }
+    };
+    if constexpr (G == 2 && !GENERAL) {
+        // The two lanes of a particle prepare alternate rows (lane `sub` the rows
+        // 2q + sub: window, bounds) and swap them by a lane swap (DPP quad_perm
+        // 1,0,3,2), so each row's window is computed once; both lanes then scan
+        // the pair's rows in order, as below. The next pair is prepared while
+        // this one is scanned.
+        auto swap = [](int x) { return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false); };
+        const int sub = grp.sub;
+        int mu = 0, mv = 0, mtp = 0;  // this lane's row
+        if (sub) advance(mu, mv, mtp);
+        int b0, e0, b1, e1, f1;  // its bounds and the shift sign of its second run
+        auto prep = [&](int r) {
+            b0 = e0 = b1 = e1 = f1 = 0;
+            if (r >= nrows) return;
+            int a0, c0, a1, c1;
+            double s1;
+            const int row = row_key(mu, mv, mtp);
+            row_runs(mu, mv, a0, c0, a1, c1, s1);
+            if (c0 >= a0) { b0 = (int)cstart[row + a0]; e0 = (int)cstart[row + c0 + 1]; }
+            if (c1 >= a1) { b1 = (int)cstart[row + a1]; e1 = (int)cstart[row + c1 + 1]; }
+            f1 = s1 > 0.0 ? 1 : (s1 < 0.0 ? -1 : 0);
+        };
+        prep(sub);
+        cf = -1;
+        for (int r0 = 0; r0 < nrows; r0 += 2) {  // uniform in the group
+            const int o[8] = {swap(b0), swap(e0), swap(b1), swap(e1), swap(f1), swap(mu), swap(mv), swap(mtp)};
+            const int m[8] = {b0, e0, b1, e1, f1, mu, mv, mtp};
+            int ra[8], rb[8];  // row r0 (lane 0's) and row r0 + 1 (lane 1's)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                ra[q] = sub ? o[q] : m[q];
+                rb[q] = sub ? m[q] : o[q];
+            }
+            if (r0 + 2 < nrows) {
+                advance(mu, mv, mtp);
+                advance(mu, mv, mtp);
+                prep(r0 + 2 + sub);
+            }
+            for (int h = 0; h < 2 && r0 + h < nrows; ++h) {
+                const int *d = h ? rb : ra;
+                if (d[7] == 1 && cf < 0) { cf = cur.total; ccf = cur.ctotal; }
+                const double sy = ry.shift(d[6], P.Ly), sz = DIM == 3 ? rz.shift(d[5], P.Lz) : 0.0;
+                const double rs1 = (double)d[4] * P.Lx;
+                const int nrun = d[2] < d[3] ? 2 : 1;
+                for (int k = 0; k < nrun; ++k)
+                    scan_run<DIM, G, GENERAL>(xr, k ? d[2] : d[0], k ? d[3] : d[1], i, P, k ? rs1 : 0.0, sy, sz, cr2,
+                                              nbr, cand, N, A.cap, A.capc, grp, cur);
+            }
+        }
+        if (cf < 0) { cf = cur.total; ccf = cur.ctotal; }
+        cw = cur.total - cf;
+        ccw = cur.ctotal - ccf;
+        return;
+    }
     int u = 0, v = 0, tp = 0;
     int row = row_key(u, v, tp);
     int a0, c0, a1, c1;
@@ -609,10 +669,7 @@ __device__ __forceinline__ void scan_block(const NbrArgs<T> &A, const SimDev &S,
         const int jb0 = b0, je0 = e0, jb1 = b1, je1 = e1;
         const double rs1 = s1;
         if (r + 1 < nrows) {  // prefetch the next row's bounds
-            if (++v == ry.count) {
-                v = 0;
-                if (++u == rz.count) { u = 0; ++tp; }
-            }
+            advance(u, v, tp);
             row = row_key(u, v, tp);
             row_runs(u, v, a0, c0, a1, c1, s1);
             b0 = e0 = b1 = e1 = 0;
