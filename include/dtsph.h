@@ -373,6 +373,8 @@ int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int6
                                   contexts with graphs or more than 64 sims,
                                   and while recent gates mostly stayed closed.
                                   Results are identical.                      */
+#define DTSPH_OPT_FILTER_LANES 13 /* lanes per particle of the candidate-list
+                                  filter: 1, 2, 4, 8 (0: automatic)           */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the launch shapes. Between steps only (EINVAL in the loop).

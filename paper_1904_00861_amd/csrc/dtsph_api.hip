@@ -1382,6 +1382,11 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
                 throw ApiError(DTSPH_EINVAL, "neighbour-build lanes must be 0, 1, 2, 4 or 8");
             c.g_nbr = (int)value;
             break;
+        case DTSPH_OPT_FILTER_LANES:
+            if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+                throw ApiError(DTSPH_EINVAL, "filter lanes must be 0, 1, 2, 4 or 8");
+            c.g_filter = (int)value;
+            break;
         case DTSPH_OPT_LANES:
             if (value != 1 && value != 2 && value != 4 && value != 8)
                 throw ApiError(DTSPH_EINVAL, "lanes per particle must be 1, 2, 4 or 8");

@@ -1,6 +1,7 @@
 """CPU checks of the C-ABI boundary: the library exports every function that
-include/dtsph.h declares, and the binding's ctypes structures have the header's
-layout (sizes and field offsets, from a probe compiled against the header)."""
+include/dtsph.h declares, the binding's constants equal the header's, and its
+ctypes structures have the header's layout (sizes and field offsets, from a
+probe compiled against the header)."""
 import ctypes as C
 import os
 import re
@@ -23,6 +24,19 @@ def declared_functions():
 
 def test_header_declares_the_binding_exports():
     assert declared_functions() == sorted(D.EXPORTS)
+
+
+def test_option_and_status_codes_match_the_header():
+    # every DTSPH_* integer constant the header defines has the same value in the
+    # binding (options, precisions, status and stop codes)
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define DTSPH_(\w+)\s+\(?(-?\d+)\)?", txt)}
+    assert "OPT_FILTER_LANES" in defs
+    for name, value in defs.items():
+        if hasattr(D, name):
+            assert getattr(D, name) == value, name
+    missing = [n for n in defs if n.startswith("OPT_") and not hasattr(D, n)]
+    assert not missing, missing
 
 
 def test_library_exports_every_declared_function():

@@ -1,0 +1,87 @@
+"""Every lane count of the neighbour-list kernels, since the autotuner may pick
+any of them: exact lists from a full build (1, 2, 4 or 8 lanes per particle,
+every cell subdivision, periodic and walled boxes, 2D and 3D, particles beyond
+the grid box) and from the candidate filter after real steps equal the
+brute-force oracle bit for bit. With two lanes the rows are prepared
+alternately by the two lanes and swapped; with one lane there is no partner;
+with four and eight the hits are ordered by ballots; small periodic boxes take
+the per-candidate minimum image."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1904_00861_amd import dtsph as D
+from paper_1904_00861_amd import inputs as I
+
+from gpu_helpers import banner
+
+pytestmark = pytest.mark.gpu
+
+
+def _dam_beyond_x():
+    # pairs of particles beyond both x ends of the grid box, each pair closer
+    # than kappa h, and one particle above the box
+    prob = I.dam_break(0.05)
+    prob.x[0, :2] = [4.6, 1.0]
+    prob.x[1, :2] = [4.65, 1.02]
+    prob.x[2, :2] = [-0.6, 1.5]
+    prob.x[3, :2] = [-0.62, 1.55]
+    prob.x[4, :2] = [2.0, 4.3]
+    return prob
+
+
+CASES = {
+    "tgv2d_16_j03": lambda: I.tgv2d(16, seed=3, jitter=0.3),
+    "tgv3d_16": lambda: I.tgv3d(16, seed=4),
+    "dam_beyond_x": _dam_beyond_x,
+    "tank_10": lambda: I.hydrostatic_tank(10),
+    "cavity_16": lambda: I.cavity(16),
+}
+
+
+@pytest.mark.parametrize("div", [1, 2, 3])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+@pytest.mark.parametrize("case", list(CASES))
+def test_build_lists_every_lane_count(case, lanes, div):
+    prob = CASES[case]()
+    banner(f"neighbour build {case} lanes {lanes} cell subdivision {div}")
+    ob, ib = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, prob.x, "brute")
+    sim = D.Sim(prob, precision=D.FP32)
+    sim.set_option(D.OPT_CELL_DIV, div)
+    sim.set_option(D.OPT_NBR_LANES, lanes)
+    off, idx = sim.neighbor_list()
+    sim.close()
+    assert np.array_equal(off, ob)
+    assert np.array_equal(idx, ib)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+@pytest.mark.parametrize("case", ["tgv2d_16_j03", "tgv3d_16", "cavity_16"])
+def test_filtered_lists_every_lane_count(case, lanes):
+    # after real steps the lists at r^{n+1} come from filtering the candidate
+    # lists of the last build (the skin covers the move)
+    prob = CASES[case]()
+    banner(f"candidate filter {case} lanes {lanes}")
+    sim = D.Sim(prob, precision=D.FP32)
+    sim.set_option(D.OPT_NBR_LANES, lanes)
+    sim.set_option(D.OPT_FILTER_LANES, lanes)
+    sim.step(3)
+    x = sim.get_state()["x"]
+    off, idx = sim.neighbor_list()
+    filters = sim.timing()["list_filters"]
+    sim.close()
+    assert filters >= 1
+    ob, ib = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, x, "brute")
+    assert np.array_equal(off, ob)
+    assert np.array_equal(idx, ib)
+
+
+def test_lane_options_reject_other_values():
+    prob = I.tgv2d(12, seed=1)
+    banner("lane options")
+    sim = D.Sim(prob, precision=D.FP32)
+    for opt in (D.OPT_NBR_LANES, D.OPT_FILTER_LANES):
+        for bad in (3, 16, -1):
+            with pytest.raises(D.DtsphError):
+                sim.set_option(opt, bad)
+    sim.close()
