@@ -1099,25 +1099,35 @@ __global__ void __launch_bounds__(256) k_shift_sums(ShiftArgs<T> A)
     using PosT = Pos<T, DIM>;
     using Rec = typename PosT::Rec;
     __shared__ double lds[4];
-    if (A.gated && !spec_gate(A.n_sims, A.iters, A.sims)) return;  // uniform in the grid
     const int sub = (int)threadIdx.x & (SL - 1);
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) / SL;
+    const bool own = i < A.Nf;  // uniform in each group of SL lanes
+    // the particle's own records, count and sim first: in flight while the gate
+    // and the sim's constants are read
+    const Rec *__restrict__ prec = (const Rec *)A.prec;
+    Rec ri{};
+    Q me{};
+    uint32_t cn = 0u;
+    int sid = 0;
+    if (own) {
+        ri = prec[i];
+        me = A.vrec[i];
+        cn = A.cnt[i];
+        sid = A.simid[i];
+    }
+    if (A.gated && !spec_gate(A.n_sims, A.iters, A.sims)) return;  // uniform in the grid
     double m2 = 0.0;
-    if (i < A.Nf) {  // uniform in each group of SL lanes
-        const SimDev &S = A.sims[A.simid[i]];
+    if (own) {
+        const SimDev &S = A.sims[sid];
         double del[3] = {0.0, 0.0, 0.0}, dpi = 0.0;
         T dvi[3] = {T(0), T(0), T(0)};
         if (S.shift) {
             const PosT pos(S);
-            const Rec *__restrict__ prec = (const Rec *)A.prec;
-            const Rec ri = prec[i];
-            const Q me = A.vrec[i];
             const T pi = pres<DIM>(me);
             const T vi[3] = {me.x, me.y, DIM == 3 ? me.z : T(0)};
             const T inv_h = (T)S.inv_h, kg = (T)S.kg, vol = (T)S.vol, rco = (T)S.shift_r;
             const int nexp = S.shift_n;
             T divr = 0, sd[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, gv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-            const uint32_t cn = A.cnt[i];
             const int total = (int)(cn & 0xffffu) + (int)(cn >> 16);
             const int *__restrict__ nb = A.nbr + i;
             // neighbours in batches of U per lane: U index loads, then 2U record
