@@ -412,7 +412,11 @@ k_pass(PassArgs<T> A)
         // fluid neighbours in batches of U: U index loads, then 2U record
         // gathers (or U coefficient loads and U gathers) in flight, then U pair
         // evaluations
-        constexpr int U = sizeof(T) == 4 ? 4 : 2;
+        // one lane per particle in the plain pseudo pass: 8 deep (the register
+        // budget holds it there without spills; the variants with more state
+        // stay at 4)
+        constexpr bool kDeep = LPP == 1 && MODE == MODE_PSEUDO && !CONV && CACHE == 0 && !MOVE && !SEPDEN;
+        constexpr int U = sizeof(T) == 4 ? (kDeep ? 8 : 4) : 2;
         int k = sub;
         for (; k + (U - 1) * LPP < nfl; k += U * LPP) {
             int jj[U];
