@@ -112,6 +112,8 @@ def lib():
                               P(C.c_int32), d, d, d]
         L.or_shift.restype = None
         L.or_shift.argtypes = [P(Params), C.c_int, C.c_int, d, d, d, d, P(C.c_int32)]
+        L.or_stop_test.restype = C.c_int
+        L.or_stop_test.argtypes = [P(Params), d, d, C.c_int]
         L.or_num_threads.restype = C.c_int
         L.or_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -278,6 +280,17 @@ def rows(prm: dict, nf: int, nw: int, mode: int, rows_idx, x, vk, pk, dk=None, v
     lib().or_rows(C.byref(P), nf, nw, int(mode), _d(x), _d(vk), _d(pk), _d(dk), _d(vn), _d(vnm1),
                   m, rows_idx.ctypes.data_as(C.POINTER(C.c_int32)), _d(vo), _d(po), _d(do))
     return vo, po, do
+
+
+def stop_test(prm: dict, rp, rv) -> str:
+    """The stop test (eq. conv and the stall rule) applied to residual histories
+    rp, rv (one value per iteration run so far). Returns the reason name, or
+    "continue"."""
+    rp = np.ascontiguousarray(rp, dtype=np.float64)
+    rv = np.ascontiguousarray(rv, dtype=np.float64)
+    assert rp.shape == rv.shape and rp.ndim == 1
+    r = lib().or_stop_test(C.byref(params(prm)), _d(rp), _d(rv), int(rp.size))
+    return REASONS.get(r, "continue")
 
 
 def num_threads() -> int:

@@ -581,6 +581,13 @@ static int stop_reason(const or_params *P, const double *hp, const double *hv, i
     return 0;
 }
 
+/* The stop test on given residual histories (count values each), for the tests
+ * that drive it with synthetic series. */
+int or_stop_test(const or_params *P, const double *hp, const double *hv, int count)
+{
+    return count > 0 ? stop_reason(P, hp, hv, count) : 0;
+}
+
 /* ---- pseudo-time loop (eqs. pkstar_frozen, vkp1_frozen, pkp1_frozen with the
  *      frozen eq. dv_dtau_exact; Algorithm 2 inner loop; R-pass) -------------
  * In: frozen positions x0, V^n (vn), V^{n-1} (vnm1); walls' prescribed velocity
