@@ -17,7 +17,10 @@
  *     term, over neighbours within the support of a quintic spline kernel;
  *   - walls use the boundary condition of Adami et al. (2012) with the wall
  *     pressure kept non-negative, as section 3.2 describes.
- * Particle shifting (section 3.5) is not part of this library.
+ *   - particle shifting with a Taylor correction (section 3.5) runs after the
+ *     corrector for the sims that ask for it; particles moving in pseudo-time
+ *     (Algorithm 1) and the steady-state solve (sections 2.3 and 3.3) are
+ *     per-sim variants of the same loop.
  *
  * Every numerical step runs in HIP kernels on the GPU. Many independent
  * simulations ("sims") can share one context and advance together.
@@ -227,6 +230,19 @@ typedef struct dtsph_info {
     int64_t device_bytes;   /* bytes of the context's device arrays          */
 } dtsph_info;
 
+/* ---- cell-ordered layout of a build (host memory; dtsph_build_cells) -----
+ * keys          int32[n]: cell key of each slot (slot = position in the sorted
+ *               order; fluid keys of every sim first, then wall keys)
+ * caller_index  int32[n]: caller index of the particle in each slot
+ * cell_start    int64[2 * n_cells + 1]: first slot of each key; key k holds
+ *               slots [cell_start[k], cell_start[k+1]) (n_cells: dtsph_info)
+ * Any pointer may be NULL (not written).                                   */
+typedef struct dtsph_cells_view {
+    int32_t *keys;
+    int32_t *caller_index;
+    int64_t *cell_start;
+} dtsph_cells_view;
+
 typedef struct dtsph_ctx dtsph_ctx;
 
 /* Create a context for n_sims simulations. sims, n_fluid, n_wall: host
@@ -268,10 +284,12 @@ int dtsph_get_state(dtsph_ctx *ctx, const dtsph_state_view *state);
  * r^{n+1} - r^(0) = dt/2 (V^{n+1} - V^(0)), the loop knows how far particles
  * will move, and the lists at r^{n+1} are then the candidates filtered by
  * the same exact predicate (no sort) whenever that distance is below 0.4 skin.
- * Other calls build on demand; calling it explicitly is optional.
- * Errors: EOVERFLOW (capacity; the message names the needed max_neighbors),
- * EHIP.                                                                     */
-int dtsph_build_cells(dtsph_ctx *ctx);
+ * Other calls build on demand; calling it explicitly is optional. out: NULL,
+ * or host arrays that receive the cell-ordered layout (dtsph_cells_view) of
+ * the lists in use, which the call builds if the positions changed since the
+ * last build. Errors: EOVERFLOW (capacity; the message names the needed
+ * max_neighbors), EHIP.                                                     */
+int dtsph_build_cells(dtsph_ctx *ctx, const dtsph_cells_view *out);
 
 /* Predictor of Algorithm 2 (between-steps -> in-loop phase): wall pass and
  * rate pass at (r^n, V^n, p^n) with dV/dtau = 0, then eq. v0 and eq. r0 in
@@ -300,18 +318,18 @@ int dtsph_correct(dtsph_ctx *ctx);
  * n_steps * n_sims reports (step-major) or NULL. Returns the worst status. */
 int dtsph_step(dtsph_ctx *ctx, int32_t n_steps, dtsph_iter_report *reps);
 
-/* Test API: neighbour lists at the current positions in caller indices.
- * offsets: host int64[n+1]; nbrs: host int32[cap] receiving each row in
- * ascending caller index; *needed (host) receives the total pair count. If
- * cap < *needed only offsets and needed are written. Builds if needed.    */
-int dtsph_neighbor_list(dtsph_ctx *ctx, int64_t *offsets, int32_t *nbrs, int64_t cap,
+/* Test API: the exact neighbour sets N(i) at the current positions (the
+ * definition given at dtsph_build_cells), one row per particle.
+ * sim: -1 for every particle of the context (rows and entries in caller
+ * indices, m = n); or s in [0, n_sims) for sim s alone (rows of its fluid
+ * then its walls, entries relative to its first particle, m = n_fluid[s] +
+ * n_wall[s]; no pair crosses sims). offsets: host int64[m + 1]; nbrs: host
+ * int32[cap] receiving each row in ascending index; *needed (host) receives
+ * the pair count. If nbrs is NULL or cap < *needed only offsets and needed
+ * are written. Builds if needed. Errors: EINVAL (sim out of range, NULL
+ * offsets or needed), EOVERFLOW, EHIP.                                      */
+int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *nbrs, int64_t cap,
                         int64_t *needed);
-
-/* Test API: the cell-ordered layout of the last build, host arrays of n
- * entries: key of each slot (fluid keys first, then wall keys), caller index
- * of each slot; cell_start: host int64[2*n_cells + 1] (start slot of each
- * key; key k holds slots [cell_start[k], cell_start[k+1])). NULL skips.     */
-int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int64_t *cell_start);
 
 /* Options (value semantics per option). Errors: EINVAL.                    */
 #define DTSPH_OPT_TIMING 1     /* n >= 1: time every n-th pair-pass, wall-pass

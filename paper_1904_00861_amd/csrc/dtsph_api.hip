@@ -205,6 +205,7 @@ void setup_keys(Ctx &c, int m)
         c.sims_h[s].key_base = (int)C;
         C += (int64_t)c.sims_h[s].ncell[0] * c.sims_h[s].ncell[1] * c.sims_h[s].ncell[2];
     }
+    if (C > c.C_max) throw ApiError(DTSPH_EINVAL, "cell grid exceeds the key tables sized at creation");
     c.C = (int)C;
     c.cell_div = m;
 }
@@ -977,6 +978,7 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         c.nw.assign(n_wall, n_wall + n_sims);
         c.max_dim = sims[0].dim;
         c.sims_h.resize(n_sims);
+        c.skin_default.resize(n_sims);
         c.fluid_begin.resize(n_sims);
         int64_t fb = 0, wb = 0;
         double cap_est = 0;
@@ -986,12 +988,17 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             const dtsph_sim_desc &d = sims[s];
             SimDev S = make_simdev(d, n_fluid[s], n_wall[s]);
             S.fluid_begin = (int)fb;
-            set_grid(S, 3);  // the finest subdivision sizes the key tables
-            int64_t cells = (int64_t)S.ncell[0] * S.ncell[1] * S.ncell[2];
+            // the finest subdivision at the smallest skin (0, see DTSPH_OPT_SKIN) has
+            // the most cells: it sizes the key tables
+            SimDev S0 = S;
+            S0.cand_r2 = S0.kh2;
+            set_grid(S0, 3);
+            int64_t cells = (int64_t)S0.ncell[0] * S0.ncell[1] * S0.ncell[2];
             C += cells;
             if (2 * C > (int64_t)4096 * 4096)
                 throw ApiError(DTSPH_EINVAL, "cell grid too large (more than 8M cells); enlarge h or shrink the box");
             c.sims_h[s] = S;
+            c.skin_default[s] = S.skin;
             c.fluid_begin[s] = (int)fb;
             for (int64_t k = 0; k < n_fluid[s]; ++k, ++caller) {
                 init_slot[caller] = (int)(fb + k);
@@ -1181,7 +1188,7 @@ int dtsph_get_state(dtsph_ctx *ctx, const dtsph_state_view *s)
     });
 }
 
-int dtsph_build_cells(dtsph_ctx *ctx)
+int dtsph_build_cells(dtsph_ctx *ctx, const dtsph_cells_view *out)
 {
     return guarded(ctx, [&](Ctx &c) {
         by_precision(c, [&](auto t) {
@@ -1190,6 +1197,21 @@ int dtsph_build_cells(dtsph_ctx *ctx)
             return 0;
         });
         readback_flags(c);
+        if (!out) return DTSPH_OK;
+        const size_t N = c.N, K = 2 * (size_t)c.C + 1;
+        if (out->keys) {
+            std::vector<uint32_t> key(N), perm(N);
+            DTSPH_HIP_CHECK(hipMemcpy(key.data(), c.key, 4 * N, hipMemcpyDeviceToHost));
+            DTSPH_HIP_CHECK(hipMemcpy(perm.data(), c.rank, 4 * N, hipMemcpyDeviceToHost));
+            for (size_t d = 0; d < N; ++d) out->keys[d] = (int32_t)key[perm[d]];
+        }
+        if (out->caller_index)
+            DTSPH_HIP_CHECK(hipMemcpy(out->caller_index, c.orig[c.buf], 4 * N, hipMemcpyDeviceToHost));
+        if (out->cell_start) {
+            std::vector<uint32_t> cs(K);
+            DTSPH_HIP_CHECK(hipMemcpy(cs.data(), c.cell_start, 4 * K, hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < K; ++k) out->cell_start[k] = cs[k];
+        }
         return DTSPH_OK;
     });
 }
@@ -1240,10 +1262,12 @@ int dtsph_step(dtsph_ctx *ctx, int32_t n_steps, dtsph_iter_report *reps)
     });
 }
 
-int dtsph_neighbor_list(dtsph_ctx *ctx, int64_t *offsets, int32_t *nbrs, int64_t cap, int64_t *needed)
+int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *nbrs, int64_t cap,
+                        int64_t *needed)
 {
     return guarded(ctx, [&](Ctx &c) {
         if (!offsets || !needed) throw ApiError(DTSPH_EINVAL, "offsets and needed are required");
+        if (sim < -1 || sim >= c.n_sims) throw ApiError(DTSPH_EINVAL, "sim must be -1 or a sim index");
         by_precision(c, [&](auto t) {
             using T = decltype(t);
             ensure_cells<T>(c);
@@ -1263,42 +1287,23 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int64_t *offsets, int32_t *nbrs, int64_t
             slot_of[orig[i]] = i;
         }
         for (size_t k = 0; k < N; ++k) len[k + 1] += len[k];
-        *needed = len[N];
-        std::memcpy(offsets, len.data(), 8 * (N + 1));
-        if (nbrs && cap >= len[N]) {
-            for (size_t cidx = 0; cidx < N; ++cidx) {
+        // caller range [cb, ce) of the requested rows
+        size_t cb = 0, ce = N;
+        if (sim >= 0) {
+            for (int s = 0; s < sim; ++s) cb += (size_t)(c.nf[s] + c.nw[s]);
+            ce = cb + (size_t)(c.nf[sim] + c.nw[sim]);
+        }
+        const int64_t base = len[cb];
+        *needed = len[ce] - base;
+        for (size_t k = cb; k <= ce; ++k) offsets[k - cb] = len[k] - base;
+        if (nbrs && cap >= *needed) {
+            for (size_t cidx = cb; cidx < ce; ++cidx) {
                 const size_t i = slot_of[cidx];
                 const int n = (int)((cnt[i] & 0xffffu) + (cnt[i] >> 16));
-                int32_t *row = nbrs + len[cidx];
-                for (int k = 0; k < n; ++k) row[k] = orig[nb[(size_t)k * N + i]];
+                int32_t *row = nbrs + (len[cidx] - base);
+                for (int k = 0; k < n; ++k) row[k] = orig[nb[(size_t)k * N + i]] - (int32_t)cb;
                 std::sort(row, row + n);
             }
-        }
-        return DTSPH_OK;
-    });
-}
-
-int dtsph_cell_layout(dtsph_ctx *ctx, int32_t *keys, int32_t *caller_index, int64_t *cell_start)
-{
-    return guarded(ctx, [&](Ctx &c) {
-        by_precision(c, [&](auto t) {
-            using T = decltype(t);
-            ensure_cells<T>(c);
-            return 0;
-        });
-        readback_flags(c);
-        const size_t N = c.N, K = 2 * (size_t)c.C + 1;
-        if (keys) {
-            std::vector<uint32_t> key(N), perm(N);
-            DTSPH_HIP_CHECK(hipMemcpy(key.data(), c.key, 4 * N, hipMemcpyDeviceToHost));
-            DTSPH_HIP_CHECK(hipMemcpy(perm.data(), c.rank, 4 * N, hipMemcpyDeviceToHost));
-            for (size_t d = 0; d < N; ++d) keys[d] = (int32_t)key[perm[d]];
-        }
-        if (caller_index) DTSPH_HIP_CHECK(hipMemcpy(caller_index, c.orig[c.buf], 4 * N, hipMemcpyDeviceToHost));
-        if (cell_start) {
-            std::vector<uint32_t> cs(K);
-            DTSPH_HIP_CHECK(hipMemcpy(cs.data(), c.cell_start, 4 * K, hipMemcpyDeviceToHost));
-            for (size_t k = 0; k < K; ++k) cell_start[k] = cs[k];
         }
         return DTSPH_OK;
     });
@@ -1340,7 +1345,7 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
             for (int s = 0; s < c.n_sims; ++s) {
                 SimDev &S = c.sims_h[s];
                 const double kh = std::sqrt(S.kh2);
-                S.skin = std::min(S.skin, 1e-3 * (double)value * S.h);
+                S.skin = std::min(c.skin_default[s], 1e-3 * (double)value * S.h);
                 S.cand_r2 = (kh + S.skin) * (kh + S.skin);
             }
             DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));

@@ -127,6 +127,7 @@ struct Ctx {
     std::vector<dtsph_sim_desc> desc;
     std::vector<int64_t> nf, nw;
     std::vector<SimDev> sims_h;
+    std::vector<double> skin_default;  // per sim: candidate skin chosen at creation
     std::vector<int> fluid_begin, wall_begin_caller, caller_begin;
 
     // phase

@@ -27,7 +27,7 @@ OPT_CELL_DIV, OPT_NBR_LANES, OPT_GRAPHS, OPT_PAIR_CACHE, OPT_SPECULATE, OPT_FILT
 EXPORTS = [
     "dtsph_create", "dtsph_destroy", "dtsph_last_error", "dtsph_set_state", "dtsph_get_state",
     "dtsph_build_cells", "dtsph_predict", "dtsph_pseudo_iterate", "dtsph_correct", "dtsph_step",
-    "dtsph_neighbor_list", "dtsph_cell_layout", "dtsph_set_option", "dtsph_get_timing",
+    "dtsph_neighbor_list", "dtsph_set_option", "dtsph_get_timing",
     "dtsph_get_info", "dtsph_autotune", "dtsph_workspace_bytes", "dtsph_set_workspace",
 ]
 
@@ -64,6 +64,10 @@ class SimDesc(C.Structure):
 class StateView(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in
                 ("x", "v", "v_prev", "p", "x_iter", "v_iter", "p_iter", "dpdtau")]
+
+
+class CellsView(C.Structure):
+    _fields_ = [("keys", C.c_void_p), ("caller_index", C.c_void_p), ("cell_start", C.c_void_p)]
 
 
 class IterReport(C.Structure):
@@ -138,13 +142,13 @@ def lib() -> C.CDLL:
         L.dtsph_last_error.restype = C.c_char_p
         L.dtsph_set_state.argtypes = [vp, P(StateView)]
         L.dtsph_get_state.argtypes = [vp, P(StateView)]
-        L.dtsph_build_cells.argtypes = [vp]
+        L.dtsph_build_cells.argtypes = [vp, P(CellsView)]
         L.dtsph_predict.argtypes = [vp]
         L.dtsph_pseudo_iterate.argtypes = [vp, C.c_int32, P(IterReport)]
         L.dtsph_correct.argtypes = [vp]
         L.dtsph_step.argtypes = [vp, C.c_int32, P(IterReport)]
-        L.dtsph_neighbor_list.argtypes = [vp, P(C.c_int64), P(C.c_int32), C.c_int64, P(C.c_int64)]
-        L.dtsph_cell_layout.argtypes = [vp, P(C.c_int32), P(C.c_int32), P(C.c_int64)]
+        L.dtsph_neighbor_list.argtypes = [vp, C.c_int32, P(C.c_int64), P(C.c_int32), C.c_int64,
+                                          P(C.c_int64)]
         L.dtsph_set_option.argtypes = [vp, C.c_int32, C.c_int64]
         L.dtsph_get_timing.argtypes = [vp, P(Timing)]
         L.dtsph_get_info.argtypes = [vp, P(Info)]
@@ -213,8 +217,19 @@ def dtsph_get_state(ctx, view: StateView) -> int:
     return _check(ctx, lib().dtsph_get_state(ctx, C.byref(view)))
 
 
-def dtsph_build_cells(ctx) -> int:
-    return _check(ctx, lib().dtsph_build_cells(ctx))
+def dtsph_build_cells(ctx, layout=None):
+    """Build (if the positions changed). With layout = (n, n_cells) also return
+    the cell-ordered layout: keys[n], caller_index[n], cell_start[2 n_cells + 1]."""
+    if layout is None:
+        _check(ctx, lib().dtsph_build_cells(ctx, None))
+        return None
+    n, n_cells = layout
+    keys = np.zeros(n, dtype=np.int32)
+    callers = np.zeros(n, dtype=np.int32)
+    starts = np.zeros(2 * n_cells + 1, dtype=np.int64)
+    view = CellsView(keys.ctypes.data, callers.ctypes.data, starts.ctypes.data)
+    _check(ctx, lib().dtsph_build_cells(ctx, C.byref(view)))
+    return keys, callers, starts
 
 
 def dtsph_predict(ctx) -> int:
@@ -240,28 +255,20 @@ def dtsph_step(ctx, n_steps: int, n_sims: int, want_reports: bool = True):
     return st, out
 
 
-def dtsph_neighbor_list(ctx, n: int):
-    off = np.zeros(n + 1, dtype=np.int64)
+def dtsph_neighbor_list(ctx, m: int, sim: int = -1):
+    """Exact neighbour rows (CSR offsets[m + 1], indices) of every particle
+    (sim = -1, m = n) or of sim `sim` alone (m = its particle count, indices
+    relative to its first particle)."""
+    off = np.zeros(m + 1, dtype=np.int64)
     need = C.c_int64()
     P = C.POINTER
-    _check(ctx, lib().dtsph_neighbor_list(ctx, off.ctypes.data_as(P(C.c_int64)), None, 0,
+    _check(ctx, lib().dtsph_neighbor_list(ctx, int(sim), off.ctypes.data_as(P(C.c_int64)), None, 0,
                                           C.byref(need)))
     idx = np.zeros(max(need.value, 1), dtype=np.int32)
-    _check(ctx, lib().dtsph_neighbor_list(ctx, off.ctypes.data_as(P(C.c_int64)),
+    _check(ctx, lib().dtsph_neighbor_list(ctx, int(sim), off.ctypes.data_as(P(C.c_int64)),
                                           idx.ctypes.data_as(P(C.c_int32)), need.value,
                                           C.byref(need)))
     return off, idx[:need.value]
-
-
-def dtsph_cell_layout(ctx, n: int, n_cells: int):
-    P = C.POINTER
-    keys = np.zeros(n, dtype=np.int32)
-    callers = np.zeros(n, dtype=np.int32)
-    starts = np.zeros(2 * n_cells + 1, dtype=np.int64)
-    _check(ctx, lib().dtsph_cell_layout(ctx, keys.ctypes.data_as(P(C.c_int32)),
-                                        callers.ctypes.data_as(P(C.c_int32)),
-                                        starts.ctypes.data_as(P(C.c_int64))))
-    return keys, callers, starts
 
 
 def dtsph_set_option(ctx, option: int, value: int) -> int:
@@ -369,6 +376,10 @@ class Sim:
     def build_cells(self):
         return dtsph_build_cells(self.ctx)
 
+    def cell_layout(self):
+        """Cell-ordered layout of the lists in use (keys, caller indices, cell starts)."""
+        return dtsph_build_cells(self.ctx, (self.n, dtsph_get_info(self.ctx)["n_cells"]))
+
     def predict(self):
         return dtsph_predict(self.ctx)
 
@@ -381,11 +392,9 @@ class Sim:
     def step(self, n_steps: int = 1, reports: bool = True):
         return dtsph_step(self.ctx, n_steps, self.n_sims, reports)
 
-    def neighbor_list(self):
-        return dtsph_neighbor_list(self.ctx, self.n)
-
-    def cell_layout(self):
-        return dtsph_cell_layout(self.ctx, self.n, self.info["n_cells"])
+    def neighbor_list(self, sim: int = -1):
+        m = self.n if sim < 0 else self.problems[sim].n
+        return dtsph_neighbor_list(self.ctx, m, sim)
 
     def set_option(self, option: int, value: int):
         return dtsph_set_option(self.ctx, option, value)

@@ -52,7 +52,7 @@ def test_library_exports_every_declared_function():
         assert hasattr(L, f)
 
 
-STRUCTS = {"dtsph_sim_desc": D.SimDesc, "dtsph_state_view": D.StateView,
+STRUCTS = {"dtsph_sim_desc": D.SimDesc, "dtsph_state_view": D.StateView, "dtsph_cells_view": D.CellsView,
            "dtsph_iter_report": D.IterReport, "dtsph_timing": D.Timing, "dtsph_info": D.Info,
            "dtsph_tune_entry": D.TuneEntry, "dtsph_tune_report": D.TuneReport}
 

@@ -219,6 +219,26 @@ def _slices(probs):
     return out
 
 
+def test_batch_neighbour_rows_per_sim():
+    # dtsph_neighbor_list(sim = s) returns sim s's rows with indices relative to
+    # its first particle: the oracle's lists of that problem alone
+    probs = _batch() + [I.dam_break(0.1, name="e")]
+    banner("batch neighbour rows per sim")
+    sim = D.Sim(probs, precision=D.FP32)
+    off_all, idx_all = sim.neighbor_list()
+    for s, (prob, sl) in enumerate(zip(probs, _slices(probs))):
+        off, idx = sim.neighbor_list(s)
+        ob, ib = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, prob.x, "brute")
+        assert np.array_equal(off, ob) and np.array_equal(idx, ib), prob.name
+        # the same rows as in the whole-context listing, shifted
+        rows = idx_all[off_all[sl.start]:off_all[sl.stop]] - sl.start
+        assert np.array_equal(rows, idx)
+    with pytest.raises(D.DtsphError) as e:
+        D.dtsph_neighbor_list(sim.ctx, 10, len(probs))
+    assert e.value.status == D.EINVAL
+    sim.close()
+
+
 def test_batch_members_match_oracle():
     probs = _batch()
     banner("batch vs oracle fp64")
@@ -319,6 +339,42 @@ def test_skin_zero_rebuilds_and_agrees():
     nf = prob.n_fluid
     assert rel_l2(ga["v"][:nf], gb["v"][:nf]) <= 1e-12
     assert rel_l2(ga["p"][:nf], gb["p"][:nf]) <= 1e-12
+
+
+def test_skin_restored_to_default():
+    # lowering the skin and raising it again restores the creation default:
+    # the run is then bit-identical to a fresh context and takes as many builds
+    prob = I.tgv2d(40, seed=21)
+    banner("skin lowered and restored")
+    a = D.Sim(prob, precision=D.FP32)
+    a.set_option(D.OPT_TIMING, 1)
+    a.step(6)
+    ga, ta = a.get_state(), a.timing()
+    a.close()
+    b = D.Sim(prob, precision=D.FP32)
+    b.set_option(D.OPT_SKIN, 0)
+    b.set_option(D.OPT_SKIN, 100000)
+    b.set_option(D.OPT_TIMING, 1)
+    b.step(6)
+    gb, tb = b.get_state(), b.timing()
+    b.close()
+    for f in ga:
+        assert np.array_equal(ga[f], gb[f]), f
+    assert ta["full_builds"] == tb["full_builds"] and ta["list_filters"] == tb["list_filters"]
+
+
+def test_skin_zero_then_finest_cells():
+    # skin 0 with the finest cell subdivision has the most cells of any setting:
+    # the key tables sized at creation hold them, and the lists stay exact
+    prob = I.tgv2d(30, seed=4, jitter=0.2)
+    banner("skin 0, cell subdivision 3")
+    sim = D.Sim(prob, precision=D.FP32)
+    sim.set_option(D.OPT_SKIN, 0)
+    sim.set_option(D.OPT_CELL_DIV, 3)
+    off, idx = sim.neighbor_list()
+    sim.close()
+    ob, ib = O.neighbors(prob.params, prob.n_fluid, 0, prob.x, "brute")
+    assert np.array_equal(off, ob) and np.array_equal(idx, ib)
 
 
 @pytest.mark.parametrize("div", [1, 2, 3])
