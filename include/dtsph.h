@@ -206,8 +206,12 @@ typedef struct dtsph_timing {
     int64_t pass_particles; /* fluid particles those launches updated         */
     int64_t wall_launches;
     double wall_ms;
-    int64_t build_launches; /* cell + neighbour-list builds                   */
+    int64_t build_launches; /* full builds timed: keys, sort, gather, lists   */
     double build_ms;
+    int64_t build_particles;/* particles those builds sorted                  */
+    int64_t filter_launches;/* list filters timed (exact lists re-derived from
+                               the candidate lists without a sort)           */
+    double filter_ms;
     /* counted on every call (timing on or off), reset with the timers:       */
     int64_t full_builds;    /* sorts + neighbour-list builds                  */
     int64_t list_filters;   /* exact lists filtered from candidate lists      */
@@ -393,6 +397,11 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *
                                   Results are identical.                      */
 #define DTSPH_OPT_FILTER_LANES 13 /* lanes per particle of the candidate-list
                                   filter: 1, 2, 4, 8 (0: automatic)           */
+#define DTSPH_OPT_ABS32_POSITIONS 14 /* ablation of the FP32 path (0 default):
+                                  1 rounds every coordinate to float32 before
+                                  the pair passes see it, i.e. float32
+                                  separations of absolute coordinates instead
+                                  of exact fixed-point ones; no effect in FP64 */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the launch shapes. Between steps only (EINVAL in the loop).

@@ -261,10 +261,16 @@ static void build_binned(const or_params *P, int nf, int nw, const double *x, nl
                 if (x[3 * i + a] < mn) mn = x[3 * i + a];
                 if (x[3 * i + a] > mx) mx = x[3 * i + a];
             }
-            if (n == 0) { mn = 0; mx = 0; }
+            if (!(mn <= mx)) { mn = 0; mx = 0; } /* no particle, or none finite */
             base[a] = mn;
             bs[a] = kh;
-            nb[a] = (int)floor((mx - mn) / kh) + 1;
+            /* at most (8n + 64)^(1/dim) + 1 bins per axis (more than twice what
+               particles at any density below a lattice's fill): beyond them,
+               particles share the last bin, where the exact predicate still
+               decides (a search, not arithmetic) */
+            const double cap = floor(pow(8.0 * n + 64.0, 1.0 / dim)) + 1.0;
+            const double span = floor((mx - mn) / kh) + 1.0;
+            nb[a] = span < cap ? (int)span : (int)cap;
         }
     }
     int64_t nbins = (int64_t)nb[0] * nb[1] * nb[2];
@@ -277,9 +283,10 @@ static void build_binned(const or_params *P, int nf, int nw, const double *x, nl
         for (int a = 2; a >= 0; --a) {
             int c = 0;
             if (a < dim) {
-                c = (int)floor((x[3 * i + a] - base[a]) / bs[a]);
-                if (c < 0) c = 0;
-                if (c > nb[a] - 1) c = nb[a] - 1;
+                double f = floor((x[3 * i + a] - base[a]) / bs[a]);
+                if (!(f >= 0.0)) f = 0.0; /* below the range, or not finite */
+                if (f > (double)(nb[a] - 1)) f = (double)(nb[a] - 1);
+                c = (int)f;
             }
             bin3[3 * i + a] = c;
             lin = lin * nb[a] + c;

@@ -384,7 +384,8 @@ void resolve_timers(Ctx &c)
         // pair passes are booked at the end of their loop, with their pairs
         if (pr[1] == 0) c.pass_times.emplace_back(pr[2], (double)ms);
         else if (pr[1] == 1) { c.tstats.wall_launches++; c.tstats.wall_ms += ms; }
-        else { c.tstats.build_launches++; c.tstats.build_ms += ms; }
+        else if (pr[1] == 2) { c.tstats.build_launches++; c.tstats.build_ms += ms; c.tstats.build_particles += c.N; }
+        else { c.tstats.filter_launches++; c.tstats.filter_ms += ms; }
     }
     c.ev_pending.clear();
     c.ev_used = 0;
@@ -1320,7 +1321,7 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
             if (value < 0) throw ApiError(DTSPH_EINVAL, "timing sample interval must be >= 0");
             c.timing = value != 0;
             c.timing_every = value > 0 ? (int)std::min<int64_t>(value, 1 << 20) : 1;
-            c.timer_count[0] = c.timer_count[1] = c.timer_count[2] = 0;
+            c.timer_count[0] = c.timer_count[1] = c.timer_count[2] = c.timer_count[3] = 0;
             break;
         case DTSPH_OPT_RESET_TIMING:
             DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
@@ -1387,6 +1388,15 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
                 throw ApiError(DTSPH_EINVAL, "neighbour-build lanes must be 0, 1, 2, 4 or 8");
             c.g_nbr = (int)value;
             break;
+        case DTSPH_OPT_ABS32_POSITIONS: {
+            if (value != 0 && value != 1) throw ApiError(DTSPH_EINVAL, "abs32 positions must be 0 or 1");
+            for (int s = 0; s < c.n_sims; ++s) c.sims_h[s].abs32 = (int)value;
+            DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+            DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
+            c.cells_valid = false;  // records are rewritten by the next build
+            c.cand_ok = c.cand_next = false;
+            break;
+        }
         case DTSPH_OPT_FILTER_LANES:
             if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
                 throw ApiError(DTSPH_EINVAL, "filter lanes must be 0, 1, 2, 4 or 8");

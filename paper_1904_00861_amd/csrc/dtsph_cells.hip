@@ -874,9 +874,9 @@ template <typename T>
 void filter_lists(Ctx &c)
 {
     c.tstats.list_filters++;
-    int t0 = timer_begin(c, 2);
+    int t0 = timer_begin(c, 3);
     launch_nbr_lists<T>(c, true);
-    timer_end(c, t0, 2);
+    timer_end(c, t0, 3);
 }
 
 // The neighbour-list kernel alone (filter = false; needs a valid cell table) or

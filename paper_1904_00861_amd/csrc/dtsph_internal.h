@@ -57,7 +57,8 @@ struct SimDev {
     double h, inv_h, rho0, mass, c, nu, nu_e;
     double g[3];
     double dt, dtau, gamma, inv2dt, tol, vref;
-    int max_iter, stall_window, conv_norm, pad0;
+    int max_iter, stall_window, conv_norm;
+    int abs32;           // ablation: pair passes see float32-rounded absolute coordinates
     double stall_rel;
     // pass coefficients: dW/dr = kg * poly(q); see the pass kernel
     double sigma, kg;
@@ -226,7 +227,7 @@ struct Ctx {
     // timing
     bool timing = false;
     int timing_every = 1;                 // time every n-th launch of each kind
-    long long timer_count[3] = {0, 0, 0};
+    long long timer_count[4] = {0, 0, 0, 0};  // pair pass, wall pass, full build, list filter
     int pass_index = 0;                   // launch index of the next pair pass in the loop
     hipEvent_t ext_start = nullptr, ext_stop = nullptr;  // events of a timed pass launch
     std::vector<std::pair<int, double>> pass_times;  // this loop's timed pair passes (index, ms)
@@ -321,7 +322,11 @@ __device__ inline void write_pos_record<float>(const SimDev &S, void *prec, int 
 {
     uint32_t q[4] = {0u, 0u, 0u, 0u};
     for (int a = 0; a < S.dim; ++a) {
-        double v = floor((xi[a] - S.lo[a]) * S.q_inv[a]);
+        // ablation (DTSPH_OPT_ABS32_POSITIONS): the coordinate rounded to float32 first;
+        // the fixed-point difference of two such values is the float32 difference
+        // (exact for neighbours, Sterbenz) rounded once, as in a float32 pipeline
+        const double xa = S.abs32 ? (double)(float)xi[a] : xi[a];
+        double v = floor((xa - S.lo[a]) * S.q_inv[a]);
         q[a] = (uint32_t)(unsigned long long)(long long)v;
     }
     if (S.dim == 2) ((uint2 *)prec)[i] = make_uint2(q[0], q[1]);

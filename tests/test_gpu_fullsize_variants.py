@@ -10,7 +10,7 @@ import pytest
 from paper_1904_00861_amd import dtsph as D
 from paper_1904_00861_amd import inputs as I
 
-from gpu_helpers import banner, oracle_steps, rel_l2
+from gpu_helpers import Bars, banner, oracle_steps, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -50,10 +50,13 @@ def test_fullsize_variant_step(case):
     sim.close()
     x, v, vp, p, oreps, _ = oracle_steps(prob, 1, fixed)
     assert reps[0]["iters"] == oreps[0]["iters"] == fixed
-    assert np.abs(g["x"] - x).max() <= TOL["x"]
-    # the dam break's momentum right side is a cancellation of grad p / rho and g
-    vs = 10.0 if case.startswith("C3") else 1.0
-    assert rel_l2(g["v"][:nf], v[:nf]) <= TOL["v"] * vs
-    assert rel_l2(g["p"][:nf], p[:nf]) <= TOL["p"]
+    # the dam break's momentum right side is a cancellation of grad p / rho and g:
+    # velocities on the |g| dt scale of those terms (zero without gravity)
+    vfl = float(np.linalg.norm(prob.params["g"])) * prob.params["dt"] * np.sqrt(nf)
+    b = Bars(f"full-size variant {case}")
+    b.absmax("x", g["x"], x, TOL["x"])
+    b.rel("V", g["v"][:nf], v[:nf], TOL["v"], vfl)
+    b.rel("p", g["p"][:nf], p[:nf], TOL["p"])
+    b.done()
     if prob.params["steady"]:
         assert np.array_equal(g["x"], prob.x)

@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle.
 
-Bars (relative L2 over fluid particles unless noted; pressure rates are compared
-on the scale of their terms, see gpu_helpers.rate_floor):
+Bars (relative L2 over fluid particles, ||gpu - oracle|| / ||oracle||, every
+measured value printed by the run):
   neighbour lists      bit-exact (same sets, caller indices ascending)
   FP64 path            one pass <= 1e-12; 20 fixed iterations <= 1e-11;
                        several real steps <= 1e-10, positions <= 1e-12 absolute;
@@ -9,10 +9,13 @@ on the scale of their terms, see gpu_helpers.rate_floor):
   FP32 path            one pass: V <= 1e-6, p <= 1e-5, dp/dtau <= 1e-4;
                        20 fixed iterations: V <= 1e-5, p <= 1e-4;
                        several real steps: V, p <= 1e-4, positions <= 1e-7 absolute;
-                       iteration counts within one of the oracle's
+                       iteration counts within one of the oracle's, and the fields
+                       compared with an oracle run of the same per-step counts
 The FP32 bars follow from float32 rounding (6e-8) of pair terms summed over
-~26 (2D) / ~110 (3D) neighbours; the pressure rate cancels (a divergence of a
-nearly solenoidal field) and carries the loosest bar.
+~26 (2D) / ~110 (3D) neighbours. The pressure rate is a cancelling sum (the
+divergence of a nearly solenoidal field plus a diffusion term): its terms are
+up to ~1e3 times its norm, so float32 rounding of the terms shows up magnified
+in its relative error.
 """
 import numpy as np
 import pytest
@@ -21,12 +24,22 @@ import oracle as O
 from paper_1904_00861_amd import dtsph as D
 from paper_1904_00861_amd import inputs as I
 
-from gpu_helpers import banner, gpu_steps, oracle_steps, rate_floor, rel_l2
+from gpu_helpers import Bars, banner, gpu_steps, oracle_steps, oracle_steps_at, rel_l2
 
 pytestmark = pytest.mark.gpu
 
 PREC = {"fp64": D.FP64, "fp32": D.FP32}
 TOL_PASS = {"fp64": dict(v=1e-12, p=1e-12, d=1e-12), "fp32": dict(v=1e-6, p=1e-5, d=1e-4)}
+# The cavity starts at rest under a tangential lid: its pressure rate before the
+# loop vanishes by symmetry (round-off on both sides), so it is compared on the
+# scale of one divergence term, rho c^2 V_ref / h per particle; every other rate
+# on its own norm.
+def _rate_floor(prob, case):
+    if case != "cavity_16":
+        return 0.0
+    p = prob.params
+    c = p["beta"] * p["vref"]
+    return p["rho0"] * c * c * p["vref"] / p["h"] * np.sqrt(prob.n_fluid)
 TOL_K20 = {"fp64": dict(v=1e-11, p=1e-11), "fp32": dict(v=1e-5, p=1e-4)}
 TOL_STEPS = {"fp64": dict(v=1e-10, p=1e-10, x=1e-12), "fp32": dict(v=1e-4, p=1e-4, x=1e-7)}
 
@@ -111,9 +124,11 @@ def test_predict_parity(case, prec):
     sim.close()
     pr = O.predict(prob.params, nf, prob.n_wall, prob.x, prob.v, prob.p)
     t = TOL_PASS[prec]
-    assert rel_l2(g["v_iter"][:nf], pr["v_iter"][:nf]) <= t["v"]
-    assert rel_l2(g["dpdtau"][:nf], pr["dpdtau"][:nf], rate_floor(prob)) <= t["d"]
-    assert np.abs(g["x_iter"] - pr["x_iter"]).max() <= (1e-14 if prec == "fp64" else 1e-8)
+    b = Bars(f"predict {case} {prec}")
+    b.rel("V(0)", g["v_iter"][:nf], pr["v_iter"][:nf], t["v"])
+    b.rel("dp/dtau", g["dpdtau"][:nf], pr["dpdtau"][:nf], t["d"], _rate_floor(prob, case))
+    b.absmax("r(0)", g["x_iter"], pr["x_iter"], 1e-14 if prec == "fp64" else 1e-8)
+    b.done()
     assert np.array_equal(g["p_iter"][:nf], prob.p[:nf])
     # the between-steps fields are untouched by the predictor
     assert np.array_equal(g["x"], prob.x) and np.array_equal(g["p"][:nf], prob.p[:nf])
@@ -136,10 +151,12 @@ def test_pseudo_iterate_fixed_k(case, k, prec):
                                     ls["v_iter"], ls["p_iter"], ls["dpdtau"], fixed_iters=k)
     t = TOL_PASS[prec] if k == 1 else TOL_K20[prec]
     assert reps[0]["iters"] == k and D.REASONS[reps[0]["reason"]] == "fixed"
-    assert rel_l2(g["v_iter"][:nf], vk[:nf]) <= t["v"]
-    assert rel_l2(g["p_iter"][:nf], pk[:nf]) <= t["p"]
+    b = Bars(f"pseudo_iterate {case} K={k} {prec}")
+    b.rel("V", g["v_iter"][:nf], vk[:nf], t["v"])
+    b.rel("p", g["p_iter"][:nf], pk[:nf], t["p"])
     if k == 1:
-        assert rel_l2(g["dpdtau"][:nf], dk[:nf], rate_floor(prob)) <= t["d"]
+        b.rel("dp/dtau", g["dpdtau"][:nf], dk[:nf], TOL_PASS[prec]["d"])
+    b.done()
     # residuals of eq. conv agree
     rtol = 1e-9 if prec == "fp64" else 1e-3
     for key in ("rp_mean", "rv_mean", "rp_max", "rv_max"):
@@ -151,25 +168,30 @@ def test_pseudo_iterate_fixed_k(case, k, prec):
 @pytest.mark.parametrize("case,steps", [("tgv2d_50", 10), ("cavity_16", 5), ("dam_0.05", 5),
                                         ("tgv3d_10", 3), ("tgv2d_23_ragged", 4)])
 def test_real_steps_parity(case, steps, prec):
+    # free-running steps: iteration counts against the oracle's own (equal in
+    # FP64, within one in FP32); fields against an oracle run that takes the GPU's
+    # per-step counts, so that both sides did the same iterations
     prob = CASES[case]()
     banner(f"steps {case} x{steps} {prec}")
     nf = prob.n_fluid
-    x, v, vp, p, oreps, ost = oracle_steps(prob, steps)
+    _, _, _, _, oreps, ost = oracle_steps(prob, steps)
     g, greps, st = gpu_steps(prob, steps, PREC[prec])
     gi = [r[0]["iters"] for r in greps]
     oi = [r["iters"] for r in oreps]
-    t = TOL_STEPS[prec]
     if prec == "fp64":
         assert gi == oi
     else:
         assert all(abs(a - b) <= 1 for a, b in zip(gi, oi))
-    loose = 1.0 if gi == oi else 20.0
-    assert rel_l2(g["v"][:nf], v[:nf]) <= t["v"] * loose
-    assert rel_l2(g["p"][:nf], p[:nf]) <= t["p"] * loose
-    assert rel_l2(g["v_prev"][:nf], vp[:nf]) <= t["v"] * loose
-    assert np.abs(g["x"] - x).max() <= t["x"] * loose
+    x, v, vp, p, _ = oracle_steps_at(prob, gi)
+    t = TOL_STEPS[prec]
+    b = Bars(f"steps {case} x{steps} {prec} iters {gi} oracle {oi}")
+    b.rel("V", g["v"][:nf], v[:nf], t["v"])
+    b.rel("p", g["p"][:nf], p[:nf], t["p"])
+    b.rel("V_prev", g["v_prev"][:nf], vp[:nf], t["v"])
+    b.absmax("x", g["x"], x, t["x"])
     if prob.n_wall:
-        assert rel_l2(g["p"][nf:], p[nf:], 1e-30 + np.linalg.norm(p[:nf])) <= t["p"] * loose
+        b.rel("p_wall", g["p"][nf:], p[nf:], t["p"])
+    b.done()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

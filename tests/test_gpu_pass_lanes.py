@@ -11,12 +11,12 @@ import pytest
 from paper_1904_00861_amd import dtsph as D
 from paper_1904_00861_amd import inputs as I
 
-from gpu_helpers import banner, oracle_steps, rel_l2
+from gpu_helpers import Bars, banner, oracle_steps, rel_l2
 
 pytestmark = pytest.mark.gpu
 
 PREC = {"fp64": D.FP64, "fp32": D.FP32}
-TOL = {"fp64": dict(v=1e-10, p=1e-9, x=1e-12), "fp32": dict(v=1e-4, p=1e-3, x=1e-7)}
+TOL = {"fp64": dict(v=1e-10, p=1e-11, x=1e-12), "fp32": dict(v=1e-5, p=1e-4, x=1e-7)}
 
 
 def _with(prob, **kw):
@@ -55,10 +55,13 @@ def test_pass_lanes_match_oracle(case, lanes, prec):
     x, v, vp, p, oreps, _ = oracle_steps(prob, 1, fixed)
     assert reps[0]["iters"] == oreps[0]["iters"] == fixed
     t = TOL[prec]
-    # the dam break's momentum right side is a cancellation of grad p / rho and g
-    vs = 10.0 if case.startswith("dam") else 1.0
-    assert np.abs(g["x"] - x).max() <= t["x"]
-    assert rel_l2(g["v"][:nf], v[:nf]) <= t["v"] * vs
-    assert rel_l2(g["p"][:nf], p[:nf]) <= t["p"]
+    # the dam break's momentum right side is a cancellation of grad p / rho and g:
+    # its velocity is compared on the |g| dt scale of those terms (zero without g)
+    vfl = float(np.linalg.norm(prob.params["g"])) * prob.params["dt"] * np.sqrt(nf)
+    b = Bars(f"pass lanes {lanes} {case} {prec}")
+    b.absmax("x", g["x"], x, t["x"])
+    b.rel("V", g["v"][:nf], v[:nf], t["v"], vfl)
+    b.rel("p", g["p"][:nf], p[:nf], t["p"])
+    b.done()
     if prob.params["steady"]:
         assert np.array_equal(g["x"], prob.x)

@@ -10,14 +10,14 @@ import oracle as O
 from paper_1904_00861_amd import dtsph as D
 from paper_1904_00861_amd import inputs as I
 
-from gpu_helpers import banner, oracle_steps, rel_l2
+from gpu_helpers import Bars, banner, oracle_steps, oracle_steps_at, rel_l2
 
 pytestmark = pytest.mark.gpu
 
 PREC = {"fp64": D.FP64, "fp32": D.FP32}
 # FP32 sums on a contracting iteration: the error settles at the size of one
 # iteration's rounding relative to the field, it does not accumulate
-TOL = {"fp64": dict(v=1e-10, p=1e-9), "fp32": dict(v=2e-4, p=2e-3)}
+TOL = {"fp64": dict(v=1e-10, p=1e-11), "fp32": dict(v=1e-5, p=1e-4)}
 
 
 def _steady(prob):
@@ -48,16 +48,21 @@ def gpu_fixed_segments(prob, n_seg, iters, precision):
 
 
 def p_floor(prm, nf):
-    """Pressure scale rho c V_ref (per particle, L2): a channel's pressure is zero
-    up to round-off, so it is compared on the scale of an acoustic disturbance."""
-    return prm["rho0"] * prm["beta"] * prm["vref"] ** 2 * np.sqrt(nf)
+    """Pressure scale rho c V_ref (per particle, L2) for the channel, whose pressure
+    vanishes identically (it is zero up to round-off); other cases compare p
+    on its own norm."""
+    if prm["periodic"][0] and not prm["periodic"][1] and prm["g"][0] != 0.0:
+        return prm["rho0"] * prm["beta"] * prm["vref"] ** 2 * np.sqrt(nf)
+    return 0.0
 
 
 def _compare(g, x, v, vp, p, nf, t, what, prm):
     assert np.array_equal(g["x"], x), f"{what}: particles moved"
-    assert rel_l2(g["v"][:nf], v[:nf]) <= t["v"], what
-    assert rel_l2(g["v_prev"][:nf], vp[:nf]) <= t["v"], what
-    assert rel_l2(g["p"][:nf], p[:nf], floor=p_floor(prm, nf)) <= t["p"], what
+    b = Bars(what)
+    b.rel("V", g["v"][:nf], v[:nf], t["v"])
+    b.rel("V_prev", g["v_prev"][:nf], vp[:nf], t["v"])
+    b.rel("p", g["p"][:nf], p[:nf], t["p"], p_floor(prm, nf))
+    b.done()
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -71,7 +76,7 @@ def test_fixed_segments_match_oracle(case, n_seg, iters, prec):
     g, greps = gpu_fixed_segments(prob, n_seg, iters, PREC[prec])
     assert [r[0]["iters"] for r in greps] == [r["iters"] for r in oreps]
     assert [r[0]["pairs"] for r in greps] == [r["pairs"] for r in oreps]
-    _compare(g, x, v, vp, p, nf, TOL[prec], case, prob.params)
+    _compare(g, x, v, vp, p, nf, TOL[prec], f"steady {case} {n_seg}x{iters} {prec}", prob.params)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -80,7 +85,7 @@ def test_free_running_segments_match_oracle(prec):
     prob.params = dict(prob.params, tol=1e-3)
     banner(f"steady free-running cavity_steady_16 {prec}")
     nf = prob.n_fluid
-    x, v, vp, p, oreps, _ = oracle_steps(prob, 4)
+    _, _, _, _, oreps, _ = oracle_steps(prob, 4)
     sim = D.Sim(prob, precision=PREC[prec])
     st, greps = sim.step(4)
     g = sim.get_state()
@@ -88,11 +93,10 @@ def test_free_running_segments_match_oracle(prec):
     gi, oi = [r[0]["iters"] for r in greps], [r["iters"] for r in oreps]
     if prec == "fp64":
         assert gi == oi
-        _compare(g, x, v, vp, p, nf, TOL[prec], "free running", prob.params)
     else:  # a stop decision may move by one iteration in FP32
         assert all(abs(a - b) <= 1 for a, b in zip(gi, oi))
-        if gi == oi:
-            _compare(g, x, v, vp, p, nf, TOL[prec], "free running", prob.params)
+    x, v, vp, p, _ = oracle_steps_at(prob, gi)
+    _compare(g, x, v, vp, p, nf, TOL[prec], f"steady free running {prec} iters {gi} oracle {oi}", prob.params)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -142,8 +146,10 @@ def test_steady_and_time_accurate_sims_share_a_context(prec):
             assert np.array_equal(sub["x"], prob.x)
         else:
             assert np.abs(sub["x"] - x).max() <= (1e-12 if prec == "fp64" else 1e-7)
-        assert rel_l2(sub["v"][:nf], v[:nf]) <= t["v"]
-        assert rel_l2(sub["p"][:nf], p[:nf], floor=p_floor(prob.params, nf)) <= t["p"]
+        b = Bars(f"mixed batch member {s} {prec}")
+        b.rel("V", sub["v"][:nf], v[:nf], t["v"])
+        b.rel("p", sub["p"][:nf], p[:nf], t["p"], p_floor(prob.params, nf))
+        b.done()
         if prec == "fp64" or prob.params["steady"]:
             # FP32 predicted positions of a moving sim may put a pair on the other
             # side of the support radius than FP64 ones do
