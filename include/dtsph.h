@@ -259,6 +259,29 @@ typedef struct dtsph_ctx dtsph_ctx;
 int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64_t *n_wall,
                  int32_t n_sims, int32_t precision, void *hip_stream, dtsph_ctx **out);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid device allocation): dtsph_create without any
+ * allocation of device memory, mapped or pinned host memory, streams or events.
+ * Arguments, checks and the resulting context are those of dtsph_create, except:
+ *   - every device array of the context lives in the library's static device
+ *     scratch of DTSPH_STATIC_SCRATCH_BYTES per GPU (held until the process
+ *     ends); ENOMEM if the context needs more (dtsph_workspace_bytes tells how
+ *     much a regular context of the same sims uses; roughly 0.8 kB per particle
+ *     in FP32, 1 kB in FP64: ~65k particles);
+ *   - one static context per GPU at a time: EINVAL while another one holds the
+ *     device's scratch (dtsph_destroy releases it). Its contents are whatever
+ *     the last static context left; creation clears what must start at zero.
+ *     Static contexts on one GPU must not overlap in time;
+ *   - the per-sim reports reach the host by a copy after a stream
+ *     synchronisation instead of through mapped memory (same results);
+ *   - options that would allocate are refused (EINVAL): PAIR_CACHE, GRAPHS,
+ *     TIMING (HIP events), and so are dtsph_set_workspace and dtsph_autotune.
+ * The context object itself is ordinary host memory. Results are identical to
+ * a dtsph_create context's, bit for bit.                                     */
+#define DTSPH_STATIC_SCRATCH_BYTES 67108864 /* 64 MiB */
+int dtsph_create_static(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64_t *n_wall,
+                        int32_t n_sims, int32_t precision, void *hip_stream, dtsph_ctx **out);
+
 /* Free the context and its device memory (synchronises its stream). NULL ok. */
 void dtsph_destroy(dtsph_ctx *ctx);
 

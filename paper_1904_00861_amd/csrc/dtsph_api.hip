@@ -19,6 +19,11 @@ struct dtsph_ctx {
     Ctx c;
 };
 
+// Device scratch of dtsph_create_static: the whole context of one static
+// context per GPU lives here. In host code this name is only a stand-in for the
+// device symbol; its device address comes from hipGetSymbolAddress (per device).
+static __device__ __align__(256) char scratch[DTSPH_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 std::string g_create_error = "no error";
@@ -71,11 +76,23 @@ void *raw_alloc(size_t bytes)
 }
 
 // Allocate a device array owned by the library and register the field that
-// holds it (see Ctx::arrays).
+// holds it (see Ctx::arrays). A static context carves it from the static
+// scratch instead (no allocation).
 template <typename P> void dev_alloc(Ctx &c, P *&slot, size_t bytes)
 {
-    void *p = raw_alloc(bytes);
-    c.owned.push_back(p);
+    void *p;
+    if (c.static_mode) {
+        const size_t b = ws_round(bytes);
+        if (c.bump_off + b > c.bump_cap)
+            throw ApiError(DTSPH_ENOMEM, "the static scratch of " + std::to_string(c.bump_cap) +
+                                             " bytes cannot hold this context (needs more than " +
+                                             std::to_string(c.bump_off + b) + ")");
+        p = c.bump + c.bump_off;
+        c.bump_off += b;
+    } else {
+        p = raw_alloc(bytes);
+        c.owned.push_back(p);
+    }
     c.arrays.push_back({(void **)&slot, bytes});
     c.device_bytes += (int64_t)bytes;
     slot = (P *)p;
@@ -130,8 +147,50 @@ void relocate(Ctx &c, char *base, size_t size)
     c.workspace_size = base ? size : 0;
 }
 
+// Per-device state of the static scratch: its device address (looked up once
+// per device) and whether a static context holds it; the host copy of a static
+// context's report mirror.
+constexpr int kMaxDevices = 64;
+constexpr size_t kStaticMirrorBytes = 16384;
+std::mutex g_static_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_busy[kMaxDevices] = {};
+alignas(64) char g_static_mirror[kMaxDevices][kStaticMirrorBytes];
+
+void *static_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) throw ApiError(DTSPH_EINVAL, "device index out of range");
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) throw HipError(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
+
+// Static contexts: bring the device copy of the mirror to the host (after the
+// stream has been synchronised), and the cleared build flags back.
+void mirror_pull(Ctx &c)
+{
+    if (c.static_mode)
+        DTSPH_HIP_CHECK(hipMemcpy(c.mirror_h, c.mirror_dev, c.mirror_bytes, hipMemcpyDeviceToHost));
+}
+
+void mirror_push_flags(Ctx &c)
+{
+    if (c.static_mode)
+        DTSPH_HIP_CHECK(hipMemcpy(c.m_flags_d, c.flags_host, sizeof(int) * F_COUNT, hipMemcpyHostToDevice));
+}
+
 void free_all(Ctx &c)
 {
+    if (c.static_mode) {  // nothing was allocated: give the scratch back
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        g_scratch_busy[c.device] = false;
+        c.static_mode = false;
+        c.mirror_h = nullptr;
+    }
     clear_graphs(c);
     if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
     c.cap_stream = nullptr;
@@ -401,6 +460,7 @@ void check_host_flags(Ctx &c)
     const int cell = c.flags_host[F_CELL_OVERFLOW], outside = c.flags_host[F_OUTSIDE];
     const int skin = c.flags_host[F_SKIN];
     for (int k = 0; k < F_COUNT; ++k) c.flags_host[k] = 0;
+    mirror_push_flags(c);
     if (skin)
         throw ApiError(DTSPH_EOVERFLOW, "a particle moving in pseudo-time (move = 2) left the candidate-list skin "
                                         "of its loop; lower dtau or dt");
@@ -426,6 +486,12 @@ void wait_reports(Ctx &c)
             if (seq[s] != c.seq) return false;
         return true;
     };
+    if (c.static_mode) {  // no mapped memory: wait for the stream, then copy
+        DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+        mirror_pull(c);
+        if (!seen()) throw ApiError(DTSPH_EHIP, "finalize completed without publishing its reports");
+        return;
+    }
     for (long spins = 1;; ++spins) {
         if (seen()) break;
         __builtin_ia32_pause();
@@ -445,6 +511,7 @@ void readback_flags(Ctx &c)
 {
     launch_publish(c);
     DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+    mirror_pull(c);
     check_host_flags(c);
 }
 
@@ -543,6 +610,7 @@ void shift_decision(Ctx &c, bool use_cand)
         c.shift_disp = c.last_disp;
     } else {
         DTSPH_HIP_CHECK(hipStreamSynchronize(c.stream));
+        mirror_pull(c);
         const double mx = *(volatile double *)c.sh_max_h;
         c.tstats.last_max_shift = mx;
         c.cand_ok = shift_cand_ok(c, mx, use_cand, c.last_disp);
@@ -944,8 +1012,8 @@ void timer_end(Ctx &c, int slot, int kind)
 
 extern "C" {
 
-int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64_t *n_wall, int32_t n_sims,
-                 int32_t precision, void *hip_stream, dtsph_ctx **out)
+static int create_impl(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64_t *n_wall, int32_t n_sims,
+                       int32_t precision, void *hip_stream, dtsph_ctx **out, bool static_mode)
 {
     if (out) *out = nullptr;
     dtsph_ctx *ctx = nullptr;
@@ -968,7 +1036,18 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         Ctx &c = ctx->c;
         DTSPH_HIP_CHECK(hipGetDevice(&c.device));
         c.stream = (hipStream_t)hip_stream;
-        DTSPH_HIP_CHECK(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+        if (static_mode) {
+            std::lock_guard<std::mutex> lk(g_static_mu);
+            char *base = (char *)static_scratch(c.device);
+            if (g_scratch_busy[c.device])
+                throw ApiError(DTSPH_EINVAL, "the static scratch of this device is held by another static context");
+            g_scratch_busy[c.device] = true;
+            c.static_mode = true;
+            c.bump = base;
+            c.bump_cap = DTSPH_STATIC_SCRATCH_BYTES;
+        } else {
+            DTSPH_HIP_CHECK(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+        }
         c.precision = precision;
         c.n_sims = n_sims;
         c.N = (int)N;
@@ -1091,10 +1170,25 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
             const size_t rb_bytes = (sizeof(MirrorRep) * n_sims + 15) / 16 * 16;
             const size_t sq_bytes = (sizeof(int) * n_sims + 15) / 16 * 16;
             const size_t bytes = fb_bytes + pb_bytes + rb_bytes + sq_bytes + 16;
-            DTSPH_HIP_CHECK(hipHostMalloc(&c.mirror_h, bytes, hipHostMallocMapped));
-            std::memset(c.mirror_h, 0, bytes);
             void *md = nullptr;
-            DTSPH_HIP_CHECK(hipHostGetDevicePointer(&md, c.mirror_h, 0));
+            if (c.static_mode) {
+                // device memory in the scratch, copied to a static host buffer after each sync
+                if (bytes > kStaticMirrorBytes)
+                    throw ApiError(DTSPH_EINVAL, "too many sims for a static context");
+                c.mirror_h = g_static_mirror[c.device];
+                c.mirror_bytes = bytes;
+                std::memset(c.mirror_h, 0, bytes);
+                const size_t b = ws_round(bytes);
+                if (c.bump_off + b > c.bump_cap) throw ApiError(DTSPH_ENOMEM, "the static scratch is too small");
+                c.mirror_dev = c.bump + c.bump_off;
+                c.bump_off += b;
+                DTSPH_HIP_CHECK(hipMemset(c.mirror_dev, 0, bytes));
+                md = c.mirror_dev;
+            } else {
+                DTSPH_HIP_CHECK(hipHostMalloc(&c.mirror_h, bytes, hipHostMallocMapped));
+                std::memset(c.mirror_h, 0, bytes);
+                DTSPH_HIP_CHECK(hipHostGetDevicePointer(&md, c.mirror_h, 0));
+            }
             char *hb = (char *)c.mirror_h, *db = (char *)md;
             c.flags_host = (int *)hb;
             c.pairs_host = (unsigned long long *)(hb + fb_bytes);
@@ -1131,6 +1225,18 @@ int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64
         if (ctx) { free_all(ctx->c); delete ctx; }
         return DTSPH_EHIP;
     }
+}
+
+int dtsph_create(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64_t *n_wall, int32_t n_sims,
+                 int32_t precision, void *hip_stream, dtsph_ctx **out)
+{
+    return create_impl(sims, n_fluid, n_wall, n_sims, precision, hip_stream, out, false);
+}
+
+int dtsph_create_static(const dtsph_sim_desc *sims, const int64_t *n_fluid, const int64_t *n_wall, int32_t n_sims,
+                        int32_t precision, void *hip_stream, dtsph_ctx **out)
+{
+    return create_impl(sims, n_fluid, n_wall, n_sims, precision, hip_stream, out, true);
 }
 
 void dtsph_destroy(dtsph_ctx *ctx)
@@ -1313,6 +1419,10 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
 {
     return guarded(ctx, [&](Ctx &c) {
+        // a static context allocates nothing: no coefficient cache, graphs or timing events
+        if (c.static_mode && value != 0 &&
+            (option == DTSPH_OPT_PAIR_CACHE || option == DTSPH_OPT_GRAPHS || option == DTSPH_OPT_TIMING))
+            throw ApiError(DTSPH_EINVAL, "option not available in a static context (it would allocate)");
         // launch shapes, grids and lists change: recorded graphs are stale
         if (option != DTSPH_OPT_TIMING && option != DTSPH_OPT_RESET_TIMING && option != DTSPH_OPT_CHUNK)
             clear_graphs(c);
@@ -1420,6 +1530,7 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
 {
     return guarded(ctx, [&](Ctx &c) {
         if (c.in_loop) throw ApiError(DTSPH_EINVAL, "dtsph_autotune: only between steps");
+        if (c.static_mode) throw ApiError(DTSPH_EINVAL, "dtsph_autotune times with HIP events: not in a static context");
         clear_graphs(c);
         const int reps = repeats > 0 ? repeats : 5;
         const bool timing = c.timing;
@@ -1583,6 +1694,7 @@ int dtsph_workspace_bytes(const dtsph_ctx *ctx, size_t *bytes)
 int dtsph_set_workspace(dtsph_ctx *ctx, void *dev, size_t bytes)
 {
     return guarded(ctx, [&](Ctx &c) {
+        if (c.static_mode) throw ApiError(DTSPH_EINVAL, "a static context keeps its arrays in the static scratch");
         char *base = (char *)dev;
         if (base == c.workspace && (base == nullptr || bytes == c.workspace_size)) return DTSPH_OK;
         if (base) {

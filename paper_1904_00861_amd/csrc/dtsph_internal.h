@@ -160,6 +160,14 @@ struct Ctx {
     std::vector<void *> owned;            // library allocations (empty while a workspace is set)
     char *workspace = nullptr;            // caller-owned, or nullptr
     size_t workspace_size = 0;
+    // context of dtsph_create_static: every device array is carved from the
+    // library's static device scratch (bump offset below), the report mirror is
+    // device memory copied to a static host buffer after each stream sync
+    bool static_mode = false;
+    char *bump = nullptr;
+    size_t bump_off = 0, bump_cap = 0;
+    char *mirror_dev = nullptr;           // static mode: device copy of the mirror
+    size_t mirror_bytes = 0;
     int64_t device_bytes = 0;
     SimDev *sims = nullptr;
     SimIter *iters = nullptr;

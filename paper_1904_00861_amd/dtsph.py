@@ -30,7 +30,9 @@ EXPORTS = [
     "dtsph_build_cells", "dtsph_predict", "dtsph_pseudo_iterate", "dtsph_correct", "dtsph_step",
     "dtsph_neighbor_list", "dtsph_set_option", "dtsph_get_timing",
     "dtsph_get_info", "dtsph_autotune", "dtsph_workspace_bytes", "dtsph_set_workspace",
+    "dtsph_create_static",
 ]
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class DtsphError(RuntimeError):
@@ -138,6 +140,7 @@ def lib() -> C.CDLL:
         P, vp = C.POINTER, C.c_void_p
         L.dtsph_create.argtypes = [P(SimDesc), P(C.c_int64), P(C.c_int64), C.c_int32, C.c_int32,
                                    vp, P(vp)]
+        L.dtsph_create_static.argtypes = L.dtsph_create.argtypes
         L.dtsph_destroy.argtypes = [vp]
         L.dtsph_destroy.restype = None
         L.dtsph_last_error.argtypes = [vp]
@@ -194,17 +197,26 @@ def _check(ctx, status: int) -> int:
 
 # ---- thin forwards with the C names ---------------------------------------------
 
-def dtsph_create(params: Sequence[dict], n_fluid: Sequence[int], n_wall: Sequence[int],
-                 precision: int = FP32, stream: Optional[int] = None):
+def _create(fn, params, n_fluid, n_wall, precision, stream):
     n = len(params)
     descs = (SimDesc * n)(*[desc_from_params(p) for p in params])
     nf = (C.c_int64 * n)(*[int(v) for v in n_fluid])
     nw = (C.c_int64 * n)(*[int(v) for v in n_wall])
     out = C.c_void_p()
-    st = lib().dtsph_create(descs, nf, nw, n, int(precision), C.c_void_p(stream or 0), C.byref(out))
+    st = fn(descs, nf, nw, n, int(precision), C.c_void_p(stream or 0), C.byref(out))
     if st < 0:
         raise DtsphError(st, last_error(None))
     return out
+
+
+def dtsph_create(params: Sequence[dict], n_fluid: Sequence[int], n_wall: Sequence[int],
+                 precision: int = FP32, stream: Optional[int] = None):
+    return _create(lib().dtsph_create, params, n_fluid, n_wall, precision, stream)
+
+
+def dtsph_create_static(params: Sequence[dict], n_fluid: Sequence[int], n_wall: Sequence[int],
+                        precision: int = FP32, stream: Optional[int] = None):
+    return _create(lib().dtsph_create_static, params, n_fluid, n_wall, precision, stream)
 
 
 def dtsph_destroy(ctx) -> None:
@@ -311,7 +323,7 @@ class Sim:
     """One context over one or more problems (``inputs.Problem``), state in torch
     float64 device tensors in caller order."""
 
-    def __init__(self, problems, precision: int = FP32, device: str = "cuda:0"):
+    def __init__(self, problems, precision: int = FP32, device: str = "cuda:0", static: bool = False):
         import torch
 
         self.torch = torch
@@ -324,9 +336,9 @@ class Sim:
         self.precision = precision
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            self.ctx = dtsph_create([p.params for p in self.problems],
-                                    [p.n_fluid for p in self.problems],
-                                    [p.n_wall for p in self.problems], precision, stream)
+            create = dtsph_create_static if static else dtsph_create
+            self.ctx = create([p.params for p in self.problems], [p.n_fluid for p in self.problems],
+                              [p.n_wall for p in self.problems], precision, stream)
         z3 = lambda: torch.zeros((self.n, 3), dtype=torch.float64, device=self.device)
         z1 = lambda: torch.zeros((self.n,), dtype=torch.float64, device=self.device)
         self.t = dict(x=z3(), v=z3(), v_prev=z3(), p=z1(), x_iter=z3(), v_iter=z3(), p_iter=z1(),
