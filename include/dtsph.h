@@ -360,7 +360,10 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *
 
 /* Options (value semantics per option). Errors: EINVAL.                    */
 #define DTSPH_OPT_TIMING 1     /* n >= 1: time every n-th pair-pass, wall-pass
-                                  and build launch with HIP events; 0: off  */
+                                  and build launch with HIP events; -1: the
+                                  first pair and wall pass of every loop
+                                  (whole workload, queued behind the build)
+                                  and every build; 0: off                  */
 #define DTSPH_OPT_RESET_TIMING 2
 #define DTSPH_OPT_CHUNK 3      /* iterations launched between stop checks (>=1) */
 #define DTSPH_OPT_BLOCK 4      /* pair-pass workgroup size: 64, 128 or 256    */

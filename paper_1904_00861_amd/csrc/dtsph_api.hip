@@ -806,6 +806,7 @@ template <typename T> void do_correct(Ctx &c)
 bool pass_timer_fires(const Ctx &c, int n)
 {
     if (!c.timing) return false;
+    if (c.timing_first) return true;  // the segment holds the loop's first pass
     for (int k = 0; k < n; ++k)
         if ((c.timer_count[0] + k) % c.timing_every == 0) return true;
     return false;
@@ -972,11 +973,20 @@ template <typename F> auto by_precision(Ctx &c, F &&f)
 
 namespace dtsph {
 
+// The first-pass mode samples the first pair and wall pass of every loop (every
+// sim takes part: the launch covers the whole workload, and it is queued behind
+// the build, so its events hold the kernel alone) and every build.
+bool timer_skips(Ctx &c, int kind)
+{
+    if (c.timing_first) return kind <= 1 && c.pass_index != 0;
+    return c.timer_count[kind]++ % c.timing_every != 0;
+}
+
 int timer_begin(Ctx &c, int kind)
 {
     if (!c.timing) return -1;
     if (c.in_segment && kind != 0) return -1;  // graph segments time pair passes only
-    if (c.timer_count[kind]++ % c.timing_every != 0) return -1;
+    if (timer_skips(c, kind)) return -1;
     size_t k = c.ev_used;
     c.ev_used += 2;
     DTSPH_HIP_CHECK(hipEventRecord(pool_event(c, k), c.stream));
@@ -988,7 +998,7 @@ int timer_slot(Ctx &c, int kind)
 {
     if (!c.timing) return -1;
     if (c.in_segment && kind != 0) return -1;
-    if (c.timer_count[kind]++ % c.timing_every != 0) return -1;
+    if (timer_skips(c, kind)) return -1;
     size_t k = c.ev_used;
     c.ev_used += 2;
     pool_event(c, k + 1);
@@ -1428,8 +1438,9 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
             clear_graphs(c);
         switch (option) {
         case DTSPH_OPT_TIMING:
-            if (value < 0) throw ApiError(DTSPH_EINVAL, "timing sample interval must be >= 0");
+            if (value < -1) throw ApiError(DTSPH_EINVAL, "timing sample interval must be >= -1");
             c.timing = value != 0;
+            c.timing_first = value == -1;
             c.timing_every = value > 0 ? (int)std::min<int64_t>(value, 1 << 20) : 1;
             c.timer_count[0] = c.timer_count[1] = c.timer_count[2] = c.timer_count[3] = 0;
             break;

@@ -235,6 +235,7 @@ struct Ctx {
     // timing
     bool timing = false;
     int timing_every = 1;                 // time every n-th launch of each kind
+    bool timing_first = false;            // time the first pair and wall pass of each loop (and every build)
     long long timer_count[4] = {0, 0, 0, 0};  // pair pass, wall pass, full build, list filter
     int pass_index = 0;                   // launch index of the next pair pass in the loop
     hipEvent_t ext_start = nullptr, ext_stop = nullptr;  // events of a timed pass launch

@@ -159,3 +159,23 @@ def test_periodic_position_outside_box_is_rejected():
     st, _ = sim.step(1)
     sim.close()
     assert st >= 0
+
+
+def test_first_pass_timing_mode():
+    # timing mode -1 samples the first pair pass of every loop (the whole batch
+    # takes part) and every full build; -2 is rejected
+    probs = [I.tgv2d(24, seed=1), I.cavity(14)]
+    banner("first-pass timing mode")
+    sim = D.Sim(probs, precision=D.FP32)
+    with pytest.raises(D.DtsphError):
+        sim.set_option(D.OPT_TIMING, -2)
+    sim.set_option(D.OPT_TIMING, -1)
+    sim.set_option(D.OPT_RESET_TIMING, 0)
+    st, reps = sim.step(4)
+    tm = sim.timing()
+    sim.close()
+    assert tm["pass_launches"] == 4
+    assert tm["pass_pairs"] == sum(sum(r["pairs"] for r in step) for step in reps)
+    assert tm["pass_particles"] == 4 * sum(p.n_fluid for p in probs)
+    assert tm["build_launches"] == tm["full_builds"] and tm["build_particles"] == tm["full_builds"] * sum(p.n for p in probs)
+    assert tm["pass_ms"] > 0 and tm["build_ms"] > 0
