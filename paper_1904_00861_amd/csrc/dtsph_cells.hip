@@ -223,8 +223,10 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
     // loads are in flight while the rank among the cell's members is counted
     const int os = A.orig_in[s];
     const int sid = A.simid_in[s];
-    double xs[3], xns[3];
-    for (int a = 0; a < 3; ++a) {
+    // in 2D the third component is zero everywhere: written, not read
+    const int dim = A.dim;
+    double xs[3] = {0.0, 0.0, 0.0}, xns[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < dim; ++a) {
         xs[a] = A.x_in[a * N + s];
         xns[a] = A.xn_in[a * N + s];
     }
@@ -234,7 +236,7 @@ __global__ void __launch_bounds__(kThreads) k_rank_gather(GatherArgs<T> A)
     T dp = T(0);
     double pmv = 0.0, pnv = 0.0;
     if (fl) {
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; a < dim; ++a) {
             vn[a] = A.vn_in[a * Nf + s];
             dvv[a] = A.dv_in[a * Nf + s];
             ww[a] = A.w_in[a * Nf + s];
