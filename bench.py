@@ -100,6 +100,21 @@ def traffic_from_profile(cfg, dtype):
     return float(m_tr.group(1)), float(m_tr.group(2))
 
 
+def apply_shape(sim, shape):
+    """Fixed launch shape (L, B, G, M): pair-pass lanes per particle, workgroup
+    size, neighbour-build lanes per particle (0: the staged-tile kernel), cell
+    subdivision."""
+    from paper_1904_00861_amd import dtsph as D
+
+    lanes, block, nbr_lanes, cell_div = shape
+    sim.set_option(D.OPT_LANES, lanes)
+    sim.set_option(D.OPT_BLOCK, block)
+    sim.set_option(D.OPT_NBR_TILES, 1 if nbr_lanes == 0 else 0)
+    if nbr_lanes:
+        sim.set_option(D.OPT_NBR_LANES, nbr_lanes)
+    sim.set_option(D.OPT_CELL_DIV, cell_div)
+
+
 def run_leg(problems, precision, steps, warmup, timing_every, shape=None, pair_cache=0):
     import torch
     from paper_1904_00861_amd import dtsph as D
@@ -109,19 +124,18 @@ def run_leg(problems, precision, steps, warmup, timing_every, shape=None, pair_c
         sim.set_option(D.OPT_PAIR_CACHE, pair_cache)
     if shape:  # fixed launch configuration instead of the autotuner
         lanes, block, nbr_lanes, cell_div = shape
-        sim.set_option(D.OPT_LANES, lanes)
-        sim.set_option(D.OPT_BLOCK, block)
-        sim.set_option(D.OPT_NBR_LANES, nbr_lanes)
-        sim.set_option(D.OPT_CELL_DIV, cell_div)
-        tune = dict(lanes=lanes, block=block, nbr_lanes=nbr_lanes, cell_div=cell_div, fixed=True)
-        log(f"fixed launch shape: pass lanes {lanes} block {block}, neighbour-build lanes {nbr_lanes}, "
-            f"cell subdivision {cell_div}")
+        apply_shape(sim, shape)
+        tune = dict(lanes=lanes, block=block, nbr_lanes=nbr_lanes, nbr_tiles=int(nbr_lanes == 0),
+                    cell_div=cell_div, fixed=True)
+        log(f"fixed launch shape: pass lanes {lanes} block {block}, neighbour-build lanes {nbr_lanes} "
+            f"(0: staged tiles), cell subdivision {cell_div}")
     else:
         tune = sim.autotune()
         log(f"autotune: pass lanes {tune['lanes']} block {tune['block']} ({tune['us']:.2f} us); " +
             " ".join(f"{e['lanes']}x{e['block']}:{e['us']:.1f}" for e in tune["entries"]) +
             f"; cell subdivision {tune['cell_div']} (full build {tune['build_us']:.1f} us)"
-            f"; neighbour build lanes {tune['nbr_lanes']} ({tune['nbr_us']:.1f} us), "
+            f"; neighbour build {'staged tiles' if tune['nbr_tiles'] else 'lanes ' + str(tune['nbr_lanes'])} "
+            f"({tune['nbr_us']:.1f} us), "
             f"filter lanes {tune['filter_lanes']} ({tune['filter_us']:.1f} us)")
     if warmup:
         sim.step(warmup)
@@ -173,7 +187,8 @@ def leg_summary(problems, leg, dtype, steps, cfg=None, timing_every=-1):
                   pairs_per_launch=round(tm["pass_pairs"] / tm["pass_launches"], 1),
                   particles_per_launch=round(tm["pass_particles"] / tm["pass_launches"], 1),
                   launch_shape=dict(lanes_per_particle=leg["tune"]["lanes"], block=leg["tune"]["block"],
-                                    nbr_lanes=leg["tune"]["nbr_lanes"], cell_div=leg["tune"]["cell_div"],
+                                    nbr_lanes=leg["tune"]["nbr_lanes"], nbr_tiles=leg["tune"]["nbr_tiles"],
+                                    cell_div=leg["tune"]["cell_div"],
                                     autotuned=not leg["tune"].get("fixed", False)))
         if dtype == "f32":
             rf["frac_of_nonpacked_peak"] = round(achieved / PEAK_NONPACKED_F32, 4)
@@ -300,11 +315,7 @@ def counter_run(problems, prec, steps, warmup, fixed, shape):
 
     sim = D.Sim(problems, precision=prec)
     if shape:
-        lanes, block, nbr_lanes, cell_div = shape
-        sim.set_option(D.OPT_LANES, lanes)
-        sim.set_option(D.OPT_BLOCK, block)
-        sim.set_option(D.OPT_NBR_LANES, nbr_lanes)
-        sim.set_option(D.OPT_CELL_DIV, cell_div)
+        apply_shape(sim, shape)
     pairs = 0
     for k in range(warmup + steps):
         sim.predict()
@@ -362,7 +373,8 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="no HIP events in the timed region")
     ap.add_argument("--shape", default=None, metavar="L,B,G,M",
                     help="fixed launch shape instead of the autotuner: pair-pass lanes per particle, "
-                         "workgroup size, neighbour-build lanes, cell subdivision (for profiling runs)")
+                         "workgroup size, neighbour-build lanes (0: the staged-tile kernel), cell subdivision "
+                         "(for profiling runs)")
     ap.add_argument("--timing-every", type=int, default=-1, metavar="N",
                     help="HIP events around every N-th pair-pass and build launch in the timed region; -1 "
                          "(default): the first pair pass of every step (the whole workload takes part and the "

@@ -428,12 +428,23 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *
                                   the pair passes see it, i.e. float32
                                   separations of absolute coordinates instead
                                   of exact fixed-point ones; no effect in FP64 */
+#define DTSPH_OPT_NBR_TILES 15 /* neighbour-list build of 2D contexts: 1
+                                  one workgroup per strip of cells stages the
+                                  positions of the strip's neighbourhood in
+                                  LDS and builds its particles' lists from
+                                  there; 0 (default) one lane group per
+                                  particle reading positions from global
+                                  memory. Same lists either way; 3D contexts
+                                  and periodic axes with fewer than 2m+3
+                                  cells always use the latter. The
+                                  autotuner times both.                      */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the launch shapes. Between steps only (EINVAL in the loop).
  * Builds the cell lists if needed, picks the cell subdivision m in {1, 2, 3}
- * together with the neighbour kernel's lanes per particle (1, 2, 4, 8) by
- * timing full builds of every pair (they only reorder the state), then times
+ * together with the neighbour kernel (lanes per particle 1, 2, 4, 8, or the
+ * staged-tile kernel where it applies) by timing full builds of every pair
+ * (they only reorder the state), then times
  * the rate pass of the predictor (it writes only scratch between steps, so the state is unchanged)
  * for every lanes-per-particle in {1, 2, 4, 8} and workgroup size in {64, 128,
  * 256}, timed as the best of three windows of `repeats` launches (<= 0: 5),
@@ -454,7 +465,8 @@ typedef struct dtsph_tune_report {
     int32_t nbr_lanes, filter_lanes; /* lanes per particle of the neighbour-list
                                         build and of the candidate filter */
     double nbr_us, filter_us;
-    int32_t cell_div, reserved2;     /* cell subdivision and its full-build time */
+    int32_t cell_div;                /* cell subdivision and its full-build time */
+    int32_t nbr_tiles;               /* 1: the staged-tile neighbour kernel */
     double build_us;
 } dtsph_tune_report;
 

@@ -31,7 +31,7 @@ std::string g_create_error = "no error";
 // autotuner choices of this process: key -> (pass lanes, pass block, neighbour-kernel
 // lanes, filter lanes, cell subdivision)
 std::mutex g_tune_mu;
-std::map<std::string, std::array<int, 5>> g_tune_cache;
+std::map<std::string, std::array<int, 6>> g_tune_cache;
 
 std::string tune_key(const Ctx &c)
 {
@@ -252,6 +252,66 @@ void set_grid(SimDev &S, int m)
             S.cs[a] = S.inv_cs[a] = 1.0;
         }
     }
+    // strips of the staged neighbour kernel (2D): about 256 particles at the
+    // lattice density, three times wider than tall (a strip row is one run of
+    // consecutive keys)
+    S.tile_w = S.tile_h = 0;
+    if (S.dim == 2) {
+        const double ppc = S.cs[0] * S.cs[1] / (S.mass / S.rho0);  // particles per cell
+        const double target = std::max(16.0, 256.0 / ppc);          // cells per strip
+        int th = (int)std::lround(std::sqrt(target / 3.0));
+        th = std::max(1, std::min(std::min(th, S.ncell[1]), kMaxTileRows));
+        int tw = (int)std::ceil(target / th);
+        tw = std::max(1, std::min(tw, S.ncell[0]));
+        S.tile_w = tw;
+        S.tile_h = th;
+    }
+}
+
+// Strips of the staged neighbour kernel at the sims' current grids: per sim its
+// fluid-cell strips and, with walls, its wall-cell strips (0 unless every sim is 2D).
+int64_t count_strips(const std::vector<SimDev> &sims)
+{
+    int64_t n = 0;
+    for (const SimDev &S : sims) {
+        if (S.dim != 2) return 0;
+        n += (int64_t)ceil_div(S.ncell[0], S.tile_w) * ceil_div(S.ncell[1], S.tile_h) * (S.nw > 0 ? 2 : 1);
+    }
+    return n;
+}
+
+// The strip table and LDS sizes for the current subdivision. The staged kernel
+// applies when every sim is 2D and every periodic axis has at least 2m+3 cells
+// (one image shift per staged column, as in k_nbr's trimmed path); otherwise
+// n_strips stays 0 and builds use the per-particle kernel.
+void setup_strips(Ctx &c)
+{
+    c.n_strips = 0;
+    if (!c.strips) return;
+    std::vector<int4> v;
+    int pmax = 0, offmax = 0;
+    for (int s = 0; s < c.n_sims; ++s) {
+        const SimDev &S = c.sims_h[s];
+        const int m = S.cell_div, m3 = 2 * m + 3;
+        if (S.dim != 2 || (S.periodic[0] && S.ncell[0] < m3) || (S.periodic[1] && S.ncell[1] < m3)) return;
+        const int ntp = S.nw > 0 ? 2 : 1;
+        for (int tp = 0; tp < ntp; ++tp)
+            for (int y0 = 0; y0 < S.ncell[1]; y0 += S.tile_h)
+                for (int x0 = 0; x0 < S.ncell[0]; x0 += S.tile_w) v.push_back(make_int4(s, tp, y0, x0));
+        const int vx = S.tile_w + 2 * m, vy = S.tile_h + 2 * m;
+        offmax = std::max(offmax, ntp * vx * vy + 1);
+        // staged particles at the lattice density (fluid cells; wall cells hold
+        // a few layers), with room for 2.5 times that
+        const double ppc = S.cs[0] * S.cs[1] / (S.mass / S.rho0);
+        pmax = std::max(pmax, (int)std::ceil(2.5 * vx * vy * ppc) + 64);
+    }
+    // LDS per workgroup: pmax positions (16 B) and slots (4 B), offmax cell offsets
+    const int room = (65536 - 1024 - 4 * offmax) / 20;
+    if ((int64_t)v.size() > c.strip_cap || room < 64) return;
+    c.tile_pmax = std::min(pmax, room);
+    c.tile_offmax = offmax;
+    DTSPH_HIP_CHECK(hipMemcpy(c.strips, v.data(), sizeof(int4) * v.size(), hipMemcpyHostToDevice));
+    c.n_strips = (int)v.size();
 }
 
 // Key bases for the current subdivision: sim s's fluid cells are keys
@@ -267,6 +327,7 @@ void setup_keys(Ctx &c, int m)
     if (C > c.C_max) throw ApiError(DTSPH_EINVAL, "cell grid exceeds the key tables sized at creation");
     c.C = (int)C;
     c.cell_div = m;
+    setup_strips(c);
 }
 
 SimDev make_simdev(const dtsph_sim_desc &d, int64_t nf, int64_t nw)
@@ -1139,6 +1200,19 @@ static int create_impl(const dtsph_sim_desc *sims, const int64_t *n_fluid, const
         c.capc = c.cap;
         dev_alloc(c, c.cand, 4 * (size_t)c.capc * (size_t)N);
         dev_alloc(c, c.ccnt, 4 * (size_t)N);
+        {   // strip table: room for the most strips of any subdivision
+            int64_t most = 0;
+            for (int m = 1; m <= 3; ++m) {
+                std::vector<SimDev> g = c.sims_h;
+                for (SimDev &S : g) set_grid(S, m);
+                most = std::max(most, count_strips(g));
+            }
+            if (most > 0 && most < INT32_MAX) {
+                c.strip_cap = (int)most;
+                dev_alloc(c, c.strips, sizeof(int4) * (size_t)most);
+            }
+        }
+        setup_keys(c, c.cell_div);
         // lanes per particle: enough threads for ~8 waves per SIMD on 256 CUs
         {
             int lpp = 1;
@@ -1151,6 +1225,7 @@ static int create_impl(const dtsph_sim_desc *sims, const int64_t *n_fluid, const
                 c.block = it->second[1];
                 c.g_nbr = it->second[2];
                 c.g_filter = it->second[3];
+                c.nbr_tiles = c.strips ? it->second[5] : 0;
                 setup_keys(c, it->second[4]);
             }
         }
@@ -1523,6 +1598,10 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
                 throw ApiError(DTSPH_EINVAL, "filter lanes must be 0, 1, 2, 4 or 8");
             c.g_filter = (int)value;
             break;
+        case DTSPH_OPT_NBR_TILES:
+            if (value != 0 && value != 1) throw ApiError(DTSPH_EINVAL, "neighbour tiles must be 0 or 1");
+            c.nbr_tiles = c.strips ? (int)value : 0;
+            break;
         case DTSPH_OPT_LANES:
             if (value != 1 && value != 2 && value != 4 && value != 8)
                 throw ApiError(DTSPH_EINVAL, "lanes per particle must be 1, 2, 4 or 8");
@@ -1577,21 +1656,27 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
         // best lane count depends on the subdivision
         {
             double best = 1e300;
-            int best_m = c.cell_div, best_g = 1;
+            int best_m = c.cell_div, best_g = 1, best_t = 0;
             for (int m = 1; m <= 3; ++m) {
                 setup_keys(c, m);
                 DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
-                for (int g = 1; g <= 8; g *= 2) {
-                    c.g_nbr = g;
+                // g = 0: the staged-tile kernel (where it applies), else lanes per particle
+                for (int g = 0; g <= 8; g = g ? 2 * g : 1) {
+                    if (g == 0 && c.n_strips == 0) continue;
+                    c.nbr_tiles = g == 0 ? 1 : 0;
+                    if (g > 0) c.g_nbr = g;
                     const double us = by_precision(c, [&](auto t) {
                         using T = decltype(t);
                         build_cells<T>(c);
                         return time_us([&] { build_cells<T>(c); });
                     });
-                    if (us < best) { best = us; best_m = m; best_g = g; }
+                    if (us < best) { best = us; best_m = m; best_g = g; best_t = c.nbr_tiles; }
                 }
             }
-            c.g_nbr = best_g;
+            // the per-particle kernel stays the fallback of a tiled context
+            // (3D or small periodic grids at another subdivision)
+            c.g_nbr = best_g > 0 ? best_g : 1;
+            c.nbr_tiles = best_t;
             setup_keys(c, best_m);
             DTSPH_HIP_CHECK(hipMemcpy(c.sims, c.sims_h.data(), sizeof(SimDev) * c.n_sims, hipMemcpyHostToDevice));
             by_precision(c, [&](auto t) {
@@ -1651,6 +1736,7 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
             rep.filter_us = best;
         }
         rep.nbr_lanes = c.g_nbr;
+        rep.nbr_tiles = c.nbr_tiles && c.n_strips > 0 ? 1 : 0;
         rep.filter_lanes = c.g_filter;
         readback_flags(c);  // a capacity overflow in the trials surfaces here
         (void)hipEventDestroy(e0);
@@ -1658,7 +1744,7 @@ int dtsph_autotune(dtsph_ctx *ctx, int32_t repeats, dtsph_tune_report *out)
         c.timing = timing;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tune_cache[tune_key(c)] = {c.lpp, c.block, c.g_nbr, c.g_filter, c.cell_div};
+            g_tune_cache[tune_key(c)] = {c.lpp, c.block, c.g_nbr, c.g_filter, c.cell_div, c.nbr_tiles};
         }
         if (out) *out = rep;
         return DTSPH_OK;

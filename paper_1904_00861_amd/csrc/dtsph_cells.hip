@@ -788,6 +788,238 @@ __global__ void __launch_bounds__(kThreads) k_filter(NbrArgs<T> A)
     }
 }
 
+// ---- staged-tile neighbour kernel (2D) ---------------------------------------
+// One workgroup per strip of tile_w x tile_h cells of one type (fluid or wall
+// cells) of one sim. Every particle that a particle of the strip can reach sits
+// in the strip's cells widened by cell_div cells on each side: fluid cells, and
+// for the fluid particles of a sim with walls also wall cells. Their positions
+// and slots are staged in LDS once, in (cell type, row, column) order with the
+// periodic images as separate columns, and each particle then visits the same
+// rows and trimmed windows as k_nbr, in the same order, with the same float64
+// predicate and appends, reading its candidates from LDS: the lists are the
+// same. A strip whose neighbourhood holds more than pmax particles reads them
+// from global memory instead. The candidate loop has no global loads, so the
+// list stores never hold it up.
+constexpr int kTileThreads = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(kTileThreads) k_nbr_tile(NbrArgs<T> A, const int4 *__restrict__ strips, int pmax)
+{
+    extern __shared__ double2 tile_lds[];
+    __shared__ int s_pb[kMaxTileRows + 1], s_sb[kMaxTileRows], s_scan[kTileThreads / 64 + 1];
+    const int4 st = strips[blockIdx.x];
+    const int s = st.x, tp = st.y, y0 = st.z, x0 = st.w;
+    const SimDev &S = A.sims[s];
+    const int nx = S.ncell[0], ny = S.ncell[1], md = S.cell_div;
+    const int xe = min(x0 + S.tile_w, nx), ye = min(y0 + S.tile_h, ny), nys = ye - y0;
+    const uint32_t *__restrict__ cstart = A.cell_start;
+    const int tid = threadIdx.x;
+    // the strip's particles: one contiguous run of slots per cell row
+    if (tid < nys) {
+        const int row = S.key_base + (tp ? A.C : 0) + (y0 + tid) * nx;
+        const int b = (int)cstart[row + x0], e = (int)cstart[row + xe];
+        s_sb[tid] = b;
+        s_pb[tid + 1] = e - b;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s_pb[0] = 0;
+        for (int t = 0; t < nys; ++t) s_pb[t + 1] += s_pb[t];
+    }
+    __syncthreads();
+    const int np = s_pb[nys];
+    if (np == 0) return;  // an empty strip (uniform)
+
+    // staged columns: virtual cells x0 - m .. x0 + tile_w - 1 + m of virtual rows
+    // y0 - m .. y0 + tile_h - 1 + m, per staged cell type
+    const int ntp = (tp == 0 && S.nw > 0) ? 2 : 1;
+    const int VX = S.tile_w + 2 * md, VY = S.tile_h + 2 * md;
+    const int NC = ntp * VY * VX;
+    double2 *lpos = tile_lds;
+    int *lslot = (int *)(lpos + pmax);
+    int *off = lslot + pmax;  // NC + 1 entries: first staged index of each cell
+    auto phys = [](int v, int n, int per) { return per ? (v < 0 ? v + n : (v >= n ? v - n : v)) : v; };
+    for (int q = tid; q < NC; q += kTileThreads) {
+        const int r = q / VX, c = q - r * VX;
+        const int t = r / VY;
+        const int vy = y0 - md + (r - t * VY), vx = x0 - md + c;
+        const bool ok = (S.periodic[1] || (vy >= 0 && vy < ny)) && (S.periodic[0] || (vx >= 0 && vx < nx));
+        int n = 0;
+        if (ok) {
+            const int key = S.key_base + (t ? A.C : 0) + phys(vy, ny, S.periodic[1]) * nx + phys(vx, nx, S.periodic[0]);
+            n = (int)cstart[key + 1] - (int)cstart[key];
+        }
+        off[q] = n;
+    }
+    __syncthreads();
+    {   // exclusive scan of the counts in place; off[NC] = the total
+        const int per = (NC + kTileThreads - 1) / kTileThreads;
+        const int b = min(tid * per, NC), e = min(b + per, NC);
+        int sum = 0;
+        for (int k = b; k < e; ++k) sum += off[k];
+        const int lane = tid & 63, wave = tid >> 6;
+        int incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) s_scan[wave] = incl;
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int w = 0; w < kTileThreads / 64; ++w) {
+                const int v = s_scan[w];
+                s_scan[w] = acc;
+                acc += v;
+            }
+            s_scan[kTileThreads / 64] = acc;
+        }
+        __syncthreads();
+        int run = s_scan[wave] + incl - sum;
+        for (int k = b; k < e; ++k) {
+            const int v = off[k];
+            off[k] = run;
+            run += v;
+        }
+        if (tid == 0) off[NC] = s_scan[kTileThreads / 64];
+        __syncthreads();
+    }
+    const int nst = off[NC];
+    const bool staged = nst <= pmax;  // uniform
+    const double2 *__restrict__ xr = (const double2 *)A.xr;
+    if (staged) {
+        for (int q = tid; q < nst; q += kTileThreads) {
+            int lo = 0, hi = NC - 1;  // the cell holding staged particle q: last k with off[k] <= q
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            const int r = lo / VX, c = lo - r * VX;
+            const int t = r / VY;
+            const int vy = y0 - md + (r - t * VY), vx = x0 - md + c;
+            const int key = S.key_base + (t ? A.C : 0) + phys(vy, ny, S.periodic[1]) * nx + phys(vx, nx, S.periodic[0]);
+            const int j = (int)cstart[key] + (q - off[lo]);
+            lpos[q] = xr[j];
+            lslot[q] = j;
+        }
+    }
+    __syncthreads();
+
+    const int N = A.N, cap = A.cap, capc = A.capc;
+    const double cr2 = S.cand_r2;
+    for (int pi = tid; pi < np; pi += kTileThreads) {
+        int t = 0;
+        while (t + 1 < nys && s_pb[t + 1] <= pi) ++t;
+        const int i = s_sb[t] + (pi - s_pb[t]);
+        const double2 me = xr[i];
+        const Probe<2> P = make_probe<2>(S, me.x, me.y, 0.0);
+        {
+            const double pos3[3] = {P.xi, P.yi, 0.0};
+            write_pos_record<T>(S, A.prec, i, pos3);
+        }
+        const int cx = cell_coord(P.xi, S.lo[0], S.inv_cs[0], nx);
+        const int cy = cell_coord(P.yi, S.lo[1], S.inv_cs[1], ny);
+        // the row windows of k_nbr's trimmed path (float, cell units relative
+        // to the particle's cell, widened by 1e-5 cells)
+        auto frac = [&](double p, int a, int c) {
+            const double f = (p - S.lo[a]) * S.inv_cs[a] - (double)c;
+            const double lim = (double)md + 3.0;
+            return (float)(f < -lim ? -lim : (f > lim + 1.0 ? lim + 1.0 : f));
+        };
+        const float fx = frac(P.xi, 0, cx), fy = frac(P.yi, 1, cy);
+        const float csy = (float)S.cs[1], icsx = (float)S.inv_cs[0], cr2f = (float)cr2;
+        // next free entries of the two lists (column-major: one column per entry)
+        int *__restrict__ pn = A.nbr + i;
+        int *__restrict__ pc = A.cand + i;
+        ListCursor cur;
+        int cf = -1, ccf = 0;
+        auto test = [&](const double2 &q, int j, double sx, double sy) {
+            const double r2 = P.r2s(q, sx, sy, 0.0);
+            const bool ok = j != i;
+            const bool in_c = ok && r2 < cr2, in_x = ok && r2 < P.kh2;
+            if (in_c && cur.ctotal < capc) *pc = j;
+            if (in_x && cur.total < cap) *pn = j;
+            if (in_c) { ++cur.ctotal; pc += N; }
+            if (in_x) { ++cur.total; pn += N; }
+        };
+        for (int tt = 0; tt < ntp; ++tt) {
+            if (tt == 1 && cf < 0) { cf = cur.total; ccf = cur.ctotal; }
+            for (int v = 0; v <= 2 * md; ++v) {
+                const int vy = cy - md + v;
+                if (!P.py && (vy < 0 || vy >= ny)) continue;
+                const int py = phys(vy, ny, P.py);
+                const double sy = P.py ? (vy < 0 ? P.Ly : (vy >= ny ? -P.Ly : 0.0)) : 0.0;
+                const float o = (float)(vy - cy);  // the row's slab is [o, o + 1) in cell units
+                const float below = (!P.py && py == 0) ? 0.f : o - fy;
+                const float above = (!P.py && py == ny - 1) ? 0.f : fy - (o + 1.f);
+                const float dd = fmaxf(below, above) - 1e-5f;
+                const float dy = dd > 0.f ? dd * csy : 0.f;
+                const float rem = cr2f - dy * dy;
+                if (rem < 0.f) continue;
+                const float wc = __builtin_amdgcn_sqrtf(rem) * icsx + 1e-5f;
+                int lo_c = cx + (int)floorf(fx - wc);
+                int hi_c = cx + (int)floorf(fx + wc);
+                lo_c = lo_c > cx - md ? lo_c : cx - md;
+                hi_c = hi_c < cx + md ? hi_c : cx + md;
+                // runs in virtual columns: [a0, b0] unshifted, then [a1, b1] with shift s1
+                int a0, b0, a1 = 0, b1 = -1;
+                double s1 = 0.0;
+                if (P.px) {
+                    a0 = lo_c > 0 ? lo_c : 0;
+                    b0 = hi_c < nx - 1 ? hi_c : nx - 1;
+                    if (lo_c < 0) { a1 = lo_c; b1 = -1; s1 = P.Lx; }
+                    else if (hi_c > nx - 1) { a1 = nx; b1 = hi_c; s1 = -P.Lx; }
+                } else {
+                    // edge cells extend outwards: a window beyond the grid still meets them
+                    a0 = lo_c < 0 ? 0 : (lo_c > nx - 1 ? nx - 1 : lo_c);
+                    b0 = hi_c < 0 ? 0 : (hi_c > nx - 1 ? nx - 1 : hi_c);
+                }
+                const int rr = (tt * VY + (vy - (y0 - md))) * VX - (x0 - md);
+                const int kb = S.key_base + (tt ? A.C : 0) + py * nx;
+                for (int k = 0; k < 2; ++k) {
+                    const int va = k ? a1 : a0, vb = k ? b1 : b0;
+                    if (vb < va) continue;
+                    const double sx = k ? s1 : 0.0;
+                    if (staged) {
+                        // a run's cells are consecutive keys, so its slots are
+                        // consecutive: slot = first slot + offset in the run;
+                        // four candidates' positions are read before the tests
+                        const int qa = off[rr + va], qb = off[rr + vb + 1];
+                        if (qa < qb) {
+                            const int j0 = lslot[qa] - qa;
+                            for (int q0 = qa; q0 < qb; q0 += 4) {
+                                double2 pq[4];
+#pragma unroll
+                                for (int u = 0; u < 4; ++u) pq[u] = lpos[q0 + u < qb ? q0 + u : qb - 1];
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    if (q0 + u < qb) test(pq[u], j0 + q0 + u, sx, sy);
+                            }
+                        }
+                    } else {
+                        const int ja = (int)cstart[kb + phys(va, nx, P.px)];
+                        const int jb = (int)cstart[kb + phys(vb, nx, P.px) + 1];
+                        for (int j = ja; j < jb; ++j) test(xr[j], j, sx, sy);
+                    }
+                }
+            }
+        }
+        if (cf < 0) { cf = cur.total; ccf = cur.ctotal; }
+        int cw = cur.total - cf, ccw = cur.ctotal - ccf;
+        if (cur.total > cap || cur.ctotal > capc) {
+            atomicOr(&A.flags[F_NBR_OVERFLOW], 1);
+            atomicMax(&A.flags[F_NBR_NEEDED], cur.total > cur.ctotal ? cur.total : cur.ctotal);
+            cf = cf < cap ? cf : cap;
+            cw = cap - cf < cw ? cap - cf : cw;
+            ccf = ccf < capc ? ccf : capc;
+            ccw = capc - ccf < ccw ? capc - ccf : ccw;
+        }
+        A.cnt[i] = (uint32_t)cf | ((uint32_t)cw << 16);
+        A.ccnt[i] = (uint32_t)ccf | ((uint32_t)ccw << 16);
+    }
+}
+
 inline int grid_for(int n) { return n > 0 ? ceil_div(n, kThreads) : 1; }
 
 template <typename T, int DIM, int G> void launch_g(Ctx &c, const NbrArgs<T> &a, bool filter)
@@ -801,6 +1033,11 @@ template <typename T, int DIM, int G> void launch_g(Ctx &c, const NbrArgs<T> &a,
 // enough threads for ~8 waves per SIMD
 template <typename T> void launch_grouped(Ctx &c, const NbrArgs<T> &a, bool filter)
 {
+    if (!filter && c.nbr_tiles && c.n_strips > 0) {
+        const size_t lds = (size_t)c.tile_pmax * (sizeof(double2) + sizeof(int)) + (size_t)c.tile_offmax * sizeof(int);
+        DTSPH_LAUNCH(c, k_nbr_tile<T>, dim3(c.n_strips), dim3(kTileThreads), lds, c.stream, a, c.strips, c.tile_pmax);
+        return;
+    }
     int g = filter ? c.g_filter : c.g_nbr;
     if (g <= 0) {
         g = 1;

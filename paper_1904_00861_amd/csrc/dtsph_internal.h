@@ -33,6 +33,7 @@ constexpr int kMaxCellOccupancy = 4096;
 constexpr int kMaxBlock = 256;
 constexpr int kMaxRanges = 32;       // active tile ranges passed to the pair pass
 constexpr int kSegTiles = 256;       // tiles per residual segment (one finalize workgroup)
+constexpr int kMaxTileRows = 32;     // cell rows per strip of the staged neighbour kernel
 
 enum PassMode { MODE_PRE = 0, MODE_PSEUDO = 1 };
 
@@ -49,6 +50,7 @@ struct SimDev {
     int seg_begin, seg_count;  // residual segments (runs of up to kSegTiles tiles)
     int ncell[3];
     int cell_div;        // cells of side >= (kappa h + skin) / cell_div; blocks of +-cell_div cells
+    int tile_w, tile_h;  // cells per strip of the staged neighbour kernel (2D)
     int periodic[3];
     int edac_reg_literal;
     double lo[3], hi[3], L[3], halfL[3], cs[3], inv_cs[3];
@@ -107,6 +109,13 @@ struct Ctx {
     int block = 256;
     int lpp = 1;             // lanes per particle in the pair pass
     int g_nbr = 0, g_filter = 0;  // lanes per particle in the neighbour kernels (0: heuristic)
+    // staged-tile neighbour kernel (2D contexts): 1 use it where it applies;
+    // strip table {sim, cell type, first row, first column} for the current
+    // subdivision, its capacity (the most strips of any subdivision), and the
+    // particles one strip may stage in LDS
+    int nbr_tiles = 0;
+    int4 *strips = nullptr;
+    int n_strips = 0, strip_cap = 0, tile_pmax = 0, tile_offmax = 0;
     int chunk = 0;           // 0 = adaptive
     int xcd_remap = 1;
     int max_dim = 2;

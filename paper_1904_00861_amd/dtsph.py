@@ -23,7 +23,7 @@ FP64, FP32 = 0, 1
 REASONS = {0: "running", 1: "converged", 2: "stalled", 3: "max_iter", 4: "nonfinite", 5: "fixed"}
 OPT_TIMING, OPT_RESET_TIMING, OPT_CHUNK, OPT_BLOCK, OPT_XCD_REMAP, OPT_LANES, OPT_SKIN = 1, 2, 3, 4, 5, 6, 7
 OPT_CELL_DIV, OPT_NBR_LANES, OPT_GRAPHS, OPT_PAIR_CACHE, OPT_SPECULATE, OPT_FILTER_LANES = 8, 9, 10, 11, 12, 13
-OPT_ABS32_POSITIONS = 14
+OPT_ABS32_POSITIONS, OPT_NBR_TILES = 14, 15
 
 EXPORTS = [
     "dtsph_create", "dtsph_destroy", "dtsph_last_error", "dtsph_set_state", "dtsph_get_state",
@@ -116,10 +116,11 @@ class TuneReport(C.Structure):
                 ("n_entries", C.c_int32), ("reserved", C.c_int32), ("entries", TuneEntry * 12),
                 ("nbr_lanes", C.c_int32), ("filter_lanes", C.c_int32),
                 ("nbr_us", C.c_double), ("filter_us", C.c_double),
-                ("cell_div", C.c_int32), ("reserved2", C.c_int32), ("build_us", C.c_double)]
+                ("cell_div", C.c_int32), ("nbr_tiles", C.c_int32), ("build_us", C.c_double)]
 
     def as_dict(self) -> dict:
         return dict(lanes=self.lanes, block=self.block, us=self.us, nbr_lanes=self.nbr_lanes,
+                    nbr_tiles=self.nbr_tiles,
                     cell_div=self.cell_div, build_us=self.build_us,
                     filter_lanes=self.filter_lanes, nbr_us=self.nbr_us, filter_us=self.filter_us,
                     entries=[dict(lanes=e.lanes, block=e.block, us=e.us)

@@ -3,7 +3,8 @@ batch of 64 sims, 2.57M particles) in the benchmark's launch configuration
 (FP32 sums, autotuned shape, XCD-aware tile order):
 
 * neighbour lists bit-exact against the oracle's binned search, every particle
-  of every config (each C4 sim against its own oracle lists);
+  of every config (each C4 sim against its own oracle lists), from the
+  autotuned kernel and from the staged-tile kernel of the 2D configs;
 * one real step at a fixed count of 4 pseudo-iterations over the whole
   workload, FP32 and FP64, every particle against the oracle's step (each C4
   sim against its own oracle run);
@@ -81,6 +82,15 @@ def _pair_band(prob, rel):
     return out
 
 
+_LISTS = {}
+
+
+def _oracle_lists(cfg, s, prob):
+    if (cfg, s) not in _LISTS:
+        _LISTS[(cfg, s)] = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, prob.x, "bins")
+    return _LISTS[(cfg, s)]
+
+
 @pytest.mark.parametrize("cfg", ["C1", "C2", "C3", "C4"])
 def test_fullsize_neighbour_lists_match_binned_oracle(cfg):
     probs = _problems(cfg)
@@ -89,7 +99,24 @@ def test_fullsize_neighbour_lists_match_binned_oracle(cfg):
     sim.autotune()
     for s, prob in enumerate(probs):
         off, idx = sim.neighbor_list(s)
-        ob, ib = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, prob.x, "bins")
+        ob, ib = _oracle_lists(cfg, s, prob)
+        assert np.array_equal(off, ob) and np.array_equal(idx, ib), (cfg, s)
+    sim.close()
+
+
+@pytest.mark.parametrize("div", [2, 3])
+@pytest.mark.parametrize("cfg", ["C1", "C3", "C4"])
+def test_fullsize_staged_tile_lists_match_binned_oracle(cfg, div):
+    # the staged-tile kernel (2D) at full size, whichever kernel the autotuner
+    # would pick
+    probs = _problems(cfg)
+    banner(f"full-size staged-tile neighbour lists {cfg} cell subdivision {div}")
+    sim = D.Sim(probs, precision=D.FP32)
+    sim.set_option(D.OPT_CELL_DIV, div)
+    sim.set_option(D.OPT_NBR_TILES, 1)
+    for s, prob in enumerate(probs):
+        off, idx = sim.neighbor_list(s)
+        ob, ib = _oracle_lists(cfg, s, prob)
         assert np.array_equal(off, ob) and np.array_equal(idx, ib), (cfg, s)
     sim.close()
 

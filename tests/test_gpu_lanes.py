@@ -1,11 +1,14 @@
-"""Every lane count of the neighbour-list kernels, since the autotuner may pick
-any of them: exact lists from a full build (1, 2, 4 or 8 lanes per particle,
-every cell subdivision, periodic and walled boxes, 2D and 3D, particles beyond
-the grid box) and from the candidate filter after real steps equal the
-brute-force oracle bit for bit. With two lanes the rows are prepared
-alternately by the two lanes and swapped; with one lane there is no partner;
-with four and eight the hits are ordered by ballots; small periodic boxes take
-the per-candidate minimum image."""
+"""Every variant of the neighbour-list kernels, since the autotuner may pick
+any of them: exact lists from a full build (the staged-tile kernel, or 1, 2, 4
+or 8 lanes per particle, every cell subdivision, periodic and walled boxes, 2D
+and 3D, particles beyond the grid box, a patch dense enough that its strips
+overflow their LDS stage and read global memory) and from the candidate
+filter after real steps equal the brute-force oracle bit for bit. With two
+lanes the rows are prepared alternately by the two lanes and swapped; with one
+lane there is no partner; with four and eight the hits are ordered by ballots;
+small periodic boxes take the per-candidate minimum image (and the per-particle
+kernel). The staged-tile kernel also keeps each list's order: FP32 steps,
+whose sums follow it, are bit-identical with either kernel."""
 import numpy as np
 import pytest
 
@@ -30,6 +33,16 @@ def _dam_beyond_x():
     return prob
 
 
+def _dense_patch():
+    # 2000 particles of a 50 x 50 vortex squeezed into a 0.2 x 0.2 square: the
+    # strips around it stage more particles than their LDS holds
+    prob = I.tgv2d(50, seed=5)
+    k = np.arange(2000)
+    prob.x[k, :2] = 0.4 + 0.2 * (prob.x[k, :2] - prob.x[k, :2].min(axis=0)) / np.ptp(prob.x[k, :2], axis=0).max()
+    prob.params["max_neighbors"] = 1400
+    return prob
+
+
 CASES = {
     "tgv2d_16_j03": lambda: I.tgv2d(16, seed=3, jitter=0.3),
     "tgv3d_16": lambda: I.tgv3d(16, seed=4),
@@ -48,11 +61,44 @@ def test_build_lists_every_lane_count(case, lanes, div):
     ob, ib = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, prob.x, "brute")
     sim = D.Sim(prob, precision=D.FP32)
     sim.set_option(D.OPT_CELL_DIV, div)
+    sim.set_option(D.OPT_NBR_TILES, 0)
     sim.set_option(D.OPT_NBR_LANES, lanes)
     off, idx = sim.neighbor_list()
     sim.close()
     assert np.array_equal(off, ob)
     assert np.array_equal(idx, ib)
+
+
+@pytest.mark.parametrize("div", [1, 2, 3])
+@pytest.mark.parametrize("case", list(CASES) + ["dense_patch"])
+def test_build_lists_staged_tiles(case, div):
+    prob = _dense_patch() if case == "dense_patch" else CASES[case]()
+    banner(f"staged-tile neighbour build {case} cell subdivision {div}")
+    ob, ib = O.neighbors(prob.params, prob.n_fluid, prob.n_wall, prob.x, "brute")
+    sim = D.Sim(prob, precision=D.FP32)
+    sim.set_option(D.OPT_CELL_DIV, div)
+    sim.set_option(D.OPT_NBR_TILES, 1)
+    off, idx = sim.neighbor_list()
+    sim.close()
+    assert np.array_equal(off, ob)
+    assert np.array_equal(idx, ib)
+
+
+@pytest.mark.parametrize("case", ["tgv2d_16_j03", "cavity_16", "tank_10", "dam_beyond_x"])
+def test_staged_tiles_keep_list_order(case):
+    # the pair sums follow each list's order: FP32 steps agree bit for bit
+    prob = CASES[case]()
+    banner(f"staged-tile vs per-particle lists, FP32 steps, {case}")
+    out = []
+    for tiles in (1, 0):
+        sim = D.Sim(prob, precision=D.FP32)
+        sim.set_option(D.OPT_NBR_TILES, tiles)
+        sim.set_option(D.OPT_NBR_LANES, 1)
+        st, reps = sim.step(3)
+        out.append(sim.get_state())
+        sim.close()
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
 
 
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8])
@@ -84,4 +130,7 @@ def test_lane_options_reject_other_values():
         for bad in (3, 16, -1):
             with pytest.raises(D.DtsphError):
                 sim.set_option(opt, bad)
+    for bad in (2, -1):
+        with pytest.raises(D.DtsphError):
+            sim.set_option(D.OPT_NBR_TILES, bad)
     sim.close()
