@@ -735,15 +735,22 @@ template <typename T> void loop_prologue(Ctx &c, int fixed, LoopRun &L)
     c.loop_cached = cache_usable(c) && (c.pair_cache == 1 || (c.pair_cache == 2 && expect >= kCacheMinIters && fits));
 }
 
+// Wall passes of a loop run with the previous iteration's residual reduction
+// (one launch less per iteration), except for the first iteration and in
+// contexts whose lists change between iterations (moving sims with list
+// updates filter the lists before each wall pass).
+bool fused_walls(const Ctx &c) { return c.Nw > 0 && !c.any_move2; }
+
 // The next chunk of iterations (its size: L.chunk, capped by the iteration limit).
 template <typename T> void launch_chunk(Ctx &c, LoopRun &L)
 {
     const int n = std::min(L.chunk, L.max_it - L.launched);
+    const bool fuse = fused_walls(c);
     for (int k = 0; k < n; ++k) {
         c.pass_index = L.launched + k;
         // moving sims with neighbour updates: exact lists at r^{k+1/2}
         if (c.any_move2 && L.launched + k > 0) filter_lists<T>(c);
-        launch_wall<T>(c, MODE_PSEUDO);
+        if (!fuse || L.launched + k == 0) launch_wall<T>(c, MODE_PSEUDO);
         // with cached coefficients the loop's first pass stores them, later ones
         // read; steady contexts keep them from loop to loop (lists and positions
         // do not change)
@@ -751,7 +758,9 @@ template <typename T> void launch_chunk(Ctx &c, LoopRun &L)
         launch_pass<T>(c, MODE_PSEUDO);
         if (c.cache_phase == 1) c.coef_valid = true;
         c.cache_phase = 0;
-        launch_finalize(c, k == n - 1);  // the chunk's last one publishes the reports
+        // the chunk's last one publishes the reports
+        if (fuse) launch_finalize_wall<T>(c, k == n - 1, L.launched + k + 1);
+        else launch_finalize(c, k == n - 1);
     }
     L.launched += n;
 }
@@ -783,6 +792,7 @@ template <typename T> int loop_finish(Ctx &c, LoopRun &L, dtsph_iter_report *rep
         }
     }
     set_active_ranges(c, true);
+    if (fused_walls(c)) launch_wall_pressure<T>(c);
     c.p_half = true;  // p^K = p^{K+1/2} - dtau/2 (dp/dtau)^K is applied lazily
     int status = DTSPH_OK, most = 1;
     bool cand = true;

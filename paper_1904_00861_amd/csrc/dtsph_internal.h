@@ -291,6 +291,10 @@ template <typename T> void launch_pre_records(Ctx &c);
 template <typename T> void launch_wall(Ctx &c, int mode, bool cand_lists = false);
 template <typename T> void launch_pass(Ctx &c, int mode, bool cand_lists = false);
 void launch_finalize(Ctx &c, bool publish);
+// iteration next-1's residual reduction together with iteration next's wall pass
+template <typename T> void launch_finalize_wall(Ctx &c, bool publish, int next);
+// wall pressures of the last iteration each sim ran (after a loop of fused wall passes)
+template <typename T> void launch_wall_pressure(Ctx &c);
 void launch_publish(Ctx &c);
 template <typename T> void launch_loop_begin(Ctx &c, int fixed_iters);
 template <typename T> void launch_move_begin(Ctx &c);

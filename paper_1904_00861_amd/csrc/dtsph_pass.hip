@@ -636,28 +636,18 @@ template <typename T> struct WallArgs {
     double *x_alt;   // MODE_PRE: walls keep their position
 };
 
+// Wall particle iw of sim S from the fluid records of buffer `par` (position
+// records of buffer `ppar` for moving sims): its record (ghost velocity and
+// pressure) into the same buffer and, with write_pw, the wall-pressure array.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
+__device__ __forceinline__ void wall_particle(const WallArgs<T> &A, const SimDev &S, int iw, int par, int ppar,
+                                              bool write_pw)
 {
     using Q = typename V4<T>::type;
     using PosT = Pos<T, DIM>;
     using Rec = typename PosT::Rec;
-    const int iw = blockIdx.x * blockDim.x + threadIdx.x;
-    if (iw >= A.Nw) return;
-    if (A.gated && !spec_gate(A.n_sims, A.iters, A.sims)) return;
     const int i = A.Nf + iw;
     const int N = A.N;
-    const int s = A.simid[i];
-    const SimDev &S = A.sims[s];
-    int par = A.cur, ppar = 0;
-    if (A.mode == MODE_PRE) {
-        for (int d = 0; d < 3; ++d) A.x_alt[d * N + i] = A.x[d * N + i];
-    } else {
-        const SimIter &It = A.iters[s];
-        if (It.done) return;
-        par = (A.cur + It.iters) & 1;
-        ppar = S.move ? It.iters & 1 : 0;  // moving fluid: records at r^{k+1/2}
-    }
     Q *__restrict__ vin = par ? A.vp1 : A.vp0;
     const PosT pos(S);
     const Rec *__restrict__ prec = (const Rec *)(ppar ? A.prec2 : A.prec);
@@ -721,7 +711,29 @@ __global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
         for (int d = 0; d < DIM; ++d) ghost[d] = vw[d];
     }
     vin[i] = make_rec<T, DIM>(ghost, pw);
-    A.pwall[iw] = pw;
+    if (write_pw) A.pwall[iw] = pw;
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_wall(WallArgs<T> A)
+{
+    const int iw = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iw >= A.Nw) return;
+    if (A.gated && !spec_gate(A.n_sims, A.iters, A.sims)) return;
+    const int i = A.Nf + iw;
+    const int N = A.N;
+    const int s = A.simid[i];
+    const SimDev &S = A.sims[s];
+    int par = A.cur, ppar = 0;
+    if (A.mode == MODE_PRE) {
+        for (int d = 0; d < 3; ++d) A.x_alt[d * N + i] = A.x[d * N + i];
+    } else {
+        const SimIter &It = A.iters[s];
+        if (It.done) return;
+        par = (A.cur + It.iters) & 1;
+        ppar = S.move ? It.iters & 1 : 0;  // moving fluid: records at r^{k+1/2}
+    }
+    wall_particle<T, DIM>(A, S, iw, par, ppar, true);
 }
 
 // ---- residual reduction and stop test (section 3.4) --------------------------
@@ -826,10 +838,11 @@ struct FinState {
     double dt, pscale, res_p, res_v, vref, tol, stall_rel;
 };
 
-__global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
+// Segment g of the residual reduction; the last segment of a sim to arrive
+// closes the sim's iteration (stop test, report).
+__device__ __forceinline__ void finalize_segment(const FinArgs &A, int g)
 {
     __shared__ int last;
-    const int g = blockIdx.x;
     const int4 sg = A.segs[g];
     const int s = sg.x;
     SimIter &It = A.iters[s];
@@ -948,6 +961,48 @@ __global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A)
     }
     done_out[s] = It.done;
     if (A.publish) publish_report(A, s, It);
+}
+
+__global__ void __launch_bounds__(kFinThreads) k_finalize(FinArgs A) { finalize_segment(A, blockIdx.x); }
+
+// Iteration k's residual reduction and stop test (the first n_segs
+// workgroups) together with the wall pass of iteration k + 1 (the others): the
+// wall pass needs only the fluid records that iteration k's pair pass wrote,
+// so both run in one launch. The walls of every sim still iterating are
+// computed, also of a sim that stops in this launch (their records are then
+// never read); the wall-pressure array keeps the values the last pair pass
+// used (k_wall_pressure writes it at the end of the loop). `next` = k + 1.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kFinThreads) k_finalize_wall(FinArgs F, WallArgs<T> W, int n_segs, int next)
+{
+    if ((int)blockIdx.x < n_segs) {
+        finalize_segment(F, blockIdx.x);
+        return;
+    }
+    const int iw = ((int)blockIdx.x - n_segs) * kFinThreads + (int)threadIdx.x;
+    if (iw >= W.Nw) return;
+    const int s = W.simid[W.Nf + iw];
+    if (W.iters[s].done) return;  // stopped before iteration k (or just now: either way unused)
+    const SimDev &S = W.sims[s];
+    wall_particle<T, DIM>(W, S, iw, (W.cur + next) & 1, S.move ? next & 1 : 0, false);
+}
+
+// End of a loop whose wall passes ran with the residual reductions: each wall
+// pressure from the record of the last iteration its sim ran.
+template <typename T>
+__global__ void __launch_bounds__(256) k_wall_pressure(int Nw, int Nf, const int *__restrict__ simid,
+                                                       const SimIter *__restrict__ iters,
+                                                       const typename V4<T>::type *__restrict__ vp0,
+                                                       const typename V4<T>::type *__restrict__ vp1, int cur,
+                                                       int dim, T *__restrict__ pwall)
+{
+    const int iw = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iw >= Nw) return;
+    const int i = Nf + iw;
+    const int k = iters[simid[i]].iters;
+    if (k < 1) return;
+    const typename V4<T>::type r = ((cur + k - 1) & 1) ? vp1[i] : vp0[i];
+    pwall[iw] = dim == 2 ? r.z : r.w;
 }
 
 // Copy the host-visible control words (build flags, stop flags, per-sim reports
@@ -1498,10 +1553,8 @@ void launch_pass(Ctx &c, int mode, bool cand_lists)
     timer_book(c, t0, 0);
 }
 
-template <typename T>
-void launch_wall(Ctx &c, int mode, bool cand_lists)
+template <typename T> WallArgs<T> wall_args(Ctx &c, int mode, bool cand_lists)
 {
-    if (c.Nw == 0) return;
     using Q = typename V4<T>::type;
     const int b = c.buf;
     WallArgs<T> a;
@@ -1518,6 +1571,14 @@ void launch_wall(Ctx &c, int mode, bool cand_lists)
     a.vwall = (const T *)c.vw[b];
     a.pwall = (T *)c.pw[b];
     a.x = c.x[c.xb]; a.x_alt = c.x[c.xb ^ 1];
+    return a;
+}
+
+template <typename T>
+void launch_wall(Ctx &c, int mode, bool cand_lists)
+{
+    if (c.Nw == 0) return;
+    const WallArgs<T> a = wall_args<T>(c, mode, cand_lists);
     int t0 = mode == MODE_PSEUDO ? timer_begin(c, 1) : -1;
     if (c.max_dim == 2) DTSPH_LAUNCH(c, (k_wall<T, 2>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
     else DTSPH_LAUNCH(c, (k_wall<T, 3>), dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, a);
@@ -1533,7 +1594,7 @@ void launch_publish(Ctx &c)
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
-void launch_finalize(Ctx &c, bool publish)
+FinArgs fin_args(Ctx &c, bool publish)
 {
     FinArgs a;
     a.sims = c.sims; a.iters = c.iters; a.partials = c.partials; a.partials2 = c.partials2;
@@ -1544,7 +1605,34 @@ void launch_finalize(Ctx &c, bool publish)
     a.pubcount = c.pubcount;
     a.publish = publish ? 1 : 0;
     if (publish) ++c.seq;  // every sim's count advances once per publishing launch
+    return a;
+}
+
+void launch_finalize(Ctx &c, bool publish)
+{
+    const FinArgs a = fin_args(c, publish);
     DTSPH_LAUNCH(c, k_finalize, dim3(c.n_segs), dim3(kFinThreads), 0, c.stream, a);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_finalize_wall(Ctx &c, bool publish, int next)
+{
+    const FinArgs f = fin_args(c, publish);
+    const WallArgs<T> w = wall_args<T>(c, MODE_PSEUDO, false);
+    const dim3 grid(c.n_segs + ceil_div(c.Nw, kFinThreads));
+    if (c.max_dim == 2) DTSPH_LAUNCH(c, (k_finalize_wall<T, 2>), grid, dim3(kFinThreads), 0, c.stream, f, w, c.n_segs, next);
+    else DTSPH_LAUNCH(c, (k_finalize_wall<T, 3>), grid, dim3(kFinThreads), 0, c.stream, f, w, c.n_segs, next);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_wall_pressure(Ctx &c)
+{
+    using Q = typename V4<T>::type;
+    const int b = c.buf;
+    DTSPH_LAUNCH(c, k_wall_pressure<T>, dim3(grid_for(c.Nw)), dim3(256), 0, c.stream, c.Nw, c.Nf, c.simid[b], c.iters,
+                 (const Q *)c.vp[0], (const Q *)c.vp[1], c.cur, c.max_dim, (T *)c.pw[b]);
     DTSPH_HIP_CHECK(hipGetLastError());
 }
 
@@ -1695,6 +1783,8 @@ void launch_get_state(Ctx &c, const dtsph_state_view &s, bool in_loop)
 #define DTSPH_INSTANTIATE(T)                                                   \
     template void launch_pass<T>(Ctx &, int, bool);                            \
     template void launch_wall<T>(Ctx &, int, bool);                            \
+    template void launch_finalize_wall<T>(Ctx &, bool, int);                   \
+    template void launch_wall_pressure<T>(Ctx &);                              \
     template void launch_pre_records<T>(Ctx &);                                \
     template void launch_loop_begin<T>(Ctx &, int);                            \
     template void launch_move_begin<T>(Ctx &);                                 \
