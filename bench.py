@@ -115,13 +115,15 @@ def apply_shape(sim, shape):
     sim.set_option(D.OPT_CELL_DIV, cell_div)
 
 
-def run_leg(problems, precision, steps, warmup, timing_every, shape=None, pair_cache=0):
+def run_leg(problems, precision, steps, warmup, timing_every, shape=None, pair_cache=0, graphs=0):
     import torch
     from paper_1904_00861_amd import dtsph as D
 
     sim = D.Sim(problems, precision=precision)
     if pair_cache:
         sim.set_option(D.OPT_PAIR_CACHE, pair_cache)
+    if graphs:
+        sim.set_option(D.OPT_GRAPHS, 1)
     if shape:  # fixed launch configuration instead of the autotuner
         lanes, block, nbr_lanes, cell_div = shape
         apply_shape(sim, shape)
@@ -371,6 +373,9 @@ def main():
                     help="workload of the second leg")
     ap.add_argument("--second-steps", type=int, default=20)
     ap.add_argument("--no-timing", action="store_true", help="no HIP events in the timed region")
+    ap.add_argument("--graphs", type=int, default=0, choices=[0, 1],
+                    help="1: record each step's segment up to the first chunk of pseudo-iterations as a HIP "
+                         "graph and replay it (main leg)")
     ap.add_argument("--shape", default=None, metavar="L,B,G,M",
                     help="fixed launch shape instead of the autotuner: pair-pass lanes per particle, "
                          "workgroup size, neighbour-build lanes (0: the staged-tile kernel), cell subdivision "
@@ -440,7 +445,7 @@ def main():
         counter_run(problems, prec, args.steps, args.warmup, args.counter_run, shape)
         return
     every = 0 if args.no_timing else args.timing_every
-    main_leg = run_leg(problems, prec, args.steps, args.warmup, every, shape, args.pair_cache)
+    main_leg = run_leg(problems, prec, args.steps, args.warmup, every, shape, args.pair_cache, args.graphs)
     main = leg_summary(problems, main_leg, dtype, args.steps, args.config, args.timing_every)
     log(f"main leg: {main_leg['seconds'] * 1e3:.2f} ms, {main['value']:.3e} pair-evals/s, "
         f"{main['ms_per_step']:.3f} ms/step, iterations/step mean {main['iterations_per_step_mean']:.2f}")
@@ -497,7 +502,7 @@ def main():
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "sims": len(problems),
                    "particles": n_particles,
                    "particle_shifting": bool(any(p.params.get("shift", 0) for p in problems)),
-                   "pair_sums": args.precision, "pair_cache": args.pair_cache,
+                   "pair_sums": args.precision, "pair_cache": args.pair_cache, "graphs": args.graphs,
                    "positions_pressure_residuals": "f64",
                    "instance_steps_per_s": main["instance_steps_per_s"],
                    "iterations_per_step_mean": main["iterations_per_step_mean"],
