@@ -80,7 +80,8 @@ def pair_evals(reports):
 
 
 def _pass_src_hash():
-    src = os.path.join(ROOT, "paper_1904_00861_amd", "csrc", "dtsph_pass.hip")
+    """sha256 of the source that holds the pair-pass kernel."""
+    src = os.path.join(ROOT, "paper_1904_00861_amd", "csrc", "dtsph_pass_dev.h")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()
 
 

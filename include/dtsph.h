@@ -220,6 +220,7 @@ typedef struct dtsph_timing {
     int64_t spec_tries;     /* speculative ends of step queued (see
                                DTSPH_OPT_SPECULATE) and how many of them ran */
     int64_t spec_hits;
+    int64_t tail_launches;  /* persistent tail launches (DTSPH_OPT_TAIL_LOOP 1) */
 } dtsph_timing;
 
 /* ---- sizes (host memory) ------------------------------------------------- */
@@ -438,6 +439,23 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *
                                   and periodic axes with fewer than 2m+3
                                   cells always use the latter. The
                                   autotuner times both.                      */
+#define DTSPH_OPT_TAIL_LOOP 16 /* schedule of a batch's pseudo-time loop,
+                                  bit-identical results in every case:
+                                  0: chunks of plain launches, the first as
+                                  long as the last loop's longest;
+                                  1 (default): the first chunk ends where, by
+                                  the last loop's per-sim counts, the sims
+                                  still iterating hold at most a quarter of
+                                  the tiles; later launches cover only those
+                                  sims' tiles, and a small remainder (each
+                                  sim at most 128 pair-pass tiles) runs the
+                                  rest of its loop in one persistent
+                                  cooperative launch (per-sim barriers on
+                                  the device, no host round trip per chunk;
+                                  not with moving or steady sims, separate
+                                  regularisers, cached pair coefficients or
+                                  in static contexts);
+                                  2: as 1 without the persistent launch.   */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the launch shapes. Between steps only (EINVAL in the loop).

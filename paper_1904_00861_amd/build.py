@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdtsph.so")
-SOURCES = ["dtsph_api.hip", "dtsph_cells.hip", "dtsph_pass.hip"]
+SOURCES = ["dtsph_api.hip", "dtsph_cells.hip", "dtsph_pass.hip", "dtsph_tail.hip"]
 ARCH = os.environ.get("DTSPH_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -686,8 +686,34 @@ void shift_decision(Ctx &c, bool use_cand)
 struct LoopRun {
     int fixed = 0, max_it = 0, launched = 0, chunk = 1;
     bool spec = false, spec_next = false;  // speculative end of step after each chunk
+    bool queued = false;  // the speculative launches follow the latest chunk
+    bool split = false;   // the first chunk ends early for a tail launch
     int tries = 0;
 };
+
+// Length of a loop's first chunk: the last loop's longest (at most 64). A
+// batch whose sims needed very different counts last time (cut schedule, see
+// DTSPH_OPT_TAIL_LOOP) stops it at the first iteration k after which, by those
+// counts, the sims still iterating hold at most a quarter of the tiles, if at
+// least 4 iterations would remain: the host reads the reports there and cuts
+// the launches down to those sims' tiles (or hands them to a tail launch),
+// instead of launching every tile for a few sims.
+int first_chunk(const Ctx &c, int max_it, bool *split = nullptr)
+{
+    const int n = std::min(c.chunk > 0 ? c.chunk : std::max(1, std::min(c.last_iters, 64)), max_it);
+    if (split) *split = false;
+    if (c.chunk > 0 || c.tail_loop == 0 || c.n_sims < 2) return n;
+    for (int k = 1; k + 4 <= n; ++k) {
+        int64_t tiles = 0;
+        for (int s = 0; s < c.n_sims; ++s)
+            if (c.prev_iters[s] < 0 || c.prev_iters[s] > k) tiles += c.sims_h[s].tile_end - c.sims_h[s].tile_begin;
+        if (4 * tiles <= c.n_tiles) {
+            if (split) *split = true;
+            return k;
+        }
+    }
+    return n;
+}
 
 template <typename T> void launch_speculation(Ctx &c, bool next_pre);
 
@@ -722,8 +748,7 @@ template <typename T> void loop_prologue(Ctx &c, int fixed, LoopRun &L)
     if (fixed == 0)
         for (auto &d : c.desc) L.max_it = std::max(L.max_it, (int)d.max_iter);
     L.launched = 0;
-    L.chunk = c.chunk > 0 ? c.chunk : std::max(1, std::min(c.last_iters, 64));
-    if (fixed > 0) L.chunk = std::min(L.chunk, fixed);
+    L.chunk = first_chunk(c, L.max_it, &L.split);
     const int expect = fixed > 0 ? fixed : c.last_iters;
     bool fits = false;
     if (c.pair_cache == 2) {
@@ -783,9 +808,14 @@ template <typename T> int loop_finish(Ctx &c, LoopRun &L, dtsph_iter_report *rep
         if (all || L.launched >= L.max_it) break;
         // more iterations than the last loop needed: chunks grow with the loop
         // (sims that stop inside a chunk leave only no-op launches behind)
-        L.chunk = c.chunk > 0 ? c.chunk : std::max(2, std::min(L.launched / 2, 32));
         set_active_ranges(c, false);
-        launch_chunk<T>(c, L);
+        if (c.tail_loop == 1 && launch_tail<T>(c, L.launched)) {
+            L.launched = L.max_it;  // every sim of the launch stops in it
+        } else {
+            L.chunk = c.chunk > 0 ? c.chunk : std::max(2, std::min(L.launched / 2, 32));
+            launch_chunk<T>(c, L);
+        }
+        L.queued = L.spec;
         if (L.spec) {
             launch_speculation<T>(c, L.spec_next);
             L.tries++;
@@ -818,6 +848,7 @@ template <typename T> int loop_finish(Ctx &c, LoopRun &L, dtsph_iter_report *rep
         else if (it.reason == DTSPH_MAXITER && status == DTSPH_OK) status = DTSPH_WARN_MAXITER;
     }
     c.last_iters = most;
+    for (int s = 0; s < c.n_sims; ++s) c.prev_iters[s] = c.reps_host[s].iters;
     for (const auto &pt : c.pass_times) {  // timed launches with the sims that took part
         int64_t pairs = 0, parts = 0;
         for (int s = 0; s < c.n_sims; ++s)
@@ -897,7 +928,7 @@ template <typename T> void step_segment(Ctx &c, LoopRun &L)
     };
     int max_it = 0;
     for (auto &d : c.desc) max_it = std::max(max_it, (int)d.max_iter);
-    const int n = std::min(c.chunk > 0 ? c.chunk : std::max(1, std::min(c.last_iters, 64)), max_it);
+    const int n = first_chunk(c, max_it);
     if (!c.graphs || pass_timer_fires(c, n)) {
         body();
         return;
@@ -998,12 +1029,15 @@ template <typename T> int do_step(Ctx &c, int n_steps, dtsph_iter_report *reps)
         // launches); after a run of misses, probe again every 16 steps
         L.spec = c.speculate && !c.graphs && c.n_sims <= 64 && (c.spec_score > 0 || ++c.spec_idle % 16 == 0);
         L.spec_next = s + 1 < n_steps && !c.any_shift;  // shifting: the rate pass waits for the shift's size
-        if (L.spec) {
+        // (not after a first chunk cut for a tail launch: the loop rarely ends there)
+        L.queued = L.spec && !L.split;
+        if (L.queued) {
             launch_speculation<T>(c, L.spec_next);
             L.tries++;
         }
         int st = loop_finish<T>(c, L, reps ? reps + (size_t)s * c.n_sims : nullptr);
-        const bool hit = L.spec && gate_open(c);
+        // the gated launches ran only if they followed the loop's last chunk
+        const bool hit = L.queued && gate_open(c);
         if (L.spec) {
             c.spec_score = std::min(8, c.spec_score + (hit ? 1 : 0) - 2 * (L.tries - (hit ? 1 : 0)));
             if (c.spec_score > 0) c.spec_idle = 0;
@@ -1140,6 +1174,7 @@ static int create_impl(const dtsph_sim_desc *sims, const int64_t *n_fluid, const
         c.max_dim = sims[0].dim;
         c.sims_h.resize(n_sims);
         c.skin_default.resize(n_sims);
+        c.prev_iters.assign(n_sims, -1);
         c.fluid_begin.resize(n_sims);
         int64_t fb = 0, wb = 0;
         double cap_est = 0;
@@ -1149,6 +1184,7 @@ static int create_impl(const dtsph_sim_desc *sims, const int64_t *n_fluid, const
             const dtsph_sim_desc &d = sims[s];
             SimDev S = make_simdev(d, n_fluid[s], n_wall[s]);
             S.fluid_begin = (int)fb;
+            S.wall_begin = (int)wb;
             // the finest subdivision at the smallest skin (0, see DTSPH_OPT_SKIN) has
             // the most cells: it sizes the key tables
             SimDev S0 = S;
@@ -1243,6 +1279,8 @@ static int create_impl(const dtsph_sim_desc *sims, const int64_t *n_fluid, const
         dev_alloc(c, c.tiles, sizeof(int2) * max_tiles);
         dev_alloc(c, c.partials, sizeof(double4) * max_tiles);
         const size_t max_segs = max_tiles / kSegTiles + (size_t)n_sims + 1;
+        if (!c.static_mode)  // tail launches: arrivals, releases, error word, group words
+            dev_alloc(c, c.tail_words, sizeof(uint32_t) * (3 * (size_t)n_sims + 2 + max_tiles / kTailGroup));
         dev_alloc(c, c.segs, sizeof(int4) * max_segs);
         dev_alloc(c, c.seg_p, sizeof(double4) * max_segs);
         dev_alloc(c, c.seg_p2, sizeof(double2) * max_segs);
@@ -1607,6 +1645,10 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
             if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
                 throw ApiError(DTSPH_EINVAL, "filter lanes must be 0, 1, 2, 4 or 8");
             c.g_filter = (int)value;
+            break;
+        case DTSPH_OPT_TAIL_LOOP:
+            if (value < 0 || value > 2) throw ApiError(DTSPH_EINVAL, "loop schedule must be 0, 1 or 2");
+            c.tail_loop = (int)value;
             break;
         case DTSPH_OPT_NBR_TILES:
             if (value != 0 && value != 1) throw ApiError(DTSPH_EINVAL, "neighbour tiles must be 0 or 1");

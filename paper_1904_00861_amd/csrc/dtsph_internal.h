@@ -34,6 +34,9 @@ constexpr int kMaxBlock = 256;
 constexpr int kMaxRanges = 32;       // active tile ranges passed to the pair pass
 constexpr int kSegTiles = 256;       // tiles per residual segment (one finalize workgroup)
 constexpr int kMaxTileRows = 32;     // cell rows per strip of the staged neighbour kernel
+constexpr int kTailMaxSims = 256;    // sims of a context that may use tail launches
+constexpr int kTailSimTiles = 128;   // tiles of one sim in a tail launch (its barrier's workgroups)
+constexpr int kTailGroup = 16;       // workgroups per first-level barrier word of a tail launch
 
 enum PassMode { MODE_PRE = 0, MODE_PSEUDO = 1 };
 
@@ -45,6 +48,7 @@ enum Flag { F_NBR_OVERFLOW = 0, F_NBR_NEEDED = 1, F_CELL_OVERFLOW = 2, F_OUTSIDE
 struct SimDev {
     int dim, nf, nw;
     int fluid_begin;     // first fluid slot
+    int wall_begin;      // first wall (index among the walls: slot Nf + wall_begin)
     int key_base;        // first fluid key; wall keys add the total cell count
     int tile_begin, tile_end;  // fluid tiles of this sim (residual partials)
     int seg_begin, seg_count;  // residual segments (runs of up to kSegTiles tiles)
@@ -153,6 +157,13 @@ struct Ctx {
     bool records_fresh = false;  // vp[cur] and the position records hold the
                                  // state at the current positions (corrector)
     int last_iters = 4;      // adaptive chunking
+    std::vector<int> prev_iters;  // per sim: iterations of its last loop (-1: none yet)
+    // loop schedule (DTSPH_OPT_TAIL_LOOP): 0 plain chunks, 1 cut first chunk
+    // and tail launches, 2 cut first chunk and plain chunks; per sim arrival and
+    // release words of the sims' barriers, an error word, then the words of
+    // the workgroup groups (tiles / kTailGroup + n_sims + 1)
+    int tail_loop = 1;
+    uint32_t *tail_words = nullptr;
     // pair-pass launches inside a loop cover only sims still iterating: tile
     // ranges (first tile, index within the launch); n_ranges == 0: every tile
     int n_ranges = 0, n_act_tiles = 0;
@@ -295,6 +306,13 @@ void launch_finalize(Ctx &c, bool publish);
 template <typename T> void launch_finalize_wall(Ctx &c, bool publish, int next);
 // wall pressures of the last iteration each sim ran (after a loop of fused wall passes)
 template <typename T> void launch_wall_pressure(Ctx &c);
+// The rest of a pseudo-time loop in one persistent launch when the sims still
+// iterating are few and small (dtsph_tail.hip); false: not launched (the caller
+// goes on with plain chunks). k0 = iterations every such sim has run.
+bool tail_kind(const Ctx &c);  // the context's kind allows tail launches at all
+bool tail_fits(const Ctx &c);  // ... and the sims still iterating fit one now
+int tail_capacity(const Ctx &c);  // workgroups of a tail launch that fit on the device at once
+template <typename T> bool launch_tail(Ctx &c, int k0);
 void launch_publish(Ctx &c);
 template <typename T> void launch_loop_begin(Ctx &c, int fixed_iters);
 template <typename T> void launch_move_begin(Ctx &c);

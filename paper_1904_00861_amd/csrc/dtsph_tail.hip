@@ -1,0 +1,358 @@
+// Persistent tail of a pseudo-time loop (Algorithm 2, the loop over k, for the
+// sims of a batch still iterating once most have stopped).
+//
+// In a batch whose sims need very different iteration counts, the last
+// iterations of a loop involve a few small sims: each iteration is then a
+// handful of workgroups, and plain launches (pair pass, residual reduction with
+// the next wall pass) cost their launch and dependency floors, several times
+// the work. Once a report shows that the sims still iterating cover few tiles,
+// one cooperative launch runs the rest of their loop: each workgroup owns one
+// tile, and the workgroups of a sim meet at a barrier of their own after each
+// pair pass (two levels: groups of kTailGroup workgroups count on a word of
+// their own, the last of each group on the sim's word). The last to arrive
+// closes the sim's iteration (residual reduction and stop test). A sim with
+// walls is released at once: its workgroups compute the walls for the next
+// iteration while the iteration is closed, and meet again before reading the
+// stop flag. Sims never wait for each other.
+//
+// Results are bit-identical to plain launches: the same pair-pass code per
+// tile, the residual reduction in the same order as k_finalize (per segment,
+// then over the segments, with the same per-wave butterflies and wave order for
+// any workgroup size), the same stop test and wall pass.
+//
+// Every barrier wait is bounded: a wait that gives up sets an error word and its
+// workgroup leaves; the sims involved then never publish their reports, which
+// the host's wait turns into an error once the launch has ended.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+
+#include "dtsph_pass_dev.h"
+
+namespace dtsph {
+
+namespace {
+
+constexpr long kTailSpin = 1L << 22;  // polls of a release word before a wait gives up (seconds)
+
+struct TailArgs {
+    int k0;              // iterations every sim in the launch has run
+    uint32_t *arrive;    // per sim: group arrivals at its barrier (zero at launch)
+    uint32_t *release;   // per sim: its barrier phases released (zero at launch)
+    uint32_t *group;     // per group of a sim's workgroups (tile_begin / kTailGroup + sim + group)
+    int *err;            // set when a wait gives up
+    uint32_t outside[kTailMaxSims / 32];  // sims not in the launch (stopped before it)
+};
+
+// A workgroup's place in its sim's barrier.
+struct TailSeat {
+    int s;               // sim
+    uint32_t *group;     // its group's word
+    uint32_t gsize;      // workgroups in its group
+    uint32_t ngroups;    // groups of the sim
+};
+
+// fin_block_reduce's reduction of kFinThreads values for a workgroup of any
+// multiple of 64 threads: value vt comes from load(vt, v); the waves take the
+// same 64-value groups in turn, with the same butterflies, and thread 0 adds the
+// group sums in the same order, so the result (thread 0) is bit-identical.
+template <typename L> __device__ inline void fin_reduce_any(double out[6], L load)
+{
+    constexpr int G = kFinThreads / 64;
+    __shared__ double lds[G][6];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int w0 = 0; w0 < G; w0 += nw) {
+        const int w = w0 + wave;
+        if (w < G) {  // uniform per wave
+            double v[6];
+            load(w * 64 + lane, v);
+            for (int o = 32; o > 0; o >>= 1) {
+                v[0] += __shfl_xor(v[0], o, 64);
+                v[1] += __shfl_xor(v[1], o, 64);
+                v[5] += __shfl_xor(v[5], o, 64);
+                v[2] = fmax(v[2], __shfl_xor(v[2], o, 64));
+                v[3] = fmax(v[3], __shfl_xor(v[3], o, 64));
+                v[4] = fmax(v[4], __shfl_xor(v[4], o, 64));
+            }
+            if (lane == 0)
+                for (int k = 0; k < 6; ++k) lds[w][k] = v[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 6; ++k) out[k] = lds[0][k];
+        for (int w = 1; w < G; ++w) {
+            out[0] += lds[w][0];
+            out[1] += lds[w][1];
+            out[2] = fmax(out[2], lds[w][2]);
+            out[3] = fmax(out[3], lds[w][3]);
+            out[4] = fmax(out[4], lds[w][4]);
+            out[5] += lds[w][5];
+        }
+    }
+    __syncthreads();
+}
+
+// Closes the current iteration of sim s (whole workgroup, after every tile of
+// the sim has written its partials): the segment sums (kept in LDS: a tail sim
+// has at most ceil(kTailSimTiles / kSegTiles) segments), their sum, the stop test
+// and, when the sim stops, its report.
+__device__ inline void tail_close(const FinArgs &F, int s, const SimDev &S)
+{
+    constexpr int kSegs = (kTailSimTiles + kSegTiles - 1) / kSegTiles;
+    __shared__ double seg[kSegs][6];
+    for (int q = 0; q < S.seg_count; ++q) {
+        const int4 sg = F.segs[S.seg_begin + q];
+        double red[6];
+        fin_reduce_any(red, [&](int vt, double v[6]) {
+            for (int k = 0; k < 6; ++k) v[k] = 0.0;
+            const int t = sg.y + vt;
+            if (t < sg.z) {
+                const double4 p = F.partials[t];
+                const double2 p2 = F.partials2[t];
+                v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w; v[4] = p2.x; v[5] = p2.y;
+            }
+        });
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 6; ++k) seg[q][k] = red[k];
+    }
+    __syncthreads();
+    double red[6];
+    fin_reduce_any(red, [&](int vt, double v[6]) {
+        for (int k = 0; k < 6; ++k) v[k] = 0.0;
+        for (int q = vt; q < S.seg_count; q += kFinThreads) {
+            if (q == vt) {
+                for (int k = 0; k < 6; ++k) v[k] = seg[q][k];
+            } else {
+                v[0] += seg[q][0]; v[1] += seg[q][1]; v[2] = fmax(v[2], seg[q][2]); v[3] = fmax(v[3], seg[q][3]);
+                v[4] = fmax(v[4], seg[q][4]); v[5] += seg[q][5];
+            }
+        }
+    });
+    if (threadIdx.x == 0) {
+        SimIter &It = F.iters[s];
+        FinState st;
+        load_fin_state(st, It, S);
+        close_iteration(F, s, It, st, red);
+        if (It.done) publish_report(F, s, It);
+    }
+}
+
+// The workgroups of a sim meet. Every wave waits for its own stores, then
+// thread 0 makes them visible device-wide with a release-only arrival on its
+// group's word (an L2 write-back, no invalidation: workgroups still computing
+// keep their cached data); the last of its group acquires and arrives on the
+// sim's word. The last to arrive acquires, runs close() (whole workgroup) and
+// releases the others, which poll the release word and acquire once it moves:
+// after close() when close_first, else before it (close() then overlaps their
+// next phase, and a later barrier orders it). close() writes global memory from
+// thread 0 only. Phases count the sim's barriers. false: a wait gave up.
+template <typename C>
+__device__ inline bool sim_barrier(const TailArgs &L, const TailSeat &seat, uint32_t &phase, bool close_first, C close)
+{
+    __shared__ int s_word;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    ++phase;
+    if (threadIdx.x == 0) {
+        int last = 0;
+        const uint32_t a = __hip_atomic_fetch_add(seat.group, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (a + 1u == phase * seat.gsize) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const uint32_t b = __hip_atomic_fetch_add(&L.arrive[seat.s], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            last = b + 1u == phase * seat.ngroups;
+            if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        s_word = last;
+    }
+    __syncthreads();
+    const bool last = s_word;
+    __syncthreads();
+    if (last) {
+        if (!close_first && threadIdx.x == 0)
+            __hip_atomic_store(&L.release[seat.s], phase, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        close();
+        if (close_first && threadIdx.x == 0)
+            __hip_atomic_store(&L.release[seat.s], phase, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        for (long spins = 0; __hip_atomic_load(&L.release[seat.s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < phase;) {
+            if (++spins > kTailSpin) {
+                atomicOr(L.err, 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_word = ok;
+    }
+    __syncthreads();
+    const bool ok = s_word;
+    __syncthreads();
+    return ok;
+}
+
+// Blocks 0 .. n_tiles-1: one tile each (through the launch's tile ranges); the
+// last block publishes the reports of the sims outside the launch. A tail
+// launch holds few workgroups, so the register budget is set for no spills
+// (FP64: 2 waves per SIMD, FP32: 3) rather than for occupancy.
+template <typename T, int DIM, bool WALLS, bool AV, int LPP>
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3)))
+k_tail(PassArgs<T> A, FinArgs F, WallArgs<T> W, TailArgs L)
+{
+    const int v = blockIdx.x;
+    if (v >= A.n_tiles) {
+        for (int s = threadIdx.x; s < F.n_sims; s += blockDim.x)
+            if ((L.outside[s >> 5] >> (s & 31)) & 1u) {
+                F.done_out[s] = 1;
+                publish_report(F, s, F.iters[s]);
+            }
+        return;
+    }
+    const int t = launch_tile(A, v);
+    const int s = A.tiles[t].x;
+    const SimDev &S = A.sims[s];
+    const int nt = S.tile_end - S.tile_begin;
+    const int bi = t - S.tile_begin;  // this workgroup's place among the sim's
+    const int gi = bi / kTailGroup;
+    TailSeat seat;
+    seat.s = s;
+    seat.group = L.group + S.tile_begin / kTailGroup + s + gi;
+    seat.gsize = (uint32_t)min(kTailGroup, nt - gi * kTailGroup);
+    seat.ngroups = (uint32_t)((nt + kTailGroup - 1) / kTailGroup);
+    const bool walls = WALLS && S.nw > 0;
+    uint32_t phase = 0;
+    __shared__ int s_done;
+    for (int k = L.k0;; ++k) {
+        pass_tile<T, DIM, WALLS, AV, false, MODE_PSEUDO, LPP, false, 0, false>(A, t, (A.cur + k) & 1, k & 1);
+        if (!sim_barrier(L, seat, phase, !walls, [&]() { tail_close(F, s, S); })) return;
+        if (walls) {  // the sim's walls for iteration k + 1 (records of its fluid at k + 1)
+            const int end = S.wall_begin + S.nw, stride = nt * (int)blockDim.x;
+            for (int iw = S.wall_begin + bi * (int)blockDim.x + (int)threadIdx.x; iw < end; iw += stride)
+                wall_particle<T, DIM>(W, S, iw, (W.cur + k + 1) & 1, 0, false);
+            if (!sim_barrier(L, seat, phase, true, []() {})) return;
+        }
+        if (threadIdx.x == 0) s_done = __hip_atomic_load(&F.iters[s].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const bool done = s_done;
+        __syncthreads();
+        if (done) return;
+    }
+}
+
+__global__ void k_tail_zero(uint32_t *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Workgroups of a kernel that fit on the device at once (cached per kernel and
+// workgroup size).
+int coresident(const void *fn, int block)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(fn, block);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 0, per = 0;
+    DTSPH_HIP_CHECK(hipGetDevice(&dev));
+    DTSPH_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    DTSPH_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, block, 0));
+    const int n = per * cus;
+    cache[key] = n;
+    return n;
+}
+
+template <typename T, int DIM, bool WALLS, bool AV> const void *tail_kernel(int lpp)
+{
+    switch (lpp) {
+    case 1: return (const void *)k_tail<T, DIM, WALLS, AV, 1>;
+    case 2: return (const void *)k_tail<T, DIM, WALLS, AV, 2>;
+    case 4: return (const void *)k_tail<T, DIM, WALLS, AV, 4>;
+    default: return (const void *)k_tail<T, DIM, WALLS, AV, 8>;
+    }
+}
+
+template <typename T> const void *tail_kernel(const Ctx &c)
+{
+    if (c.max_dim == 2) {
+        if (c.any_walls) return c.any_av ? tail_kernel<T, 2, true, true>(c.lpp) : tail_kernel<T, 2, true, false>(c.lpp);
+        return c.any_av ? tail_kernel<T, 2, false, true>(c.lpp) : tail_kernel<T, 2, false, false>(c.lpp);
+    }
+    if (c.any_walls) return c.any_av ? tail_kernel<T, 3, true, true>(c.lpp) : tail_kernel<T, 3, true, false>(c.lpp);
+    return c.any_av ? tail_kernel<T, 3, false, true>(c.lpp) : tail_kernel<T, 3, false, false>(c.lpp);
+}
+
+}  // namespace
+
+// Tail launches run the plain pseudo pass only: no moving or steady sims, one
+// regulariser, no cached coefficients, no speculative gate, not a static
+// context (whose callers may not allow a cooperative launch).
+bool tail_kind(const Ctx &c)
+{
+    return c.tail_loop == 1 && !c.static_mode && !c.any_move && !c.any_steady && !c.sep_den && c.pair_cache == 0 &&
+           c.n_sims <= kTailMaxSims && c.block <= kMaxBlock;
+}
+
+// Can the sims still iterating (stop flags from the last report, tile ranges
+// from set_active_ranges) run the rest of their loop in one tail launch? Each
+// must be small, and the launch's tile ranges must cover exactly them.
+bool tail_fits(const Ctx &c)
+{
+    if (!tail_kind(c) || c.loop_cached || c.gated || c.replay) return false;
+    int64_t tiles = 0;
+    for (int s = 0; s < c.n_sims; ++s) {
+        if (c.flags_host[F_COUNT + s]) continue;
+        const int nt = c.sims_h[s].tile_end - c.sims_h[s].tile_begin;
+        if (nt <= 0 || nt > kTailSimTiles) return false;
+        tiles += nt;
+    }
+    // a small remainder of a batch (a single sim runs its loop with plain
+    // launches: inside a launch a device-wide barrier costs about what a kernel
+    // boundary does, so a persistent loop gains nothing there)
+    if (tiles == 0 || 4 * tiles > c.n_tiles || tiles + 1 > tail_capacity(c)) return false;
+    return tiles == c.n_act_tiles;  // not every tile of a context in which some sims stopped
+}
+
+int tail_capacity(const Ctx &c)
+{
+    const void *fn = c.precision == DTSPH_FP32 ? tail_kernel<float>(c) : tail_kernel<double>(c);
+    return coresident(fn, c.block);
+}
+
+template <typename T> bool launch_tail(Ctx &c, int k0)
+{
+    if (!tail_fits(c)) return false;
+    const void *fn = tail_kernel<T>(c);
+    const int grid = c.n_act_tiles + 1;
+    PassArgs<T> a = pass_args<T>(c, MODE_PSEUDO, false);
+    FinArgs f = fin_args(c, true);
+    WallArgs<T> w = wall_args<T>(c, MODE_PSEUDO, false);
+    TailArgs L;
+    L.k0 = k0;
+    L.arrive = c.tail_words;
+    L.release = c.tail_words + c.n_sims;
+    L.err = (int *)(c.tail_words + 2 * c.n_sims);
+    L.group = c.tail_words + 2 * c.n_sims + 1;
+    for (int q = 0; q < kTailMaxSims / 32; ++q) L.outside[q] = 0u;
+    for (int s = 0; s < c.n_sims; ++s)
+        if (c.flags_host[F_COUNT + s]) L.outside[s >> 5] |= 1u << (s & 31);
+    const int nw = 2 * c.n_sims + 1 + c.n_tiles / kTailGroup + c.n_sims + 1;  // arrivals, releases, error, groups
+    hipLaunchKernelGGL(k_tail_zero, dim3((nw + 255) / 256), dim3(256), 0, c.stream, c.tail_words, nw);
+    DTSPH_HIP_CHECK(hipGetLastError());
+    void *args[] = {&a, &f, &w, &L};
+    DTSPH_HIP_CHECK(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(c.block), args, 0, c.stream));
+    c.tstats.tail_launches++;
+    return true;
+}
+
+template bool launch_tail<float>(Ctx &, int);
+template bool launch_tail<double>(Ctx &, int);
+
+}  // namespace dtsph

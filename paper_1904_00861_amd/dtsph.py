@@ -23,7 +23,7 @@ FP64, FP32 = 0, 1
 REASONS = {0: "running", 1: "converged", 2: "stalled", 3: "max_iter", 4: "nonfinite", 5: "fixed"}
 OPT_TIMING, OPT_RESET_TIMING, OPT_CHUNK, OPT_BLOCK, OPT_XCD_REMAP, OPT_LANES, OPT_SKIN = 1, 2, 3, 4, 5, 6, 7
 OPT_CELL_DIV, OPT_NBR_LANES, OPT_GRAPHS, OPT_PAIR_CACHE, OPT_SPECULATE, OPT_FILTER_LANES = 8, 9, 10, 11, 12, 13
-OPT_ABS32_POSITIONS, OPT_NBR_TILES = 14, 15
+OPT_ABS32_POSITIONS, OPT_NBR_TILES, OPT_TAIL_LOOP = 14, 15, 16
 
 EXPORTS = [
     "dtsph_create", "dtsph_destroy", "dtsph_last_error", "dtsph_set_state", "dtsph_get_state",
@@ -91,7 +91,7 @@ class Timing(C.Structure):
                 ("build_particles", C.c_int64), ("filter_launches", C.c_int64), ("filter_ms", C.c_double),
                 ("full_builds", C.c_int64), ("list_filters", C.c_int64),
                 ("last_max_shift", C.c_double), ("last_disp", C.c_double),
-                ("spec_tries", C.c_int64), ("spec_hits", C.c_int64)]
+                ("spec_tries", C.c_int64), ("spec_hits", C.c_int64), ("tail_launches", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
