@@ -200,8 +200,10 @@ def leg_summary(problems, leg, dtype, steps, cfg=None, timing_every=-1):
                                   "calibrated), from the committed counter summary of this kernel source")
             rf["traffic_over_algorithmic"] = round(tr[0] / tr[1], 3)
         out["roofline"] = rf
-        launches_all = sum(max(r["iters"] for r in step) for step in leg["reports"])
-        out["pass_share_of_step_time"] = round(tm["pass_ms"] / tm["pass_launches"] * launches_all * 1e-3 / secs, 4)
+        # the time every pair evaluation of the timed region would take at the
+        # rate of the timed full-batch launches, as a share of that region
+        s_per_pair = tm["pass_ms"] * 1e-3 / tm["pass_pairs"]
+        out["pass_share_of_step_time"] = round(evals * s_per_pair / secs, 4)
     if tm["build_launches"] > 0 and tm["build_ms"] > 0:
         n_all = sum(p.n for p in problems)
         exact = sum(r["pairs"] for r in leg["reports"][-1]) / n_all  # fluid rows; walls add few
