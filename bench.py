@@ -116,7 +116,7 @@ def apply_shape(sim, shape):
     sim.set_option(D.OPT_CELL_DIV, cell_div)
 
 
-def run_leg(problems, precision, steps, warmup, timing_every, shape=None, pair_cache=0, graphs=0):
+def run_leg(problems, precision, steps, warmup, timing_every, shape=None, pair_cache=0, graphs=0, schedule=None):
     import torch
     from paper_1904_00861_amd import dtsph as D
 
@@ -125,6 +125,8 @@ def run_leg(problems, precision, steps, warmup, timing_every, shape=None, pair_c
         sim.set_option(D.OPT_PAIR_CACHE, pair_cache)
     if graphs:
         sim.set_option(D.OPT_GRAPHS, 1)
+    if schedule is not None:
+        sim.set_option(D.OPT_TAIL_LOOP, schedule)
     if shape:  # fixed launch configuration instead of the autotuner
         lanes, block, nbr_lanes, cell_div = shape
         apply_shape(sim, shape)
@@ -379,6 +381,9 @@ def main():
                     help="workload of the second leg")
     ap.add_argument("--second-steps", type=int, default=20)
     ap.add_argument("--no-timing", action="store_true", help="no HIP events in the timed region")
+    ap.add_argument("--schedule", type=int, default=None, choices=[0, 1, 2],
+                    help="loop schedule of the main leg (DTSPH_OPT_TAIL_LOOP): 0 plain chunks, 1 cut first chunk "
+                         "and a persistent tail launch (the library's default), 2 cut first chunk, plain chunks")
     ap.add_argument("--graphs", type=int, default=0, choices=[0, 1],
                     help="1: record each step's segment up to the first chunk of pseudo-iterations as a HIP "
                          "graph and replay it (main leg)")
@@ -451,7 +456,8 @@ def main():
         counter_run(problems, prec, args.steps, args.warmup, args.counter_run, shape)
         return
     every = 0 if args.no_timing else args.timing_every
-    main_leg = run_leg(problems, prec, args.steps, args.warmup, every, shape, args.pair_cache, args.graphs)
+    main_leg = run_leg(problems, prec, args.steps, args.warmup, every, shape, args.pair_cache, args.graphs,
+                       args.schedule)
     main = leg_summary(problems, main_leg, dtype, args.steps, args.config, args.timing_every)
     log(f"main leg: {main_leg['seconds'] * 1e3:.2f} ms, {main['value']:.3e} pair-evals/s, "
         f"{main['ms_per_step']:.3f} ms/step, iterations/step mean {main['iterations_per_step_mean']:.2f}")
@@ -509,6 +515,7 @@ def main():
                    "particles": n_particles,
                    "particle_shifting": bool(any(p.params.get("shift", 0) for p in problems)),
                    "pair_sums": args.precision, "pair_cache": args.pair_cache, "graphs": args.graphs,
+                   "loop_schedule": 1 if args.schedule is None else args.schedule,
                    "positions_pressure_residuals": "f64",
                    "instance_steps_per_s": main["instance_steps_per_s"],
                    "iterations_per_step_mean": main["iterations_per_step_mean"],
