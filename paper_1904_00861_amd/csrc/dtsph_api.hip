@@ -976,15 +976,16 @@ template <typename T> void step_segment(Ctx &c, LoopRun &L)
     DTSPH_HIP_CHECK(hipGraphLaunch(ex, c.stream));
 }
 
-// Speculative end of step: behind a device gate (spec_gate, evaluated by every
-// gated workgroup: every sim stopped, no non-finite residual, candidate lists
-// still cover r^{n+1}) queue the corrector
+// Speculative end of step: behind a device gate (every sim stopped, no
+// non-finite residual, candidate lists still cover r^{n+1}; evaluated once by
+// k_gate into a word every gated workgroup reads) queue the corrector
 // and, when another step follows, the next rate pass on the candidate lists, so
 // the GPU works while the host waits for the reports. When the gate is closed
 // these launches return at once and the host proceeds as without them.
 template <typename T> void launch_speculation(Ctx &c, bool next_pre)
 {
     c.tstats.spec_tries++;
+    launch_gate(c);
     c.gated = true;
     const bool p_half = c.p_half;
     c.p_half = true;  // state at the end of a loop: p^K is still pending
@@ -1232,7 +1233,7 @@ static int create_impl(const dtsph_sim_desc *sims, const int64_t *n_fluid, const
 
         // device memory
         dev_alloc(c, c.sims, sizeof(SimDev) * n_sims);
-        dev_alloc(c, c.iters, sizeof(SimIter) * n_sims);
+        dev_alloc(c, c.iters, sizeof(SimIter) * (n_sims + 1));  // + the speculative gate
         if (precision == DTSPH_FP32) alloc_state<float>(c);
         else alloc_state<double>(c);
         dev_alloc(c, c.key, 4 * (size_t)N);

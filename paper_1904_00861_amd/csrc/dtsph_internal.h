@@ -190,7 +190,7 @@ struct Ctx {
     size_t mirror_bytes = 0;
     int64_t device_bytes = 0;
     SimDev *sims = nullptr;
-    SimIter *iters = nullptr;
+    SimIter *iters = nullptr;             // per sim, then the speculative gate (k_gate)
     int *orig[2] = {nullptr, nullptr};
     int *simid[2] = {nullptr, nullptr};
     double *x[2] = {nullptr, nullptr};    // active positions (3 x N SoA)
@@ -306,6 +306,7 @@ void launch_finalize(Ctx &c, bool publish);
 template <typename T> void launch_finalize_wall(Ctx &c, bool publish, int next);
 // wall pressures of the last iteration each sim ran (after a loop of fused wall passes)
 template <typename T> void launch_wall_pressure(Ctx &c);
+void launch_gate(Ctx &c);  // the speculative gate, before gated launches
 // The rest of a pseudo-time loop in one persistent launch when the sims still
 // iterating are few and small (dtsph_tail.hip); false: not launched (the caller
 // goes on with plain chunks). k0 = iterations every such sim has run.

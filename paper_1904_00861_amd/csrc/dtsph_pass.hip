@@ -511,6 +511,12 @@ void launch_wall(Ctx &c, int mode, bool cand_lists)
     if (mode == MODE_PSEUDO) timer_end(c, t0, 1);
 }
 
+void launch_gate(Ctx &c)
+{
+    DTSPH_LAUNCH(c, k_gate, dim3(1), dim3(256), 0, c.stream, c.n_sims, c.iters, c.sims);
+    DTSPH_HIP_CHECK(hipGetLastError());
+}
+
 void launch_publish(Ctx &c)
 {
     const int n = F_COUNT + c.n_sims;

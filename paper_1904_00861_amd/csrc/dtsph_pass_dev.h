@@ -119,12 +119,26 @@ template <int DIM> struct Pos<double, DIM> {
 // applies to the same, published, values).
 __device__ inline bool spec_gate(int n_sims, const SimIter *__restrict__ iters, const SimDev *__restrict__ sims)
 {
-    bool go = true;
-    for (int s = 0; s < n_sims; ++s) {
+    (void)sims;
+    return iters[n_sims].done != 0;  // evaluated once by k_gate before the gated launches
+}
+
+// The speculative gate, once per speculative end of step (one workgroup,
+// before the gated launches): every sim stopped, no non-finite residual, and
+// the candidate lists still cover r^{n+1}. Written to the loop-state slot after
+// the sims' own (a word each gated workgroup reads instead of every sim's state).
+__global__ void __launch_bounds__(256) k_gate(int n_sims, SimIter *__restrict__ iters, const SimDev *__restrict__ sims)
+{
+    __shared__ int ok;
+    if (threadIdx.x == 0) ok = 1;
+    __syncthreads();
+    for (int s = threadIdx.x; s < n_sims; s += blockDim.x) {
         const SimIter &It = iters[s];
-        go = go && It.done && It.reason != DTSPH_NONFINITE && sims[s].skin > 0 && It.disp < 0.4 * sims[s].skin;
+        if (!(It.done && It.reason != DTSPH_NONFINITE && sims[s].skin > 0 && It.disp < 0.4 * sims[s].skin))
+            atomicAnd(&ok, 0);
     }
-    return go;
+    __syncthreads();
+    if (threadIdx.x == 0) iters[n_sims].done = ok;
 }
 
 template <typename T> struct PassConst {
