@@ -210,7 +210,7 @@ def leg_summary(problems, leg, dtype, steps, cfg=None, timing_every=-1):
         n_all = sum(p.n for p in problems)
         exact = sum(r["pairs"] for r in leg["reports"][-1]) / n_all  # fluid rows; walls add few
         p0 = problems[0].params
-        skin = (0.25 if p0.get("shift", 0) else 0.1) * p0["h"]
+        skin = (0.25 if p0.get("shift", 0) else 0.3) * p0["h"]
         kh = p0["kappa"] * p0["h"]
         cand = exact * ((kh + skin) / kh) ** dim
         bpp = build_bytes_per_particle(dtype, dim, exact, cand)

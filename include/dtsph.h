@@ -308,7 +308,8 @@ int dtsph_get_state(dtsph_ctx *ctx, const dtsph_state_view *state);
  * sets equal those of any implementation of that formula. The lists are
  * needed once per position change: at r^n and at r^(0) in each step; the
  * pseudo-time loop reuses them (frozen particles). A build also keeps
- * candidate lists of radius kappa*h + skin (skin = 0.1 h); since
+ * candidate lists of radius kappa*h + skin (skin = 0.3 h; 0.25 h with
+ * particle shifting); since
  * r^{n+1} - r^(0) = dt/2 (V^{n+1} - V^(0)), the loop knows how far particles
  * will move, and the lists at r^{n+1} are then the candidates filtered by
  * the same exact predicate (no sort) whenever that distance is below 0.4 skin.
@@ -372,7 +373,7 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *
 #define DTSPH_OPT_LANES 6      /* lanes per particle in the pair pass: 1, 2, 4, 8
                                   (default: smallest giving >= 512k threads)  */
 #define DTSPH_OPT_SKIN 7       /* candidate-list skin in thousandths of h, at
-                                  most the default (100; 250 for sims with
+                                  most the default (300; 250 for sims with
                                   shifting) (0: rebuild the cell lists at
                                   every position change)                     */
 #define DTSPH_OPT_CELL_DIV 8   /* cell side >= (kappa h + skin) / value, value
