@@ -412,7 +412,7 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *
                                   artificial viscosity 8 / 16 B more in 2D,
                                   16 / 32 B in 3D), which adds to
                                   dtsph_workspace_bytes; between steps only. */
-#define DTSPH_OPT_SPECULATE 12 /* 1 (default): dtsph_step queues the corrector
+#define DTSPH_OPT_SPECULATE 12 /* 1: dtsph_step queues the corrector
                                   and the next step's rate pass (with shifting:
                                   the shift kernels instead of the rate pass)
                                   behind a device gate (every sim stopped, no
@@ -422,7 +422,9 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *
                                   nothing and the step ends as with 0. Off for
                                   contexts with graphs or more than 64 sims,
                                   and while recent gates mostly stayed closed.
-                                  Results are identical.                      */
+                                  Results are identical. 0 (default): with the
+                                  cut loop schedule most chunks do not end the
+                                  loop, and speculation measured no faster.   */
 #define DTSPH_OPT_FILTER_LANES 13 /* lanes per particle of the candidate-list
                                   filter: 1, 2, 4, 8 (0: automatic)           */
 #define DTSPH_OPT_ABS32_POSITIONS 14 /* ablation of the FP32 path (0 default):

@@ -227,7 +227,7 @@ struct Ctx {
     // speculative end of step (dtsph_step): the corrector and the next rate pass
     // are queued behind a device gate before the host reads the loop's reports
     bool gated = false;                   // the next launches are speculative
-    bool speculate = true, spec_ready = false;
+    bool speculate = false, spec_ready = false;  // DTSPH_OPT_SPECULATE (off by default)
     int spec_score = 4, spec_idle = 0;    // recent success of speculation (adaptive)
     // after shifting: skip the read-back of the largest shift while shifts keep
     // leaving the candidate skin (checked later, at the next wait)
