@@ -36,7 +36,7 @@ constexpr int kSegTiles = 256;       // tiles per residual segment (one finalize
 constexpr int kMaxTileRows = 32;     // cell rows per strip of the staged neighbour kernel
 constexpr int kTailMaxSims = 256;    // sims of a context that may use tail launches
 constexpr int kTailSimTiles = 128;   // tiles of one sim in a tail launch (its barrier's workgroups)
-constexpr int kTailGroup = 16;       // workgroups per first-level barrier word of a tail launch
+constexpr int kTailGroup = 32;       // workgroups per first-level barrier word of a tail launch
 
 enum PassMode { MODE_PRE = 0, MODE_PSEUDO = 1 };
 

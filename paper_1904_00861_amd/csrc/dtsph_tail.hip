@@ -160,9 +160,14 @@ __device__ inline bool sim_barrier(const TailArgs &L, const TailSeat &seat, uint
         const uint32_t a = __hip_atomic_fetch_add(seat.group, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (a + 1u == phase * seat.gsize) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const uint32_t b = __hip_atomic_fetch_add(&L.arrive[seat.s], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            last = b + 1u == phase * seat.ngroups;
-            if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (seat.ngroups == 1) {  // the group is the sim: its last is the last
+                last = 1;
+            } else {
+                const uint32_t b =
+                    __hip_atomic_fetch_add(&L.arrive[seat.s], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                last = b + 1u == phase * seat.ngroups;
+                if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
         }
         s_word = last;
     }

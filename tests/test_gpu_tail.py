@@ -91,7 +91,7 @@ def test_tail_launches_every_lane_count(lanes, block):
 
 def test_tail_launch_multi_group_sims():
     # an 8100-particle vortex at 64-particle tiles: 127 tiles, so its barrier
-    # spans 8 groups of workgroups, next to a cavity (the big vortex stops at
+    # spans 4 groups of workgroups, next to a cavity (the big vortex stops at
     # once: the two small sims are the remainder)
     banner("tail launch with multi-group sims")
     probs = lambda: [_loose(I.tgv2d(200, seed=11)), I.tgv2d(90, seed=9, re=500.0), I.cavity(30, re=800.0)]
