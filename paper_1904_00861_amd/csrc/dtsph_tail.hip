@@ -57,14 +57,17 @@ struct TailSeat {
 // multiple of 64 threads: value vt comes from load(vt, v); the waves take the
 // same 64-value groups in turn, with the same butterflies, and thread 0 adds the
 // group sums in the same order, so the result (thread 0) is bit-identical.
-template <typename L> __device__ inline void fin_reduce_any(double out[6], L load)
+// Values from n on are zero: their groups are not loaded, and thread 0 combines
+// +0.0 for them (which is what their butterflies give).
+template <typename L> __device__ inline void fin_reduce_any(double out[6], int n, L load)
 {
     constexpr int G = kFinThreads / 64;
     __shared__ double lds[G][6];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int w0 = 0; w0 < G; w0 += nw) {
+    const int gn = (n + 63) / 64;  // groups holding values
+    for (int w0 = 0; w0 < gn; w0 += nw) {
         const int w = w0 + wave;
-        if (w < G) {  // uniform per wave
+        if (w < gn) {  // uniform per wave
             double v[6];
             load(w * 64 + lane, v);
             for (int o = 32; o > 0; o >>= 1) {
@@ -81,14 +84,16 @@ template <typename L> __device__ inline void fin_reduce_any(double out[6], L loa
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 0; k < 6; ++k) out[k] = lds[0][k];
+        for (int k = 0; k < 6; ++k) out[k] = gn > 0 ? lds[0][k] : 0.0;
         for (int w = 1; w < G; ++w) {
-            out[0] += lds[w][0];
-            out[1] += lds[w][1];
-            out[2] = fmax(out[2], lds[w][2]);
-            out[3] = fmax(out[3], lds[w][3]);
-            out[4] = fmax(out[4], lds[w][4]);
-            out[5] += lds[w][5];
+            double g[6];
+            for (int k = 0; k < 6; ++k) g[k] = w < gn ? lds[w][k] : 0.0;
+            out[0] += g[0];
+            out[1] += g[1];
+            out[2] = fmax(out[2], g[2]);
+            out[3] = fmax(out[3], g[3]);
+            out[4] = fmax(out[4], g[4]);
+            out[5] += g[5];
         }
     }
     __syncthreads();
@@ -97,15 +102,15 @@ template <typename L> __device__ inline void fin_reduce_any(double out[6], L loa
 // Closes the current iteration of sim s (whole workgroup, after every tile of
 // the sim has written its partials): the segment sums (kept in LDS: a tail sim
 // has at most ceil(kTailSimTiles / kSegTiles) segments), their sum, the stop test
-// and, when the sim stops, its report.
-__device__ inline void tail_close(const FinArgs &F, int s, const SimDev &S)
+// and, when the sim stops, its report. Returns the stop flag (thread 0).
+__device__ inline int tail_close(const FinArgs &F, int s, const SimDev &S)
 {
     constexpr int kSegs = (kTailSimTiles + kSegTiles - 1) / kSegTiles;
     __shared__ double seg[kSegs][6];
     for (int q = 0; q < S.seg_count; ++q) {
         const int4 sg = F.segs[S.seg_begin + q];
         double red[6];
-        fin_reduce_any(red, [&](int vt, double v[6]) {
+        fin_reduce_any(red, sg.z - sg.y, [&](int vt, double v[6]) {
             for (int k = 0; k < 6; ++k) v[k] = 0.0;
             const int t = sg.y + vt;
             if (t < sg.z) {
@@ -119,7 +124,7 @@ __device__ inline void tail_close(const FinArgs &F, int s, const SimDev &S)
     }
     __syncthreads();
     double red[6];
-    fin_reduce_any(red, [&](int vt, double v[6]) {
+    fin_reduce_any(red, S.seg_count, [&](int vt, double v[6]) {
         for (int k = 0; k < 6; ++k) v[k] = 0.0;
         for (int q = vt; q < S.seg_count; q += kFinThreads) {
             if (q == vt) {
@@ -130,26 +135,31 @@ __device__ inline void tail_close(const FinArgs &F, int s, const SimDev &S)
             }
         }
     });
+    int stop = 0;
     if (threadIdx.x == 0) {
         SimIter &It = F.iters[s];
         FinState st;
         load_fin_state(st, It, S);
         close_iteration(F, s, It, st, red);
-        if (It.done) publish_report(F, s, It);
+        stop = It.done;
+        if (stop) publish_report(F, s, It);
     }
+    return stop;  // thread 0
 }
 
 // The workgroups of a sim meet. Every wave waits for its own stores, then
 // thread 0 makes them visible device-wide with a release-only arrival on its
 // group's word (an L2 write-back, no invalidation: workgroups still computing
-// keep their cached data); the last of its group acquires and arrives on the
-// sim's word. The last to arrive acquires, runs close() (whole workgroup) and
-// releases the others, which poll the release word and acquire once it moves:
-// after close() when close_first, else before it (close() then overlaps their
-// next phase, and a later barrier orders it). close() writes global memory from
-// thread 0 only. Phases count the sim's barriers. false: a wait gave up.
+// keep their cached data); the last of its group acquires and, when the sim has
+// several groups, arrives on the sim's word. The last to arrive acquires, runs
+// close() (whole workgroup; its value in thread 0: the sim's stop flag) and
+// releases the others with (phase << 1 | stop flag) in the release word, which
+// they poll and acquire once it moves: after close() when close_first, else
+// before it with a zero flag (close() then overlaps their next phase, and a
+// later barrier orders it). close() writes global memory from thread 0 only.
+// Phases count the sim's barriers. Returns the flag, or -1: a wait gave up.
 template <typename C>
-__device__ inline bool sim_barrier(const TailArgs &L, const TailSeat &seat, uint32_t &phase, bool close_first, C close)
+__device__ inline int sim_barrier(const TailArgs &L, const TailSeat &seat, uint32_t &phase, bool close_first, C close)
 {
     __shared__ int s_word;
     __builtin_amdgcn_s_waitcnt(0);
@@ -176,29 +186,41 @@ __device__ inline bool sim_barrier(const TailArgs &L, const TailSeat &seat, uint
     __syncthreads();
     if (last) {
         if (!close_first && threadIdx.x == 0)
-            __hip_atomic_store(&L.release[seat.s], phase, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        close();
-        if (close_first && threadIdx.x == 0)
-            __hip_atomic_store(&L.release[seat.s], phase, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        return true;
+            __hip_atomic_store(&L.release[seat.s], phase << 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int stop = close();
+        if (threadIdx.x == 0) {
+            const int flag = close_first ? stop : 0;
+            if (close_first)
+                __hip_atomic_store(&L.release[seat.s], phase << 1 | (uint32_t)flag, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            s_word = flag;
+        }
+        __syncthreads();
+        const int r = s_word;
+        __syncthreads();
+        return r;
     }
     if (threadIdx.x == 0) {
-        int ok = 1;
-        for (long spins = 0; __hip_atomic_load(&L.release[seat.s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < phase;) {
-            if (++spins > kTailSpin) {
+        int r = -1;
+        for (long spins = 0;; ++spins) {
+            const uint32_t w = __hip_atomic_load(&L.release[seat.s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((w >> 1) >= phase) {
+                r = (int)(w & 1u);
+                break;
+            }
+            if (spins > kTailSpin) {
                 atomicOr(L.err, 1);
-                ok = 0;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        s_word = ok;
+        s_word = r;
     }
     __syncthreads();
-    const bool ok = s_word;
+    const int r = s_word;
     __syncthreads();
-    return ok;
+    return r;
 }
 
 // Blocks 0 .. n_tiles-1: one tile each (through the launch's tile ranges); the
@@ -231,21 +253,22 @@ k_tail(PassArgs<T> A, FinArgs F, WallArgs<T> W, TailArgs L)
     seat.ngroups = (uint32_t)((nt + kTailGroup - 1) / kTailGroup);
     const bool walls = WALLS && S.nw > 0;
     uint32_t phase = 0;
-    __shared__ int s_done;
     for (int k = L.k0;; ++k) {
         pass_tile<T, DIM, WALLS, AV, false, MODE_PSEUDO, LPP, false, 0, false>(A, t, (A.cur + k) & 1, k & 1);
-        if (!sim_barrier(L, seat, phase, !walls, [&]() { tail_close(F, s, S); })) return;
+        int stop = sim_barrier(L, seat, phase, !walls, [&]() { return tail_close(F, s, S); });
+        if (stop < 0) return;
         if (walls) {  // the sim's walls for iteration k + 1 (records of its fluid at k + 1)
             const int end = S.wall_begin + S.nw, stride = nt * (int)blockDim.x;
             for (int iw = S.wall_begin + bi * (int)blockDim.x + (int)threadIdx.x; iw < end; iw += stride)
                 wall_particle<T, DIM>(W, S, iw, (W.cur + k + 1) & 1, 0, false);
-            if (!sim_barrier(L, seat, phase, true, []() {})) return;
+            // the iteration's close has arrived at this barrier: its last reads the flag
+            stop = sim_barrier(L, seat, phase, true, [&]() {
+                return threadIdx.x == 0 ? __hip_atomic_load(&F.iters[s].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                        : 0;
+            });
+            if (stop < 0) return;
         }
-        if (threadIdx.x == 0) s_done = __hip_atomic_load(&F.iters[s].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const bool done = s_done;
-        __syncthreads();
-        if (done) return;
+        if (stop) return;
     }
 }
 
