@@ -480,7 +480,52 @@ __device__ __forceinline__ void pass_tile(const PassArgs<T> &A, int t, int par, 
             }
         }
         if (WALLS) {
-            for (int k = nfl + sub; k < nfl + nwl; k += LPP) {
+            // wall neighbours in batches too (UW index loads, then their ghost
+            // records, position records and wall velocities in flight), summed
+            // in list order like the rest; FP32 plain passes only (the FP64 and
+            // the heavier variants would spill registers)
+            constexpr int UW = sizeof(T) == 4 && !CONV && CACHE == 0 && !MOVE && !SEPDEN ? 4 : 1;
+            const int nend = nfl + nwl;
+            int k = nfl + sub;
+            for (; UW > 1 && k + (UW - 1) * LPP < nend; k += UW * LPP) {
+                int jj[UW];
+#pragma unroll
+                for (int m = 0; m < UW; ++m) jj[m] = nb[(size_t)(k + m * LPP) * N];
+                Q gj[UW], cc[UW];
+                Rec rj[UW];
+                AvT ua[UW];
+                T vw[UW][3];
+#pragma unroll
+                for (int m = 0; m < UW; ++m) {
+                    gj[m] = vin[jj[m]];  // ghost velocity and wall pressure
+                    const int jw = jj[m] - Nf;
+                    for (int d = 0; d < 3; ++d) vw[m][d] = d < DIM ? A.vwall[d * A.Nw + jw] : T(0);
+                    if (CACHE == 2) {
+                        cc[m] = cf[(size_t)(k + m * LPP) * N];
+                        ua[m] = AV ? cu[(size_t)(k + m * LPP) * N] : u0;
+                    } else {
+                        rj[m] = prec[jj[m]];
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < UW; ++m) {
+                    T r[3], vd[3], vv[3];
+                    for (int d = 0; d < 3; ++d) vd[d] = vi[d] - vw[m][d];
+                    vv[0] = vi[0] - gj[m].x;
+                    vv[1] = vi[1] - gj[m].y;
+                    vv[2] = DIM == 3 ? vi[2] - gj[m].z : T(0);
+                    if (CACHE == 2) {
+                        pair_cached<T, DIM, AV, CONV>(K, cc[m], ua[m], vd, vv, vi, av, pi, pres<DIM>(gj[m]), acc);
+                    } else {
+                        pos.delta(ri, rj[m], r);
+                        const size_t e = (size_t)(k + m * LPP) * N;
+                        pair_terms<T, DIM, AV, SEPDEN, CONV, CACHE == 1>(K, r, vd, vv, vi, av, pi, pres<DIM>(gj[m]), acc,
+                                                                         CACHE ? cf + e : nullptr,
+                                                                         (CACHE && AV) ? cu + e : nullptr);
+                    }
+                }
+            }
+            for (; k < nend; k += LPP) {
                 const int j = nb[(size_t)k * N];
                 const Q gj = vin[j];  // ghost velocity and wall pressure
                 const int jw = j - Nf;
