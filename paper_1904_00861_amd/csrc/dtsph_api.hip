@@ -1284,8 +1284,11 @@ static int create_impl(const dtsph_sim_desc *sims, const int64_t *n_fluid, const
         dev_alloc(c, c.tiles, sizeof(int2) * max_tiles);
         dev_alloc(c, c.partials, sizeof(double4) * max_tiles);
         const size_t max_segs = max_tiles / kSegTiles + (size_t)n_sims + 1;
-        if (!c.static_mode)  // tail launches: arrivals, releases, error word, group words
-            dev_alloc(c, c.tail_words, sizeof(uint32_t) * (3 * (size_t)n_sims + 2 + max_tiles / kTailGroup));
+        if (!c.static_mode) {  // tail launches: arrivals, error word, group words; odd iterations' partials
+            dev_alloc(c, c.tail_words, sizeof(uint32_t) * (2 * (size_t)n_sims + 2 + max_tiles / kTailGroup));
+            dev_alloc(c, c.tail_part4, sizeof(double4) * max_tiles);
+            dev_alloc(c, c.tail_part2, sizeof(double2) * max_tiles);
+        }
         dev_alloc(c, c.segs, sizeof(int4) * max_segs);
         dev_alloc(c, c.seg_p, sizeof(double4) * max_segs);
         dev_alloc(c, c.seg_p2, sizeof(double2) * max_segs);

@@ -159,11 +159,14 @@ struct Ctx {
     int last_iters = 4;      // adaptive chunking
     std::vector<int> prev_iters;  // per sim: iterations of its last loop (-1: none yet)
     // loop schedule (DTSPH_OPT_TAIL_LOOP): 0 plain chunks, 1 cut first chunk
-    // and tail launches, 2 cut first chunk and plain chunks; per sim arrival and
-    // release words of the sims' barriers, an error word, then the words of
-    // the workgroup groups (tiles / kTailGroup + n_sims + 1)
+    // and tail launches, 2 cut first chunk and plain chunks; per sim arrival
+    // words of the sims' barriers, an error word, then the words of the
+    // workgroup groups (tiles / kTailGroup + n_sims + 1); the tail launches'
+    // second buffer of residual partials (odd iterations)
     int tail_loop = 1;
     uint32_t *tail_words = nullptr;
+    double4 *tail_part4 = nullptr;
+    double2 *tail_part2 = nullptr;
     // pair-pass launches inside a loop cover only sims still iterating: tile
     // ranges (first tile, index within the launch); n_ranges == 0: every tile
     int n_ranges = 0, n_act_tiles = 0;

@@ -357,15 +357,16 @@ template <typename T, int DIM, bool HEAVY> struct PassWaves {
 // buffers: the rate pass reads buffer `cur`; iteration k of sim s reads buffer
 // par = (cur + k) & 1 and writes the other (ppar = k & 1 picks the position
 // records of moving sims), so a sim whose loop has stopped simply drops out.
+// The tile's record tl = tiles[t] and its sim's constants S are the caller's
+// (a persistent caller keeps them on chip); the tile's residual partials go to
+// part4[t], part2[t].
 template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP, bool CONV, int CACHE, bool MOVE>
-__device__ __forceinline__ void pass_tile(const PassArgs<T> &A, int t, int par, int ppar)
+__device__ __forceinline__ void pass_tile_at(const PassArgs<T> &A, const SimDev &S, int t, int2 tl, int par, int ppar,
+                                             double4 *__restrict__ part4, double2 *__restrict__ part2)
 {
     using Q = typename V4<T>::type;
     using PosT = Pos<T, DIM>;
     using Rec = typename PosT::Rec;
-    const int2 tl = A.tiles[t];
-    const int s = tl.x;
-    const SimDev &S = A.sims[s];
     const int sub = (int)threadIdx.x & (LPP - 1);
     const int i = tl.y + (int)threadIdx.x / LPP;
     const bool active = i < S.fluid_begin + S.nf;
@@ -664,10 +665,18 @@ __device__ __forceinline__ void pass_tile(const PassArgs<T> &A, int t, int par, 
                 a4 = fmax(a4, lds[wv][4]);
                 a5 += lds[wv][5];
             }
-            A.partials[t] = make_double4(a0, a1, a2, a3);
-            A.partials2[t] = make_double2(a4, a5);
+            part4[t] = make_double4(a0, a1, a2, a3);
+            part2[t] = make_double2(a4, a5);
         }
     }
+}
+
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP, bool CONV, int CACHE, bool MOVE>
+__device__ __forceinline__ void pass_tile(const PassArgs<T> &A, int t, int par, int ppar)
+{
+    const int2 tl = A.tiles[t];
+    pass_tile_at<T, DIM, WALLS, AV, SEPDEN, MODE, LPP, CONV, CACHE, MOVE>(A, A.sims[tl.x], t, tl, par, ppar, A.partials,
+                                                                          A.partials2);
 }
 
 template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP, bool CONV, int CACHE = 0,
@@ -935,13 +944,13 @@ __device__ inline void load_fin_state(FinState &F, const SimIter &It, const SimD
     F.stall_rel = S.stall_rel;
 }
 
-// Iteration F.iters of sim s from its reduced partials red = {sum |D|, sum
+// Iteration F.iters of a sim from its reduced partials red = {sum |D|, sum
 // |Vtilde|, max |D|, max |Vtilde|, max |V - V^(0)|^2, pairs} (one thread): the
-// residuals of eq. conv, the stop test, the loop state and the stop flag.
-__device__ inline void close_iteration(const FinArgs &A, int s, SimIter &It, const FinState &F, const double red[6])
+// residuals of eq. conv, the stop test and the loop state It, whose done flag
+// the caller publishes.
+__device__ inline void close_iteration(SimIter &It, const FinState &F, const double red[6])
 {
     const double sd = red[0], sv = red[1], md = red[2], mv = red[3], mw = red[4], np = red[5];
-    int *done_out = A.done_out;
     It.disp = F.steady ? 0.0 : 0.5 * F.dt * sqrt(mw);  // steady sims never move
     It.pairs = (long long)np;
     const double rp = sd * F.res_p, rv = sv * F.res_v;
@@ -990,7 +999,6 @@ __device__ inline void close_iteration(const FinArgs &A, int s, SimIter &It, con
         It.done = 1;
         It.reason = reason;
     }
-    done_out[s] = It.done;
 }
 
 // Segment g of the residual reduction; the last segment of a sim to arrive
@@ -1043,7 +1051,8 @@ __device__ __forceinline__ void finalize_segment(const FinArgs &A, int g)
     fin_block_reduce(red);
     if (threadIdx.x != 0) return;
     A.tickets[s] = 0u;
-    close_iteration(A, s, It, F, red);
+    close_iteration(It, F, red);
+    A.done_out[s] = It.done;
     if (A.publish) publish_report(A, s, It);
 }
 

@@ -7,13 +7,17 @@
 // the next wall pass) cost their launch and dependency floors, several times
 // the work. Once a report shows that the sims still iterating cover few tiles,
 // one cooperative launch runs the rest of their loop: each workgroup owns one
-// tile, and the workgroups of a sim meet at a barrier of their own after each
-// pair pass (two levels: groups of kTailGroup workgroups count on a word of
-// their own, the last of each group on the sim's word). The last to arrive
-// closes the sim's iteration (residual reduction and stop test). A sim with
-// walls is released at once: its workgroups compute the walls for the next
-// iteration while the iteration is closed, and meet again before reading the
-// stop flag. Sims never wait for each other.
+// tile and keeps its sim's constants and loop state on chip, and the
+// workgroups of a sim meet at a barrier of their own after each pair pass (two
+// levels: groups of kTailGroup workgroups count on a word of their own, the
+// last of each group on the sim's word). Every workgroup then closes the
+// iteration itself (residual reduction and stop test, from the sim's partials),
+// so all of them take the same stop decision without a second round trip; the
+// sim's first workgroup stores the loop state and the report. The partials
+// alternate between two buffers with the iteration's parity, so a workgroup
+// that starts the next pass never overwrites partials another is still
+// reading. A sim with walls computes them for the next iteration after the
+// close and meets again before the next pass. Sims never wait for each other.
 //
 // Results are bit-identical to plain launches: the same pair-pass code per
 // tile, the residual reduction in the same order as k_finalize (per segment,
@@ -34,21 +38,22 @@ namespace dtsph {
 
 namespace {
 
-constexpr long kTailSpin = 1L << 22;  // polls of a release word before a wait gives up (seconds)
+constexpr long kTailSpin = 1L << 22;  // polls of a barrier word before a wait gives up (seconds)
 
 struct TailArgs {
     int k0;              // iterations every sim in the launch has run
     uint32_t *arrive;    // per sim: group arrivals at its barrier (zero at launch)
-    uint32_t *release;   // per sim: its barrier phases released (zero at launch)
     uint32_t *group;     // per group of a sim's workgroups (tile_begin / kTailGroup + sim + group)
     int *err;            // set when a wait gives up
+    double4 *part4[2];   // residual partials by iteration parity ([0]: the plain launches' buffer)
+    double2 *part2[2];
     uint32_t outside[kTailMaxSims / 32];  // sims not in the launch (stopped before it)
 };
 
 // A workgroup's place in its sim's barrier.
 struct TailSeat {
-    int s;               // sim
     uint32_t *group;     // its group's word
+    uint32_t *sim;       // the sim's word (sims of several groups)
     uint32_t gsize;      // workgroups in its group
     uint32_t ngroups;    // groups of the sim
 };
@@ -99,128 +104,121 @@ template <typename L> __device__ inline void fin_reduce_any(double out[6], int n
     __syncthreads();
 }
 
-// Closes the current iteration of sim s (whole workgroup, after every tile of
-// the sim has written its partials): the segment sums (kept in LDS: a tail sim
-// has at most ceil(kTailSimTiles / kSegTiles) segments), their sum, the stop test
-// and, when the sim stops, its report. Returns the stop flag (thread 0).
-__device__ inline int tail_close(const FinArgs &F, int s, const SimDev &S)
+// This thread's values of the first round of the residual reduction of a
+// tail sim (fin_reduce_any's value wave * 64 + lane), all issued at once right
+// after the barrier.
+__device__ inline void prefetch_partials(double v[6], const SimDev &S, const double4 *p4, const double2 *p2)
 {
-    constexpr int kSegs = (kTailSimTiles + kSegTiles - 1) / kSegTiles;
-    __shared__ double seg[kSegs][6];
-    for (int q = 0; q < S.seg_count; ++q) {
-        const int4 sg = F.segs[S.seg_begin + q];
-        double red[6];
-        fin_reduce_any(red, sg.z - sg.y, [&](int vt, double v[6]) {
-            for (int k = 0; k < 6; ++k) v[k] = 0.0;
-            const int t = sg.y + vt;
-            if (t < sg.z) {
-                const double4 p = F.partials[t];
-                const double2 p2 = F.partials2[t];
-                v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w; v[4] = p2.x; v[5] = p2.y;
-            }
-        });
-        if (threadIdx.x == 0)
-            for (int k = 0; k < 6; ++k) seg[q][k] = red[k];
+    const int b = S.tile_begin, n = S.tile_end - S.tile_begin;
+    const int vt = (int)threadIdx.x;  // wave * 64 + lane
+    for (int k = 0; k < 6; ++k) v[k] = 0.0;
+    if (vt < n) {
+        const double4 p = p4[b + vt];
+        const double2 q = p2[b + vt];
+        v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w; v[4] = q.x; v[5] = q.y;
     }
-    __syncthreads();
+}
+
+// Closes iteration It.iters of sim s in the calling workgroup (every thread;
+// after sim_meet, so that every tile's partials p4, p2 are visible; pre holds
+// this thread's first-round values from prefetch_partials): a tail sim is one
+// residual segment (kTailSimTiles <= kSegTiles), reduced as k_finalize reduces
+// it, then the sum over the one segment, and the stop test on the workgroup's
+// own copy of the loop state It; every workgroup of the sim computes the same.
+// When the sim stops, the writer (its first workgroup) stores the loop state,
+// the stop flag and the report. Returns the stop flag.
+__device__ inline int tail_close(const FinArgs &F, int s, const SimDev &S, SimIter &It, const double pre[6],
+                                 const double4 *p4, const double2 *p2, bool writer)
+{
+    static_assert(kTailSimTiles <= kSegTiles, "a tail sim is a single residual segment");
+    __shared__ double seg[6];
+    __shared__ int s_stop;
+    const int b = S.tile_begin, n = S.tile_end - S.tile_begin;
     double red[6];
-    fin_reduce_any(red, S.seg_count, [&](int vt, double v[6]) {
+    fin_reduce_any(red, n, [&](int vt, double v[6]) {
+        if (vt == (int)threadIdx.x) {  // the first round: already loaded
+            for (int k = 0; k < 6; ++k) v[k] = pre[k];
+            return;
+        }
         for (int k = 0; k < 6; ++k) v[k] = 0.0;
-        for (int q = vt; q < S.seg_count; q += kFinThreads) {
-            if (q == vt) {
-                for (int k = 0; k < 6; ++k) v[k] = seg[q][k];
-            } else {
-                v[0] += seg[q][0]; v[1] += seg[q][1]; v[2] = fmax(v[2], seg[q][2]); v[3] = fmax(v[3], seg[q][3]);
-                v[4] = fmax(v[4], seg[q][4]); v[5] += seg[q][5];
-            }
+        if (vt < n) {
+            const double4 p = p4[b + vt];
+            const double2 q = p2[b + vt];
+            v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w; v[4] = q.x; v[5] = q.y;
         }
     });
-    int stop = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) seg[k] = red[k];
+    __syncthreads();
+    fin_reduce_any(red, 1, [&](int vt, double v[6]) {
+        for (int k = 0; k < 6; ++k) v[k] = vt == 0 ? seg[k] : 0.0;
+    });
     if (threadIdx.x == 0) {
-        SimIter &It = F.iters[s];
         FinState st;
         load_fin_state(st, It, S);
-        close_iteration(F, s, It, st, red);
-        stop = It.done;
-        if (stop) publish_report(F, s, It);
+        close_iteration(It, st, red);
+        if (writer && It.done) {  // no one reads the device loop state of a sim still iterating
+            F.iters[s] = It;
+            F.done_out[s] = 1;
+            publish_report(F, s, It);
+        }
+        s_stop = It.done;
     }
-    return stop;  // thread 0
+    __syncthreads();
+    const int stop = s_stop;
+    __syncthreads();
+    return stop;
 }
 
 // The workgroups of a sim meet. Every wave waits for its own stores, then
 // thread 0 makes them visible device-wide with a release-only arrival on its
 // group's word (an L2 write-back, no invalidation: workgroups still computing
-// keep their cached data); the last of its group acquires and, when the sim has
-// several groups, arrives on the sim's word. The last to arrive acquires, runs
-// close() (whole workgroup; its value in thread 0: the sim's stop flag) and
-// releases the others with (phase << 1 | stop flag) in the release word, which
-// they poll and acquire once it moves: after close() when close_first, else
-// before it with a zero flag (close() then overlaps their next phase, and a
-// later barrier orders it). close() writes global memory from thread 0 only.
-// Phases count the sim's barriers. Returns the flag, or -1: a wait gave up.
-template <typename C>
-__device__ inline int sim_barrier(const TailArgs &L, const TailSeat &seat, uint32_t &phase, bool close_first, C close)
+// keep their cached data); in a sim of several groups the last of each group
+// acquires and arrives on the sim's word. Every workgroup polls the word that
+// counts the whole sim (its group's word when the group is the sim) until all
+// have arrived, then acquires. Phases count the sim's barriers. Returns false
+// when the wait gave up.
+__device__ inline bool sim_meet(const TailArgs &L, const TailSeat &seat, uint32_t &phase)
 {
-    __shared__ int s_word;
+    __shared__ int s_ok;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     ++phase;
     if (threadIdx.x == 0) {
-        int last = 0;
         const uint32_t a = __hip_atomic_fetch_add(seat.group, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (a + 1u == phase * seat.gsize) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (seat.ngroups == 1) {  // the group is the sim: its last is the last
-                last = 1;
-            } else {
-                const uint32_t b =
-                    __hip_atomic_fetch_add(&L.arrive[seat.s], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                last = b + 1u == phase * seat.ngroups;
-                if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        uint32_t *word = seat.group;
+        uint32_t target = phase * seat.gsize;
+        if (seat.ngroups > 1) {
+            if (a + 1u == target) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_fetch_add(seat.sim, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
+            word = seat.sim;
+            target = phase * seat.ngroups;
         }
-        s_word = last;
-    }
-    __syncthreads();
-    const bool last = s_word;
-    __syncthreads();
-    if (last) {
-        if (!close_first && threadIdx.x == 0)
-            __hip_atomic_store(&L.release[seat.s], phase << 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const int stop = close();
-        if (threadIdx.x == 0) {
-            const int flag = close_first ? stop : 0;
-            if (close_first)
-                __hip_atomic_store(&L.release[seat.s], phase << 1 | (uint32_t)flag, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            s_word = flag;
-        }
-        __syncthreads();
-        const int r = s_word;
-        __syncthreads();
-        return r;
-    }
-    if (threadIdx.x == 0) {
-        int r = -1;
-        for (long spins = 0;; ++spins) {
-            const uint32_t w = __hip_atomic_load(&L.release[seat.s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((w >> 1) >= phase) {
-                r = (int)(w & 1u);
-                break;
-            }
+        int ok = 1;
+        for (long spins = 0; __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++spins) {
             if (spins > kTailSpin) {
                 atomicOr(L.err, 1);
+                ok = 0;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        s_word = r;
+        s_ok = ok;
     }
     __syncthreads();
-    const int r = s_word;
+    const bool ok = s_ok;
     __syncthreads();
-    return r;
+    return ok;
+}
+
+// Copy of `bytes` (a multiple of 4) from global memory into LDS, whole workgroup.
+__device__ inline void copy_words(void *dst, const void *src, int bytes)
+{
+    for (int w = (int)threadIdx.x; w < bytes / 4; w += (int)blockDim.x)
+        ((uint32_t *)dst)[w] = ((const uint32_t *)src)[w];
 }
 
 // Blocks 0 .. n_tiles-1: one tile each (through the launch's tile ranges); the
@@ -231,6 +229,7 @@ template <typename T, int DIM, bool WALLS, bool AV, int LPP>
 __global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3)))
 k_tail(PassArgs<T> A, FinArgs F, WallArgs<T> W, TailArgs L)
 {
+    static_assert(sizeof(SimDev) % 4 == 0 && sizeof(SimIter) % 4 == 0, "word copies");
     const int v = blockIdx.x;
     if (v >= A.n_tiles) {
         for (int s = threadIdx.x; s < F.n_sims; s += blockDim.x)
@@ -240,35 +239,41 @@ k_tail(PassArgs<T> A, FinArgs F, WallArgs<T> W, TailArgs L)
             }
         return;
     }
+    __shared__ SimDev S;   // the sim's constants
+    __shared__ SimIter It; // this workgroup's copy of the sim's loop state
     const int t = launch_tile(A, v);
-    const int s = A.tiles[t].x;
-    const SimDev &S = A.sims[s];
+    const int2 tl = A.tiles[t];
+    const int s = tl.x;
+    copy_words(&S, &A.sims[s], (int)sizeof(SimDev));
+    copy_words(&It, &F.iters[s], (int)sizeof(SimIter));
+    __syncthreads();
     const int nt = S.tile_end - S.tile_begin;
     const int bi = t - S.tile_begin;  // this workgroup's place among the sim's
     const int gi = bi / kTailGroup;
     TailSeat seat;
-    seat.s = s;
     seat.group = L.group + S.tile_begin / kTailGroup + s + gi;
+    seat.sim = L.arrive + s;
     seat.gsize = (uint32_t)min(kTailGroup, nt - gi * kTailGroup);
     seat.ngroups = (uint32_t)((nt + kTailGroup - 1) / kTailGroup);
     const bool walls = WALLS && S.nw > 0;
     uint32_t phase = 0;
+    double pre[6];
     for (int k = L.k0;; ++k) {
-        pass_tile<T, DIM, WALLS, AV, false, MODE_PSEUDO, LPP, false, 0, false>(A, t, (A.cur + k) & 1, k & 1);
-        int stop = sim_barrier(L, seat, phase, !walls, [&]() { return tail_close(F, s, S); });
-        if (stop < 0) return;
+        const int q = k & 1;
+        pass_tile_at<T, DIM, WALLS, AV, false, MODE_PSEUDO, LPP, false, 0, false>(A, S, t, tl, (A.cur + k) & 1, k & 1,
+                                                                                  L.part4[q], L.part2[q]);
+        if (!sim_meet(L, seat, phase)) return;
+        prefetch_partials(pre, S, L.part4[q], L.part2[q]);
+        const int stop = tail_close(F, s, S, It, pre, L.part4[q], L.part2[q], bi == 0);
         if (walls) {  // the sim's walls for iteration k + 1 (records of its fluid at k + 1)
             const int end = S.wall_begin + S.nw, stride = nt * (int)blockDim.x;
             for (int iw = S.wall_begin + bi * (int)blockDim.x + (int)threadIdx.x; iw < end; iw += stride)
                 wall_particle<T, DIM>(W, S, iw, (W.cur + k + 1) & 1, 0, false);
-            // the iteration's close has arrived at this barrier: its last reads the flag
-            stop = sim_barrier(L, seat, phase, true, [&]() {
-                return threadIdx.x == 0 ? __hip_atomic_load(&F.iters[s].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                        : 0;
-            });
-            if (stop < 0) return;
+            if (stop) return;
+            if (!sim_meet(L, seat, phase)) return;
+        } else if (stop) {
+            return;
         }
-        if (stop) return;
     }
 }
 
@@ -365,13 +370,16 @@ template <typename T> bool launch_tail(Ctx &c, int k0)
     TailArgs L;
     L.k0 = k0;
     L.arrive = c.tail_words;
-    L.release = c.tail_words + c.n_sims;
-    L.err = (int *)(c.tail_words + 2 * c.n_sims);
-    L.group = c.tail_words + 2 * c.n_sims + 1;
+    L.err = (int *)(c.tail_words + c.n_sims);
+    L.group = c.tail_words + c.n_sims + 1;
+    L.part4[0] = c.partials;
+    L.part2[0] = c.partials2;
+    L.part4[1] = c.tail_part4;
+    L.part2[1] = c.tail_part2;
     for (int q = 0; q < kTailMaxSims / 32; ++q) L.outside[q] = 0u;
     for (int s = 0; s < c.n_sims; ++s)
         if (c.flags_host[F_COUNT + s]) L.outside[s >> 5] |= 1u << (s & 31);
-    const int nw = 2 * c.n_sims + 1 + c.n_tiles / kTailGroup + c.n_sims + 1;  // arrivals, releases, error, groups
+    const int nw = c.n_sims + 1 + c.n_tiles / kTailGroup + c.n_sims + 1;  // arrivals, error, groups
     hipLaunchKernelGGL(k_tail_zero, dim3((nw + 255) / 256), dim3(256), 0, c.stream, c.tail_words, nw);
     DTSPH_HIP_CHECK(hipGetLastError());
     void *args[] = {&a, &f, &w, &L};
