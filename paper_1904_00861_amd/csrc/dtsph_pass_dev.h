@@ -359,8 +359,11 @@ template <typename T, int DIM, bool HEAVY> struct PassWaves {
 // records of moving sims), so a sim whose loop has stopped simply drops out.
 // The tile's record tl = tiles[t] and its sim's constants S are the caller's
 // (a persistent caller keeps them on chip); the tile's residual partials go to
-// part4[t], part2[t].
-template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP, bool CONV, int CACHE, bool MOVE>
+// part4[t], part2[t]. With PRED (latency-bound callers) a list's last partial
+// batch is issued at once, slots past the list masked, instead of one neighbour
+// after the other; the sums are the same, in the same order.
+template <typename T, int DIM, bool WALLS, bool AV, bool SEPDEN, int MODE, int LPP, bool CONV, int CACHE, bool MOVE,
+          bool PRED = false>
 __device__ __forceinline__ void pass_tile_at(const PassArgs<T> &A, const SimDev &S, int t, int2 tl, int par, int ppar,
                                              double4 *__restrict__ part4, double2 *__restrict__ part2)
 {
@@ -462,6 +465,35 @@ __device__ __forceinline__ void pass_tile_at(const PassArgs<T> &A, const SimDev 
                 }
             }
         }
+        if constexpr (PRED && CACHE == 0) {
+            if (k < nfl) {  // the last, partial batch (U - 1 entries at most)
+                int jj[U];
+#pragma unroll
+                for (int m = 0; m < U; ++m) {
+                    const int km = k + m * LPP;
+                    jj[m] = km < nfl ? nb[(size_t)km * N] : i;
+                }
+                Rec rj[U];
+                Q vj[U];
+#pragma unroll
+                for (int m = 0; m < U; ++m) {
+                    rj[m] = prec[jj[m]];
+                    vj[m] = vin[jj[m]];
+                }
+#pragma unroll
+                for (int m = 0; m < U; ++m) {
+                    if (k + m * LPP < nfl) {
+                        T r[3], vd[3];
+                        vd[0] = vi[0] - vj[m].x;
+                        vd[1] = vi[1] - vj[m].y;
+                        vd[2] = DIM == 3 ? vi[2] - vj[m].z : T(0);
+                        pos.delta(ri, rj[m], r);
+                        pair_terms<T, DIM, AV, SEPDEN, CONV, false>(K, r, vd, vd, vi, av, pi, pres<DIM>(vj[m]), acc);
+                    }
+                }
+                k = nfl;
+            }
+        }
         for (; k < nfl; k += LPP) {
             const int j = nb[(size_t)k * N];
             const Q vj = vin[j];
@@ -524,6 +556,39 @@ __device__ __forceinline__ void pass_tile_at(const PassArgs<T> &A, const SimDev 
                                                                          CACHE ? cf + e : nullptr,
                                                                          (CACHE && AV) ? cu + e : nullptr);
                     }
+                }
+            }
+            if constexpr (PRED && CACHE == 0 && UW > 1) {
+                if (k < nend) {  // the last, partial batch of walls
+                    int jj[UW];
+#pragma unroll
+                    for (int m = 0; m < UW; ++m) {
+                        const int km = k + m * LPP;
+                        jj[m] = km < nend ? nb[(size_t)km * N] : -1;
+                    }
+                    Q gj[UW];
+                    Rec rj[UW];
+                    T vw[UW][3];
+#pragma unroll
+                    for (int m = 0; m < UW; ++m) {
+                        const int j = jj[m] >= 0 ? jj[m] : Nf;  // a valid wall slot for the masked ones
+                        gj[m] = vin[j];
+                        for (int d = 0; d < 3; ++d) vw[m][d] = d < DIM ? A.vwall[d * A.Nw + (j - Nf)] : T(0);
+                        rj[m] = prec[j];
+                    }
+#pragma unroll
+                    for (int m = 0; m < UW; ++m) {
+                        if (jj[m] >= 0) {
+                            T r[3], vd[3], vv[3];
+                            for (int d = 0; d < 3; ++d) vd[d] = vi[d] - vw[m][d];
+                            vv[0] = vi[0] - gj[m].x;
+                            vv[1] = vi[1] - gj[m].y;
+                            vv[2] = DIM == 3 ? vi[2] - gj[m].z : T(0);
+                            pos.delta(ri, rj[m], r);
+                            pair_terms<T, DIM, AV, SEPDEN, CONV, false>(K, r, vd, vv, vi, av, pi, pres<DIM>(gj[m]), acc);
+                        }
+                    }
+                    k = nend;
                 }
             }
             for (; k < nend; k += LPP) {

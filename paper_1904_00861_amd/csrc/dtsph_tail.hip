@@ -224,9 +224,10 @@ __device__ inline void copy_words(void *dst, const void *src, int bytes)
 // Blocks 0 .. n_tiles-1: one tile each (through the launch's tile ranges); the
 // last block publishes the reports of the sims outside the launch. A tail
 // launch holds few workgroups, so the register budget is set for no spills
-// (FP64: 2 waves per SIMD, FP32: 3) rather than for occupancy.
+// (FP64 and 3D: 2 waves per SIMD, FP32 2D: 3) rather than for occupancy.
 template <typename T, int DIM, bool WALLS, bool AV, int LPP>
-__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3)))
+__global__ void __launch_bounds__(kMaxBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 || DIM == 3 ? 2 : 3)))
 k_tail(PassArgs<T> A, FinArgs F, WallArgs<T> W, TailArgs L)
 {
     static_assert(sizeof(SimDev) % 4 == 0 && sizeof(SimIter) % 4 == 0, "word copies");
@@ -260,8 +261,11 @@ k_tail(PassArgs<T> A, FinArgs F, WallArgs<T> W, TailArgs L)
     double pre[6];
     for (int k = L.k0;; ++k) {
         const int q = k & 1;
-        pass_tile_at<T, DIM, WALLS, AV, false, MODE_PSEUDO, LPP, false, 0, false>(A, S, t, tl, (A.cur + k) & 1, k & 1,
-                                                                                  L.part4[q], L.part2[q]);
+        // the last partial batch of a list issued at once (2D: in 3D the masked
+        // batch compiles to a different fusion of multiplies and adds, so its
+        // sums would round differently from the plain launches')
+        pass_tile_at<T, DIM, WALLS, AV, false, MODE_PSEUDO, LPP, false, 0, false, DIM == 2>(
+            A, S, t, tl, (A.cur + k) & 1, k & 1, L.part4[q], L.part2[q]);
         if (!sim_meet(L, seat, phase)) return;
         prefetch_partials(pre, S, L.part4[q], L.part2[q]);
         const int stop = tail_close(F, s, S, It, pre, L.part4[q], L.part2[q], bi == 0);
