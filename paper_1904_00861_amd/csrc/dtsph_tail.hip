@@ -123,7 +123,8 @@ __device__ inline void prefetch_partials(double v[6], const SimDev &S, const dou
 // after sim_meet, so that every tile's partials p4, p2 are visible; pre holds
 // this thread's first-round values from prefetch_partials): a tail sim is one
 // residual segment (kTailSimTiles <= kSegTiles), reduced as k_finalize reduces
-// it, then the sum over the one segment, and the stop test on the workgroup's
+// it, then the sum over the one segment (on thread 0: the same operations that
+// k_finalize's reduction applies to it), and the stop test on the workgroup's
 // own copy of the loop state It; every workgroup of the sim computes the same.
 // When the sim stops, the writer (its first workgroup) stores the loop state,
 // the stop flag and the report. Returns the stop flag.
@@ -131,7 +132,6 @@ __device__ inline int tail_close(const FinArgs &F, int s, const SimDev &S, SimIt
                                  const double4 *p4, const double2 *p2, bool writer)
 {
     static_assert(kTailSimTiles <= kSegTiles, "a tail sim is a single residual segment");
-    __shared__ double seg[6];
     __shared__ int s_stop;
     const int b = S.tile_begin, n = S.tile_end - S.tile_begin;
     double red[6];
@@ -147,13 +147,17 @@ __device__ inline int tail_close(const FinArgs &F, int s, const SimDev &S, SimIt
             v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w; v[4] = q.x; v[5] = q.y;
         }
     });
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 6; ++k) seg[k] = red[k];
-    __syncthreads();
-    fin_reduce_any(red, 1, [&](int vt, double v[6]) {
-        for (int k = 0; k < 6; ++k) v[k] = vt == 0 ? seg[k] : 0.0;
-    });
     if (threadIdx.x == 0) {
+        // The sum over the segments: with one segment, k_finalize's butterflies
+        // and group sums combine it only with +0.0 (the other threads' and
+        // groups' values), which leaves a sum s as s + 0.0 and a maximum m as
+        // fmax(m, 0.0) (the partials are non-negative or NaN).
+        red[0] += 0.0;
+        red[1] += 0.0;
+        red[5] += 0.0;
+        red[2] = fmax(red[2], 0.0);
+        red[3] = fmax(red[3], 0.0);
+        red[4] = fmax(red[4], 0.0);
         FinState st;
         load_fin_state(st, It, S);
         close_iteration(It, st, red);
