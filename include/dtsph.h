@@ -459,6 +459,14 @@ int dtsph_neighbor_list(dtsph_ctx *ctx, int32_t sim, int64_t *offsets, int32_t *
                                   regularisers, cached pair coefficients or
                                   in static contexts);
                                   2: as 1 without the persistent launch.   */
+#define DTSPH_OPT_TAIL_SPIN 17 /* polls of a tail launch's barrier word before
+                                  a waiting workgroup gives up (>= 1; 0
+                                  restores the default, 4194304, several
+                                  seconds). A wait that gives up leaves the
+                                  launch, its sims publish no report, and the
+                                  call returns DTSPH_EHIP with the particle
+                                  state undefined; small values exist to test
+                                  that path.                                 */
 int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value);
 
 /* Autotuner of the launch shapes. Between steps only (EINVAL in the loop).

@@ -564,7 +564,8 @@ void wait_reports(Ctx &c)
             const hipError_t e = hipStreamQuery(c.stream);
             if (e == hipSuccess) {
                 if (seen()) break;
-                throw ApiError(DTSPH_EHIP, "finalize completed without publishing its reports");
+                throw ApiError(DTSPH_EHIP, "the loop's launches completed without publishing every report "
+                                           "(a tail launch's barrier wait gave up, or a kernel failed)");
             }
             if (e != hipErrorNotReady) throw HipError(e, "hipStreamQuery", __FILE__, __LINE__);
         }
@@ -1657,6 +1658,10 @@ int dtsph_set_option(dtsph_ctx *ctx, int32_t option, int64_t value)
         case DTSPH_OPT_TAIL_LOOP:
             if (value < 0 || value > 2) throw ApiError(DTSPH_EINVAL, "loop schedule must be 0, 1 or 2");
             c.tail_loop = (int)value;
+            break;
+        case DTSPH_OPT_TAIL_SPIN:
+            if (value < 0) throw ApiError(DTSPH_EINVAL, "tail barrier polls must be >= 0");
+            c.tail_spin = value > 0 ? value : kTailSpinDefault;
             break;
         case DTSPH_OPT_NBR_TILES:
             if (value != 0 && value != 1) throw ApiError(DTSPH_EINVAL, "neighbour tiles must be 0 or 1");

@@ -35,6 +35,7 @@ constexpr int kMaxRanges = 32;       // active tile ranges passed to the pair pa
 constexpr int kSegTiles = 256;       // tiles per residual segment (one finalize workgroup)
 constexpr int kMaxTileRows = 32;     // cell rows per strip of the staged neighbour kernel
 constexpr int kTailMaxSims = 256;    // sims of a context that may use tail launches
+constexpr int64_t kTailSpinDefault = 1LL << 22;  // polls of a tail barrier word before a wait gives up
 constexpr int kTailSimTiles = 128;   // tiles of one sim in a tail launch (its barrier's workgroups)
 constexpr int kTailGroup = 32;       // workgroups per first-level barrier word of a tail launch
 
@@ -164,6 +165,7 @@ struct Ctx {
     // workgroup groups (tiles / kTailGroup + n_sims + 1); the tail launches'
     // second buffer of residual partials (odd iterations)
     int tail_loop = 1;
+    int64_t tail_spin = kTailSpinDefault;  // polls of a tail barrier before a wait gives up
     uint32_t *tail_words = nullptr;
     double4 *tail_part4 = nullptr;
     double2 *tail_part2 = nullptr;

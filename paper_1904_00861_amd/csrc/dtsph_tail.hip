@@ -38,13 +38,12 @@ namespace dtsph {
 
 namespace {
 
-constexpr long kTailSpin = 1L << 22;  // polls of a barrier word before a wait gives up (seconds)
-
 struct TailArgs {
     int k0;              // iterations every sim in the launch has run
     uint32_t *arrive;    // per sim: group arrivals at its barrier (zero at launch)
     uint32_t *group;     // per group of a sim's workgroups (tile_begin / kTailGroup + sim + group)
     int *err;            // set when a wait gives up
+    long long spin;      // polls of a barrier word before a wait gives up
     double4 *part4[2];   // residual partials by iteration parity ([0]: the plain launches' buffer)
     double2 *part2[2];
     uint32_t outside[kTailMaxSims / 32];  // sims not in the launch (stopped before it)
@@ -202,7 +201,7 @@ __device__ inline bool sim_meet(const TailArgs &L, const TailSeat &seat, uint32_
         }
         int ok = 1;
         for (long spins = 0; __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++spins) {
-            if (spins > kTailSpin) {
+            if (spins >= L.spin) {
                 atomicOr(L.err, 1);
                 ok = 0;
                 break;
@@ -377,6 +376,7 @@ template <typename T> bool launch_tail(Ctx &c, int k0)
     WallArgs<T> w = wall_args<T>(c, MODE_PSEUDO, false);
     TailArgs L;
     L.k0 = k0;
+    L.spin = c.tail_spin;
     L.arrive = c.tail_words;
     L.err = (int *)(c.tail_words + c.n_sims);
     L.group = c.tail_words + c.n_sims + 1;

@@ -23,7 +23,7 @@ FP64, FP32 = 0, 1
 REASONS = {0: "running", 1: "converged", 2: "stalled", 3: "max_iter", 4: "nonfinite", 5: "fixed"}
 OPT_TIMING, OPT_RESET_TIMING, OPT_CHUNK, OPT_BLOCK, OPT_XCD_REMAP, OPT_LANES, OPT_SKIN = 1, 2, 3, 4, 5, 6, 7
 OPT_CELL_DIV, OPT_NBR_LANES, OPT_GRAPHS, OPT_PAIR_CACHE, OPT_SPECULATE, OPT_FILTER_LANES = 8, 9, 10, 11, 12, 13
-OPT_ABS32_POSITIONS, OPT_NBR_TILES, OPT_TAIL_LOOP = 14, 15, 16
+OPT_ABS32_POSITIONS, OPT_NBR_TILES, OPT_TAIL_LOOP, OPT_TAIL_SPIN = 14, 15, 16, 17
 
 EXPORTS = [
     "dtsph_create", "dtsph_destroy", "dtsph_last_error", "dtsph_set_state", "dtsph_get_state",

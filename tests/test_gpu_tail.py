@@ -6,7 +6,8 @@ remaining sims' tiles. Every step must equal schedule 0 bit for bit (fields,
 reports, status): batches whose sims stop at different iterations, with and
 without walls, FP32 and FP64, 2D and 3D, at every lane count and workgroup size,
 sims stopping at their iteration limit inside a tail launch, barriers over
-several groups of workgroups, a single sim, and the fixed-iteration call."""
+several groups of workgroups, a single sim, and the fixed-iteration call; a
+barrier wait that gives up (forced by a one-poll limit) is an error, not a hang."""
 import numpy as np
 import pytest
 
@@ -126,4 +127,25 @@ def test_loop_schedule_rejects_other_values():
     for bad in (-1, 3):
         with pytest.raises(D.DtsphError):
             sim.set_option(D.OPT_TAIL_LOOP, bad)
+    with pytest.raises(D.DtsphError):
+        sim.set_option(D.OPT_TAIL_SPIN, -1)
     sim.close()
+
+
+def test_tail_barrier_wait_that_gives_up_is_an_error():
+    # Barrier waits limited to one poll: the first workgroup of a sim to arrive
+    # leaves at once, the others give up at their next barrier, every kernel
+    # ends, the sim publishes no report and the step returns an error. A fresh
+    # context afterwards runs normally.
+    banner("tail launch with barrier waits that give up")
+    sim = D.Sim(CASES["batch_mixed"](), precision=D.FP32)
+    sim.step(1)  # a first loop: the per-sim counts that cut the next ones
+    sim.set_option(D.OPT_TAIL_SPIN, 1)
+    with pytest.raises(D.DtsphError):
+        for _ in range(6):
+            sim.step(1)
+    sim.close()
+    plain, _ = _run(CASES["batch_tgv"](), D.FP32, 0, 3)
+    tail, n1 = _run(CASES["batch_tgv"](), D.FP32, 1, 3)
+    assert n1 > 0
+    _same(plain, tail, "after an abandoned tail launch")
